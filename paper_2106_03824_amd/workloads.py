@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs: R-MAT and G(n,p) graphs and update batches.
+
+This module produces inputs only; it holds none of the PLDS arithmetic.  Both
+the GPU library's tests and benchmark and the CPU oracle's tests draw their
+graphs and batches from here, through ``csrc/workloads.c``.
+
+Seeds: a graph uses seed 1 by default; batch stream ``j`` of workload ``c``
+uses seed ``1000*c + j``.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "csrc", "workloads.c")
+LIB = os.path.join(HERE, "libplds_workloads.so")
+_LIB = None
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_U8P = ctypes.POINTER(ctypes.c_uint8)
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build(force=True):
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", SRC, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        L = ctypes.CDLL(build(force=False))
+        L.wl_rmat.restype = ctypes.c_int64
+        L.wl_rmat.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_uint64, ctypes.c_int32, _I32P]
+        L.wl_er.restype = ctypes.c_int64
+        L.wl_er.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, _I32P, ctypes.c_int64]
+        L.wl_permutation.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, _I32P]
+        L.wl_permute_edges.argtypes = [_I32P, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64]
+        L.wl_new_pairs.argtypes = [ctypes.c_int64, _I32P, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                   ctypes.c_uint64, _I32P]
+        L.wl_sample_edges.argtypes = [_I32P, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, _I32P]
+        L.wl_filter_present.argtypes = [_I32P, ctypes.c_int64, _I32P, ctypes.c_int64, _U8P]
+        L.wl_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, _U64P]
+        _LIB = L
+    return _LIB
+
+
+def _e(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1, 2))
+
+
+def rmat(scale, m, a=0.57, b=0.19, c=0.19, seed=1, relabel=True):
+    """``m`` unique undirected R-MAT edges on ``2**scale`` vertices, int32 [m,2]."""
+    out = np.empty((int(m), 2), dtype=np.int32)
+    r = _lib().wl_rmat(int(scale), int(m), float(a), float(b), float(c), int(seed), int(bool(relabel)),
+                       out.ctypes.data_as(_I32P))
+    if r < 0:
+        raise ValueError("rmat: bad arguments")
+    return out
+
+
+def er(n, p, seed=1):
+    """G(n,p) edge list, int32 [m,2] (pairs (v,w) with w < v)."""
+    cap = int(n * (n - 1) / 2 * p * 1.2 + 64)
+    while True:
+        out = np.empty((cap, 2), dtype=np.int32)
+        k = _lib().wl_er(int(n), float(p), int(seed), out.ctypes.data_as(_I32P), cap)
+        if k < 0:
+            raise ValueError("er: bad arguments")
+        if k <= cap:
+            return out[:k].copy()
+        cap = int(k)
+
+
+def permutation(n, seed, stream=0):
+    out = np.empty(int(n), dtype=np.int32)
+    _lib().wl_permutation(int(n), int(seed), int(stream), out.ctypes.data_as(_I32P))
+    return out
+
+
+def permute_edges(edges, seed, stream=0):
+    e = _e(edges).copy()
+    _lib().wl_permute_edges(e.ctypes.data_as(_I32P), e.shape[0], int(seed), int(stream))
+    return e
+
+
+def new_pairs(n, edges, count, seed, stream=0):
+    """``count`` distinct uniform pairs u != v absent from ``edges``."""
+    e = _e(edges)
+    out = np.empty((int(count), 2), dtype=np.int32)
+    rc = _lib().wl_new_pairs(int(n), e.ctypes.data_as(_I32P), e.shape[0], int(count), int(seed), int(stream),
+                             out.ctypes.data_as(_I32P))
+    if rc:
+        raise ValueError("new_pairs: bad arguments")
+    return out
+
+
+def sample_edges(edges, count, seed, stream=0):
+    """``count`` edges of ``edges`` drawn uniformly without replacement."""
+    e = _e(edges)
+    out = np.empty((int(count), 2), dtype=np.int32)
+    rc = _lib().wl_sample_edges(e.ctypes.data_as(_I32P), e.shape[0], int(count), int(seed), int(stream),
+                                out.ctypes.data_as(_I32P))
+    if rc:
+        raise ValueError("sample_edges: bad arguments")
+    return out
+
+
+def present(edges, query):
+    """Boolean mask: which undirected pairs of ``query`` occur in ``edges``."""
+    e, q = _e(edges), _e(query)
+    out = np.zeros(q.shape[0], dtype=np.uint8)
+    _lib().wl_filter_present(e.ctypes.data_as(_I32P), e.shape[0], q.ctypes.data_as(_I32P), q.shape[0],
+                             out.ctypes.data_as(_U8P))
+    return out.astype(bool)
+
+
+def draws(seed, stream, count):
+    """Raw 64-bit counter-based draws, for seeded choices made in Python."""
+    out = np.empty(int(count), dtype=np.uint64)
+    _lib().wl_draws(int(seed), int(stream), int(count), out.ctypes.data_as(_U64P))
+    return out
+
+
+def uniforms(seed, stream, count):
+    return (draws(seed, stream, count) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
