@@ -1,0 +1,146 @@
+/*
+ * plds.h -- C ABI of the MI355X (gfx950) batch-dynamic approximate k-core
+ * library: the parallel level data structure (PLDS) of Liu, Shi, Yu,
+ * Dhulipala and Shun, "Parallel Batch-Dynamic Algorithms for k-Core
+ * Decomposition and Related Graph Problems" (SPAA'22, arXiv 2106.03824).
+ *
+ * The structure keeps, for an undirected graph on vertices 0..n-1 that changes
+ * by batches of edge insertions and deletions (problem statement,
+ * Preliminaries: batch-dynamic setting), a level for every vertex such that
+ * Invariants 1 and 2 hold (Section "Detailed PLDS Algorithm"), and from it a
+ * (2+3/lambda)(1+delta)-approximate coreness estimate (Def. coreness
+ * estimate, Lemma decomp-bound).
+ *
+ * Conventions for every function:
+ *   - return value: PLDS_OK (0) or a negative PLDS_E* code; nothing throws.
+ *   - "device pointer": memory the caller allocated on the GPU of the handle
+ *     (hipMalloc or a torch CUDA tensor).  The caller owns it and keeps it
+ *     alive until the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is ordered on it.  Batch calls (insert/delete/update/load_state)
+ *     return only after their work on `stream` is complete; plds_coreness,
+ *     plds_levels and plds_degrees only enqueue work.
+ *   - a handle is not thread-safe; distinct handles are independent.
+ *   - vertex ids are int32 in [0, n); n <= 2^31 - 1.
+ */
+#ifndef PLDS_H
+#define PLDS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLDS_OK 0
+#define PLDS_EINVAL -1 /* bad argument: n < 1, delta <= 0, lambda <= 0, NULL, count < 0 */
+#define PLDS_ERANGE -2 /* a vertex id outside [0, n); the batch is rejected, state unchanged */
+#define PLDS_ENOMEM -3 /* device or host allocation failed; state unchanged            */
+#define PLDS_EHIP -4   /* a HIP runtime call failed; the handle should be destroyed     */
+#define PLDS_ESTATE -5 /* an internal consistency check failed (see plds_check)          */
+
+typedef struct plds plds_t;
+
+typedef struct {
+    int64_t n;          /* number of vertices                                         */
+    int64_t m;          /* current number of undirected edges                         */
+    int32_t t;          /* least t >= 0 with (1+delta)^t >= n                          */
+    int32_t L;          /* levels per group (default 4t, at least 1)                  */
+    int32_t G;          /* number of groups, t+1                                      */
+    int32_t K;          /* number of levels, G*L                                      */
+    double delta, lambda;
+    int64_t slab_slots; /* adjacency slots allocated (pool capacity, int32 each)     */
+    int64_t slab_used;  /* slots handed out (live slabs plus abandoned ones)          */
+} plds_info_t;
+
+typedef struct {
+    int64_t applied_ins;   /* unique new edges inserted by the last batch call          */
+    int64_t applied_del;   /* unique present edges deleted by the last batch call       */
+    int64_t sweeps_ins;    /* levels at which some vertex moved up                      */
+    int64_t sweeps_del;    /* levels to which some vertex moved down                    */
+    int64_t moves_up;      /* one-level up-moves                                         */
+    int64_t moves_down;    /* down-moves (each vertex at most once per batch)            */
+    int64_t dl_calcs;      /* desire-level computations                                  */
+    int64_t slots_scanned; /* adjacency slots read by the level sweeps                   */
+    int64_t top_level;     /* highest level reached during the call                      */
+    int64_t viol_ins0;     /* Invariant-1 violators right after the insertions           */
+    int64_t viol_del0;     /* Invariant-2 violators right after the deletions            */
+    int64_t host_syncs;    /* host round trips made by the call                          */
+    int64_t reserved[4];
+} plds_stats_t;
+
+/* Create an empty structure on the current HIP device: all n vertices at
+ * level 0, no edges.  delta > 0 and lambda > 0 are the constants of
+ * Invariants 1-2.  Groups g_0..g_t with t = ceil(log_{1+delta} n), each of
+ * 4t levels (Section "Detailed PLDS Algorithm"). */
+int plds_create(int64_t n, double delta, double lambda, plds_t **out);
+
+/* As plds_create; levels_per_group > 0 overrides 4t (e.g. 3 for the paper's
+ * worked examples); edge_capacity_hint (>= 0) pre-sizes the adjacency pool. */
+int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int64_t edge_capacity_hint,
+                   plds_t **out);
+
+int plds_destroy(plds_t *h);
+
+/* Update(B) of Algorithm 1 with B = (ins, del): all insertions are applied
+ * and rebalanced (RebalanceInsertions, Algorithm 2), then all deletions
+ * (RebalanceDeletions, Algorithm 3, desire-levels per Def. desire-level).
+ * ins / del: device pointers to int32 [count][2] edge lists (u, v); either
+ * may be NULL with count 0.  Preprocessing (framework section): pairs are
+ * undirected, self-loops are ignored, duplicates collapse, inserting a
+ * present edge or deleting an absent one has no effect.  Deletions are
+ * checked against the graph after the insertions, so a pair in both lists
+ * ends absent.  Any id outside [0, n) in either list rejects the whole call
+ * with PLDS_ERANGE before anything changes. */
+int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, void *stream);
+int plds_batch_insert(plds_t *h, const int32_t *edges, int64_t count, void *stream);
+int plds_batch_delete(plds_t *h, const int32_t *edges, int64_t count, void *stream);
+
+/* Coreness estimate (Def. coreness estimate): (1+delta)^max(floor((l+1)/L)-1,0)
+ * for a vertex at level l with at least one edge, 0.0 for an isolated one.
+ * vertices: device int32 [count], or NULL for all n (count ignored).
+ * out: device float64 [count] (or [n]).  The power is read from a table built
+ * on the host by repeated double multiplication (see plds_thresholds).  An id
+ * outside [0, n) yields -1.0 and latches PLDS_ERANGE for plds_sync. */
+int plds_coreness(plds_t *h, const int32_t *vertices, int64_t count, double *out, void *stream);
+
+/* Current level of every vertex: device int32 [n]. */
+int plds_levels(plds_t *h, int32_t *out, void *stream);
+/* Current degree of every vertex: device int32 [n]. */
+int plds_degrees(plds_t *h, int32_t *out, void *stream);
+
+int plds_info(const plds_t *h, plds_info_t *out);
+
+/* Host copies of the per-group tables (G entries each, any may be NULL):
+ * up_max[g] = floor((2+3/lambda)(1+delta)^g)  -- Invariant 1 holds iff up <= it;
+ * dn_min[g] = ceil((1+delta)^g)               -- Invariant 2 holds iff up* >= it;
+ * pow_tab[g] = (1+delta)^g formed by g repeated double multiplications. */
+int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *pow_tab);
+
+/* Statistics of the last batch call. */
+int plds_stats(const plds_t *h, plds_stats_t *out);
+
+/* Checkpoint.  plds_dump_state writes the edge list (u < v, unordered) to the
+ * device buffer edges [cap][2] and the levels to device int32 [n]; *m_out
+ * receives m (PLDS_EINVAL and nothing written if cap < m).  plds_load_state
+ * replaces the whole state by the given edges (device int32 [m][2]) and
+ * levels (device int32 [n], each in [0, K)); it returns plds_check() of the
+ * loaded state. */
+int plds_dump_state(plds_t *h, int32_t *edges, int64_t cap, int64_t *m_out, int32_t *levels, void *stream);
+int plds_load_state(plds_t *h, const int32_t *edges, int64_t m, const int32_t *levels, void *stream);
+
+/* Full on-device check: up/up* counters equal recounted degrees, Invariants
+ * 1 and 2 hold at every vertex, isolated vertices sit at level 0, levels lie
+ * in [0, K), slab contents match degrees.  PLDS_OK or PLDS_ESTATE. */
+int plds_check(plds_t *h, void *stream);
+
+/* Wait for all work of the handle on `stream`; returns and clears a latched
+ * asynchronous error (PLDS_ERANGE from plds_coreness). */
+int plds_sync(plds_t *h, void *stream);
+
+const char *plds_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1532 @@
+// plds.hip -- MI355X (gfx950) implementation of the parallel level data
+// structure (PLDS) for batch-dynamic (2+eps)-approximate k-core decomposition
+// (Liu, Shi, Yu, Dhulipala, Shun, SPAA'22).  C ABI in include/plds.h.
+//
+// Device state (all in HBM, int32 unless noted):
+//   level[n], deg[n], up[n], ups[n]    level, degree, up-degree, up*-degree
+//   off[n] (int64), cap[n], fill[n]    per-vertex open-addressing hash slab in
+//                                      one pool: slots pool[off .. off+cap),
+//                                      -1 empty, -2 tombstone, else neighbour id
+//   stay[n], cnt2[n], addc[n], dl[n], rcstamp[n]   per-batch scratch
+// The level loops (Algorithms 2 and 3) run as short kernels ordered on one
+// stream; the host enqueues a run of steps and reads a small control block
+// back between runs.  Each step reads its level from the control block, so
+// the host never needs the level to enqueue it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/plds.h"
+
+namespace {
+
+constexpr int32_t kEmpty = -1;
+constexpr int32_t kTomb = -2;
+constexpr uint64_t kEmpty64 = ~0ull;
+constexpr int kBlock = 256;          // threads per block of the sweep kernels
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int32_t kChunk = 256;      // slab slots per work item of a sweep
+constexpr int32_t kMinCap = 8;       // smallest slab, slots
+constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels
+constexpr int kDlGrid = 1024;        // blocks of the desire-level kernel
+constexpr int32_t kInf = INT32_MAX;
+
+// error bits latched on device
+constexpr int32_t kErrRange = 1;     // id out of range
+constexpr int32_t kErrFull = 2;      // slab insert found no free slot
+constexpr int32_t kErrLevel = 4;     // a level left [0, K)
+constexpr int32_t kErrOrder = 8;     // a desire-level not above the processed level
+constexpr int32_t kErrPool = 16;     // pool exhausted
+
+struct Ctl {
+    int32_t l;            // level of the current step
+    int32_t done;         // loop finished
+    int32_t cur;          // ping-pong index of the cascade / pending lists
+    int32_t n_mv;         // movers of the current step
+    int32_t casc_n[2];    // cascade list sizes
+    int32_t p_n[2];       // pending list sizes (deletion)
+    int32_t n_chunks;     // work items of the current step
+    int32_t n_rc;         // desire-level recomputations of the current step
+    int32_t nm;           // running minimum of pending desire-levels
+    int32_t blocks_done;  // last-block election
+    int32_t err;          // latched error bits
+    int32_t n_valid;      // valid unique edges of the batch being applied
+    int32_t n_touch;      // distinct endpoints of those edges
+    int32_t n_grow;       // slabs to regrow
+    int32_t n_cand;       // initial candidates
+    int32_t step_id;      // deletion step counter (stamps)
+    int32_t pad[2];
+    int64_t grow_req;     // slots requested by regrowth
+    int64_t pool_top;     // next free pool slot
+    int64_t sweeps, moves, scanned, dl_calcs, top, m_out;
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+    int32_t n, L, G, K;
+    int32_t *up_max, *dn_min;         // [G+1] (entry G = INT_MAX / unused)
+    double *pow_tab;                  // [G]
+    int32_t *level, *deg, *up, *ups, *cap, *fill;
+    int64_t *off;
+    int32_t *pool;
+    int64_t pool_cap;
+    int32_t *stay, *cnt2, *addc, *dl, *rcstamp;
+    Ctl *ctl;
+    // batch scratch
+    uint64_t *hset;
+    uint64_t hmask;
+    int32_t *valid;                   // [batch][2]
+    int32_t *touch;                   // [n]
+    int32_t *grow, *newcap;           // [n]
+    int64_t *oldoff;                  // [n]
+    int32_t *oldcap;                  // [n]
+    // level loop scratch
+    int32_t *cand, *sorted;           // [n]
+    int32_t *lvl_cnt, *lvl_start, *next_nz;   // [K+1]
+    int32_t *casc0, *casc1;           // [n]
+    int32_t *mv;                      // [n]
+    int64_t *chunks;                  // [chunk_cap]
+    int64_t chunk_cap;
+    int32_t *p0, *p1;                 // [n]
+    int32_t *rc;                      // [n]
+};
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // integer finaliser (low-bias 32-bit mixer)
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+// home slot of `key` in a slab of `cap` slots (multiply-high range map)
+__device__ __forceinline__ uint32_t home(int32_t key, int32_t cap) {
+    return (uint32_t)(((uint64_t)mix32((uint32_t)key) * (uint32_t)cap) >> 32);
+}
+
+__device__ __forceinline__ int32_t wave_sum(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ void latch(Ctl *c, int32_t bits) { atomicOr(&c->err, bits); }
+
+// append x to list[0..cap) through counter *n; an overflow is latched
+__device__ __forceinline__ void push(int32_t *list, int32_t *n, int32_t cap, int32_t x, Ctl *c) {
+    int32_t k = atomicAdd(n, 1);
+    if (k < cap) list[k] = x;
+    else latch(c, kErrLevel);
+}
+
+// ----------------------------------------------------------------- slabs
+__device__ bool slab_has(const int32_t *s, int32_t cap, int32_t key) {
+    if (cap == 0) return false;
+    uint32_t i = home(key, cap);
+    for (int32_t p = 0; p < cap; p++) {
+        int32_t x = s[i];
+        if (x == key) return true;
+        if (x == kEmpty) return false;
+        if (++i == (uint32_t)cap) i = 0;
+    }
+    return false;
+}
+
+// key is known absent; space is guaranteed by the growth plan
+__device__ bool slab_put(int32_t *s, int32_t cap, int32_t key, int32_t *fill) {
+    if (cap == 0) return false;
+    uint32_t i = home(key, cap);
+    for (int32_t p = 0; p < cap; p++) {
+        int32_t x = s[i];
+        if (x == kEmpty || x == kTomb) {
+            int32_t prev = atomicCAS(&s[i], x, key);
+            if (prev == x) {
+                if (x == kEmpty && fill) atomicAdd(fill, 1);
+                return true;
+            }
+        }
+        if (++i == (uint32_t)cap) i = 0;
+    }
+    return false;
+}
+
+__device__ bool slab_del(int32_t *s, int32_t cap, int32_t key) {
+    if (cap == 0) return false;
+    uint32_t i = home(key, cap);
+    for (int32_t p = 0; p < cap; p++) {
+        int32_t x = s[i];
+        if (x == key) {
+            s[i] = kTomb;
+            return true;
+        }
+        if (x == kEmpty) return false;
+        if (++i == (uint32_t)cap) i = 0;
+    }
+    return false;
+}
+
+// ------------------------------------------------------- preprocessing
+__global__ void k_range_check(const int32_t *e, int64_t cnt, int32_t n, Ctl *ctl) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * cnt; i += stride) {
+        int32_t x = e[i];
+        if (x < 0 || x >= n) latch(ctl, kErrRange);
+    }
+}
+
+// Batch preprocessing (framework section): canonical (min,max) pair, no
+// self-loop, first copy only (hash set), then keep it iff its presence in the
+// graph equals want_present (insertions: absent, deletions: present).
+__global__ void k_dedupe(Dev d, const int32_t *e, int64_t cnt, int want_present) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        int32_t a = e[2 * i], b = e[2 * i + 1];
+        if (a == b) continue;
+        int32_t u = min(a, b), v = max(a, b);
+        uint64_t key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
+        uint64_t j = mix64(key) & d.hmask;
+        bool fresh = false;
+        for (uint64_t p = 0; p <= d.hmask; p++) {
+            uint64_t x = d.hset[j];
+            if (x == key) break;
+            if (x == kEmpty64) {
+                uint64_t prev = atomicCAS((unsigned long long *)&d.hset[j], (unsigned long long)kEmpty64,
+                                          (unsigned long long)key);
+                if (prev == kEmpty64) {
+                    fresh = true;
+                    break;
+                }
+                if (prev == key) break;
+            }
+            j = (j + 1) & d.hmask;
+        }
+        if (!fresh) continue;
+        // probe the smaller slab of the two endpoints
+        int32_t s = d.cap[u] <= d.cap[v] ? u : v, t = s == u ? v : u;
+        bool present = slab_has(d.pool + d.off[s], d.cap[s], t);
+        if ((int)present != want_present) continue;
+        int32_t k = atomicAdd(&d.ctl->n_valid, 1);
+        d.valid[2 * k] = u;
+        d.valid[2 * k + 1] = v;
+    }
+}
+
+// count new slots per endpoint; first touch records the vertex
+__global__ void k_touch(Dev d) {
+    int32_t nv = d.ctl->n_valid;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * nv; i += stride) {
+        int32_t x = d.valid[i];
+        if (atomicAdd(&d.addc[x], 1) == 0) push(d.touch, &d.ctl->n_touch, d.n, x, d.ctl);
+    }
+}
+
+// slabs that would exceed 80% occupancy are regrown to 60% of the new size
+__global__ void k_plan_growth(Dev d) {
+    int32_t nt = d.ctl->n_touch;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
+        int32_t x = d.touch[i];
+        int64_t k = d.addc[x], c = d.cap[x];
+        if ((d.fill[x] + k) * 5 <= c * 4) continue;
+        int64_t live = d.deg[x] + k;
+        int64_t nc = (live * 5 + 2) / 3;
+        nc = ((std::max<int64_t>(nc, kMinCap) + 7) / 8) * 8;
+        if (nc > INT32_MAX / 2) latch(d.ctl, kErrPool);
+        int32_t g = atomicAdd(&d.ctl->n_grow, 1);
+        d.grow[g] = x;
+        d.newcap[g] = (int32_t)nc;
+        atomicAdd((unsigned long long *)&d.ctl->grow_req, (unsigned long long)nc);
+    }
+}
+
+// allocate the new slabs from the pool and clear them
+__global__ void k_grow_alloc(Dev d) {
+    int32_t ng = d.ctl->n_grow;
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = gridDim.x * blockDim.x / kWave;
+    for (int g = wid; g < ng; g += nw) {
+        int32_t x = d.grow[g], nc = d.newcap[g];
+        int64_t base = 0;
+        if (lane == 0) {
+            base = (int64_t)atomicAdd((unsigned long long *)&d.ctl->pool_top, (unsigned long long)nc);
+            d.oldoff[g] = d.off[x];
+            d.oldcap[g] = d.cap[x];
+        }
+        base = __shfl(base, 0, kWave);
+        if (base + nc > d.pool_cap) {
+            if (lane == 0) {
+                latch(d.ctl, kErrPool);
+                d.newcap[g] = 0;
+            }
+            continue;
+        }
+        for (int32_t s = lane; s < nc; s += kWave) d.pool[base + s] = kEmpty;
+        if (lane == 0) {
+            d.off[x] = base;
+            d.cap[x] = nc;
+            d.fill[x] = 0;
+        }
+    }
+}
+
+// move the live entries of each regrown slab into its new slab
+__global__ void k_grow_move(Dev d) {
+    int32_t ng = d.ctl->n_grow;
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = gridDim.x * blockDim.x / kWave;
+    for (int g = wid; g < ng; g += nw) {
+        int32_t x = d.grow[g];
+        if (d.newcap[g] == 0) continue;
+        const int32_t *os = d.pool + d.oldoff[g];
+        int32_t oc = d.oldcap[g];
+        for (int32_t s = lane; s < oc; s += kWave) {
+            int32_t w = os[s];
+            if (w >= 0 && !slab_put(d.pool + d.off[x], d.cap[x], w, &d.fill[x])) latch(d.ctl, kErrFull);
+        }
+    }
+}
+
+// Insert both directed copies; degrees and up/up* counters follow the
+// current levels: up(a) counts b iff level(b) >= level(a), up*(a) iff
+// level(b) >= level(a)-1.
+__global__ void k_apply_ins(Dev d) {
+    int32_t nv = d.ctl->n_valid;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        int32_t a = d.valid[2 * i], b = d.valid[2 * i + 1];
+        if (!slab_put(d.pool + d.off[a], d.cap[a], b, &d.fill[a])) latch(d.ctl, kErrFull);
+        if (!slab_put(d.pool + d.off[b], d.cap[b], a, &d.fill[b])) latch(d.ctl, kErrFull);
+        int32_t la = d.level[a], lb = d.level[b];
+        atomicAdd(&d.deg[a], 1);
+        atomicAdd(&d.deg[b], 1);
+        if (lb >= la) atomicAdd(&d.up[a], 1);
+        if (lb >= la - 1) atomicAdd(&d.ups[a], 1);
+        if (la >= lb) atomicAdd(&d.up[b], 1);
+        if (la >= lb - 1) atomicAdd(&d.ups[b], 1);
+    }
+}
+
+// Remove both directed copies (tombstones) and the counter contributions.
+__global__ void k_apply_del(Dev d) {
+    int32_t nv = d.ctl->n_valid;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        int32_t a = d.valid[2 * i], b = d.valid[2 * i + 1];
+        if (!slab_del(d.pool + d.off[a], d.cap[a], b)) latch(d.ctl, kErrFull);
+        if (!slab_del(d.pool + d.off[b], d.cap[b], a)) latch(d.ctl, kErrFull);
+        int32_t la = d.level[a], lb = d.level[b];
+        atomicSub(&d.deg[a], 1);
+        atomicSub(&d.deg[b], 1);
+        if (lb >= la) atomicSub(&d.up[a], 1);
+        if (lb >= la - 1) atomicSub(&d.ups[a], 1);
+        if (la >= lb) atomicSub(&d.up[b], 1);
+        if (la >= lb - 1) atomicSub(&d.ups[b], 1);
+    }
+}
+
+// --------------------------------------------------- insertion sweep
+// Initial candidates of Algorithm 2: endpoints of inserted edges that
+// violate Invariant 1, bucketed by level.
+__global__ void k_ins_seed(Dev d) {
+    int32_t nt = d.ctl->n_touch;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
+        int32_t x = d.touch[i];
+        d.addc[x] = 0;
+        int32_t lx = d.level[x];
+        if (d.up[x] > d.up_max[lx / d.L]) {
+            push(d.cand, &d.ctl->n_cand, d.n, x, d.ctl);
+            atomicAdd(&d.lvl_cnt[lx], 1);
+        }
+    }
+}
+
+// single block: exclusive scan of the per-level counts, next non-empty level
+__global__ void k_level_scan(Dev d) {
+    __shared__ int32_t part[1024];
+    int K = d.K, tid = threadIdx.x, nt = blockDim.x;
+    int per = (K + nt - 1) / nt, lo = min(K, tid * per), hi = min(K, lo + per);
+    int32_t s = 0;
+    for (int i = lo; i < hi; i++) s += d.lvl_cnt[i];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t acc = 0;
+        for (int t = 0; t < nt; t++) {
+            int32_t x = part[t];
+            part[t] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+    int32_t acc = part[tid];
+    for (int i = lo; i < hi; i++) {
+        d.lvl_start[i] = acc;
+        acc += d.lvl_cnt[i];
+    }
+    if (tid == nt - 1) d.lvl_start[K] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t nz = K;
+        d.next_nz[K] = K;
+        for (int i = K - 1; i >= 0; i--) {
+            if (d.lvl_cnt[i] > 0) nz = i;
+            d.next_nz[i] = nz;
+        }
+        d.ctl->l = nz;
+        d.ctl->done = nz >= K;
+        d.ctl->cur = 0;
+        d.ctl->casc_n[0] = d.ctl->casc_n[1] = 0;
+        d.ctl->n_chunks = 0;
+        d.ctl->blocks_done = 0;
+    }
+}
+
+__global__ void k_level_scatter(Dev d) {
+    int32_t nc = d.ctl->n_cand;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        int32_t x = d.cand[i];
+        int32_t lx = d.level[x];
+        int32_t pos = d.lvl_start[lx] + atomicSub(&d.lvl_cnt[lx], 1) - 1;
+        d.sorted[pos] = x;
+    }
+}
+
+__device__ __forceinline__ void add_chunks(Dev &d, int32_t v) {
+    int32_t c = d.cap[v];
+    int32_t nch = (c + kChunk - 1) / kChunk;
+    if (nch == 0) return;
+    int32_t base = atomicAdd(&d.ctl->n_chunks, nch);
+    if (base + nch > d.chunk_cap) {
+        latch(d.ctl, kErrPool);
+        return;
+    }
+    for (int32_t k = 0; k < nch; k++) d.chunks[base + k] = ((int64_t)v << 32) | (uint32_t)k;
+}
+
+// Step of Algorithm 2 at level l, part 1: the movers S_l are the sorted
+// candidates of level l and the cascade (vertices marked at level l).
+__global__ void k_ins_prep(Dev d) {
+    if (d.ctl->done) return;
+    int32_t l = d.ctl->l, cur = d.ctl->cur;
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < 0 || l + 1 >= d.K) {
+        if (gid == 0) latch(d.ctl, kErrLevel);
+        return;
+    }
+    int32_t a0 = d.lvl_start[l], a1 = d.lvl_start[l + 1];
+    int32_t nA = a1 - a0, nB = min(d.ctl->casc_n[cur], d.n);
+    const int32_t *casc = cur ? d.casc1 : d.casc0;
+    int stride = gridDim.x * blockDim.x;
+    if (nA + nB > d.n) {
+        if (gid == 0) latch(d.ctl, kErrLevel);
+        return;
+    }
+    for (int i = gid; i < nA + nB; i += stride) {
+        int32_t v = i < nA ? d.sorted[a0 + i] : casc[i - nA];
+        d.mv[i] = v;
+        add_chunks(d, v);
+    }
+    if (gid == 0) d.ctl->n_mv = nA + nB;
+}
+
+// Part 2: every mover v scans its slab.  Neighbour w at level l stays iff it
+// does not violate Invariant 1 (its up-degree is untouched in this step);
+// w at l+1 gains v as up-neighbour and is marked if that makes it exceed the
+// cap of level l+1; w at l+2 gains v as up*-neighbour.
+__global__ void k_ins_scan(Dev d) {
+    if (d.ctl->done) return;
+    int32_t l = d.ctl->l, nxt = d.ctl->cur ^ 1, nch = d.ctl->n_chunks;
+    int32_t *casc = nxt ? d.casc1 : d.casc0;
+    int32_t ub0 = d.up_max[l / d.L], ub1 = d.up_max[(l + 1) / d.L];
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = gridDim.x * blockDim.x / kWave;
+    int32_t scanned = 0;
+    for (int c = wid; c < nch; c += nw) {
+        int64_t desc = d.chunks[c];
+        int32_t v = (int32_t)(desc >> 32), k = (int32_t)(desc & 0xffffffff);
+        int32_t cap = d.cap[v];
+        const int32_t *s = d.pool + d.off[v];
+        int32_t lo = k * kChunk, hi = min(lo + kChunk, cap);
+        int32_t stay = 0;
+        for (int32_t e = lo + lane; e < hi; e += kWave) {
+            int32_t w = s[e];
+            if (w < 0) continue;
+            int32_t lw = d.level[w];
+            if (lw == l) {
+                stay += d.up[w] <= ub0;
+            } else if (lw == l + 1) {
+                int32_t old = atomicAdd(&d.up[w], 1);
+                if (old == ub1) push(casc, &d.ctl->casc_n[nxt], d.n, w, d.ctl);
+            } else if (lw == l + 2) {
+                atomicAdd(&d.ups[w], 1);
+            }
+        }
+        scanned += hi - lo;
+        stay = wave_sum(stay);
+        if (lane == 0 && stay) atomicAdd(&d.stay[v], stay);
+    }
+    if (lane == 0 && scanned) atomicAdd((unsigned long long *)&d.ctl->scanned, (unsigned long long)scanned);
+}
+
+// Part 3: movers take level l+1 with up*(v) = old up(v) and up(v) = old up(v)
+// minus the neighbours that stayed at l; a mover still above the cap of l+1
+// stays marked.  The last block picks the next level.
+__global__ void k_ins_fin(Dev d) {
+    if (d.ctl->done) return;
+    int32_t l = d.ctl->l, cur = d.ctl->cur, nxt = cur ^ 1, nmv = d.ctl->n_mv;
+    int32_t *casc = nxt ? d.casc1 : d.casc0;
+    int32_t ub1 = d.up_max[(l + 1) / d.L];
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmv; i += stride) {
+        int32_t v = d.mv[i];
+        d.level[v] = l + 1;
+        int32_t u = d.up[v];
+        d.ups[v] = u;
+        u -= d.stay[v];
+        d.stay[v] = 0;
+        d.up[v] = u;
+        if (u > ub1) push(casc, &d.ctl->casc_n[nxt], d.n, v, d.ctl);
+    }
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&d.ctl->blocks_done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        Ctl *c = d.ctl;
+        c->sweeps += 1;
+        c->moves += nmv;
+        c->top = max(c->top, (int64_t)(l + 1));
+        int32_t cn = atomicAdd(&c->casc_n[nxt], 0);
+        c->casc_n[cur] = 0;
+        c->cur = nxt;
+        c->n_chunks = 0;
+        c->n_mv = 0;
+        c->blocks_done = 0;
+        if (cn > 0) {
+            if (l + 2 >= d.K) {     // no vertex may pass the first level of the top group
+                latch(c, kErrLevel);
+                c->done = 1;
+            }
+            c->l = l + 1;
+        } else {
+            int32_t nl = l + 1 < d.K ? d.next_nz[l + 1] : d.K;
+            if (nl >= d.K) c->done = 1;
+            else c->l = nl;
+        }
+    }
+}
+
+// ------------------------------------------------------ deletion sweep
+// Desire-level (Def. desire-level) of an Invariant-2 violator w at level lw:
+// the largest l' in [1, lw-1] with cnt(l'-1) >= dn_min[(l'-1)/L], where
+// cnt(j) = #neighbours at level >= j; 0 if there is none.  Such an l' also
+// satisfies Invariant 1 (the count one level up is below dn_min <= up_max).
+// One block per vertex: histogram of neighbour levels in LDS (bins 0..lw-1,
+// the top bin holding every level >= lw-1), then a suffix scan.
+__device__ int32_t block_dl(Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_t *seg, int32_t *red) {
+    int tid = threadIdx.x, nt = blockDim.x;
+    int32_t nb = lw;
+    for (int i = tid; i < nb; i += nt) hist[i] = 0;
+    __syncthreads();
+    int32_t cap = d.cap[w];
+    const int32_t *s = d.pool + d.off[w];
+    for (int32_t e = tid; e < cap; e += nt) {
+        int32_t x = s[e];
+        if (x >= 0) atomicAdd(&hist[min(d.level[x], lw - 1)], 1);
+    }
+    __syncthreads();
+    int per = (nb + nt - 1) / nt, lo = min(nb, tid * per), hi = min(nb, lo + per);
+    int32_t sum = 0;
+    for (int i = lo; i < hi; i++) sum += hist[i];
+    seg[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {   // exclusive suffix sums of the segments
+        int32_t acc = 0;
+        for (int t = nt - 1; t >= 0; t--) {
+            int32_t x = seg[t];
+            seg[t] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+    int32_t best = -1, cnt = seg[tid];
+    for (int j = hi - 1; j >= lo; j--) {
+        cnt += hist[j];                       // cnt(j)
+        if (j <= lw - 2 && cnt >= d.dn_min[j / d.L]) {
+            best = j;
+            break;
+        }
+    }
+    int32_t wb = wave_max(best);
+    if (tid % kWave == 0) red[tid / kWave] = wb;
+    __syncthreads();
+    int32_t r = -1;
+    for (int i = 0; i < nt / kWave; i++) r = max(r, red[i]);
+    __syncthreads();
+    return r >= 0 ? r + 1 : 0;
+}
+
+// mode 0: seed from the endpoints of deleted edges (list = touch, pending
+// list = cur).  mode 1: recompute for the vertices listed in rc during a
+// step (pending list = next); the last block then closes the step.
+__global__ void k_dl(Dev d, int mode) {
+    extern __shared__ int32_t lds[];
+    int32_t *seg = lds, *red = lds + kBlock, *hist = lds + kBlock + 16;
+    Ctl *c = d.ctl;
+    int32_t cur = c->cur, tgt = mode == 0 ? cur : (cur ^ 1);
+    int32_t *plist = tgt ? d.p1 : d.p0;
+    int32_t cnt = mode == 0 ? c->n_touch : c->n_rc;
+    const int32_t *list = mode == 0 ? d.touch : d.rc;
+    int32_t l = mode == 0 ? -1 : c->l;
+    bool skip = mode == 1 && c->done;
+    int32_t ncalc = 0;
+    for (int i = blockIdx.x; !skip && i < cnt; i += gridDim.x) {
+        int32_t w = list[i];
+        if (mode == 0 && threadIdx.x == 0) d.addc[w] = 0;
+        int32_t lw = d.level[w];
+        bool viol = lw > 0 && d.ups[w] < d.dn_min[(lw - 1) / d.L];
+        if (!viol) continue;                  // block-uniform
+        int32_t dv = block_dl(d, w, lw, hist, seg, red);
+        ncalc++;
+        if (threadIdx.x == 0) {
+            if (dv <= l || dv >= lw) latch(c, kErrOrder);
+            if (d.dl[w] < 0) push(plist, &c->p_n[tgt], d.n, w, c);
+            d.dl[w] = dv;
+            atomicMin(&c->nm, dv);
+        }
+    }
+    if (threadIdx.x == 0 && ncalc) atomicAdd((unsigned long long *)&c->dl_calcs, (unsigned long long)ncalc);
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&c->blocks_done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        c->blocks_done = 0;
+        if (mode == 1 && !skip) {
+            c->sweeps += 1;
+            c->moves += c->n_mv;
+            c->p_n[cur] = 0;
+            c->cur = cur ^ 1;
+            c->n_mv = 0;
+            c->n_chunks = 0;
+            c->n_rc = 0;
+            c->step_id += 1;
+        }
+        if (!skip) {
+            int32_t nm = atomicAdd(&c->nm, 0);
+            c->nm = kInf;
+            if (nm == kInf) c->done = 1;
+            else c->l = nm;
+        }
+    }
+}
+
+// Step of Algorithm 3 at level l, part 1: the movers are the pending
+// vertices whose desire-level is l; the rest stay pending.
+__global__ void k_del_select(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    int32_t l = c->l, cur = c->cur, nxt = cur ^ 1, np = c->p_n[cur];
+    const int32_t *P = cur ? d.p1 : d.p0;
+    int32_t *Q = nxt ? d.p1 : d.p0;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
+        int32_t v = P[i], dv = d.dl[v];
+        if (dv == l) {
+            push(d.mv, &c->n_mv, d.n, v, c);
+            add_chunks(d, v);
+        } else {
+            if (dv < l) latch(c, kErrOrder);
+            push(Q, &c->p_n[nxt], d.n, v, c);
+            atomicMin(&c->nm, dv);
+        }
+    }
+}
+
+// Part 2: every mover v (previous level pv) scans its slab.  A neighbour w
+// with dl(w) = l moves too.  Any other w loses v from its up-degree if
+// l < level(w) <= pv and from its up*-degree if l+1 < level(w) <= pv+1; a w
+// that starts violating Invariant 2, or that is already pending, gets its
+// desire-level recomputed after the step.  v's own degrees at level l are
+// counted on the way.
+__global__ void k_del_scan(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    int32_t l = c->l, nch = c->n_chunks, sid = c->step_id;
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = gridDim.x * blockDim.x / kWave;
+    int32_t scanned = 0;
+    for (int ci = wid; ci < nch; ci += nw) {
+        int64_t desc = d.chunks[ci];
+        int32_t v = (int32_t)(desc >> 32), k = (int32_t)(desc & 0xffffffff);
+        int32_t cap = d.cap[v], pv = d.level[v];
+        const int32_t *s = d.pool + d.off[v];
+        int32_t lo = k * kChunk, hi = min(lo + kChunk, cap);
+        int32_t cu = 0, cus = 0;
+        for (int32_t e = lo + lane; e < hi; e += kWave) {
+            int32_t w = s[e];
+            if (w < 0) continue;
+            int32_t dw = d.dl[w];
+            if (dw == l) {
+                cu++;
+                cus++;
+                continue;
+            }
+            int32_t lw = d.level[w];
+            cu += lw >= l;
+            cus += lw >= l - 1;
+            bool again = dw >= 0;
+            if (lw > l && lw <= pv) atomicSub(&d.up[w], 1);
+            if (lw > l + 1 && lw <= pv + 1) {
+                int32_t old = atomicSub(&d.ups[w], 1);
+                if (old == d.dn_min[(lw - 1) / d.L]) again = true;
+            }
+            if (again && atomicExch(&d.rcstamp[w], sid) != sid) push(d.rc, &c->n_rc, d.n, w, c);
+        }
+        scanned += hi - lo;
+        cu = wave_sum(cu);
+        cus = wave_sum(cus);
+        if (lane == 0) {
+            if (cu) atomicAdd(&d.stay[v], cu);
+            if (cus) atomicAdd(&d.cnt2[v], cus);
+        }
+    }
+    if (lane == 0 && scanned) atomicAdd((unsigned long long *)&c->scanned, (unsigned long long)scanned);
+}
+
+// Part 3: movers take level l with their recounted degrees and leave the
+// pending set.
+__global__ void k_del_fin(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    int32_t l = c->l, nmv = c->n_mv;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmv; i += stride) {
+        int32_t v = d.mv[i];
+        d.level[v] = l;
+        d.up[v] = d.stay[v];
+        d.ups[v] = d.cnt2[v];
+        d.stay[v] = 0;
+        d.cnt2[v] = 0;
+        d.dl[v] = -1;
+    }
+}
+
+// ------------------------------------------------------------- queries
+// Def. coreness estimate: (1+delta)^max(floor((l+1)/L)-1, 0), 0 if isolated.
+__global__ void k_coreness(Dev d, const int32_t *vs, int64_t cnt, double *out) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        int32_t v = vs ? vs[i] : (int32_t)i;
+        if (v < 0 || v >= d.n) {
+            out[i] = -1.0;
+            latch(d.ctl, kErrRange);
+            continue;
+        }
+        int32_t e = (d.level[v] + 1) / d.L - 1;
+        out[i] = d.deg[v] == 0 ? 0.0 : d.pow_tab[e > 0 ? e : 0];
+    }
+}
+
+// Full check, one wave per vertex; bad[0..5] count violations of:
+// counters, Invariant 1, Invariant 2, isolated at level 0, level range,
+// slab live count == degree.
+__global__ void k_check(Dev d, int32_t *bad) {
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = gridDim.x * blockDim.x / kWave;
+    for (int v = wid; v < d.n; v += nw) {
+        int32_t lv = d.level[v], cap = d.cap[v];
+        const int32_t *s = d.pool + d.off[v];
+        int32_t cu = 0, cus = 0, live = 0;
+        for (int32_t e = lane; e < cap; e += kWave) {
+            int32_t w = s[e];
+            if (w < 0) continue;
+            int32_t lw = d.level[w];
+            live++;
+            cu += lw >= lv;
+            cus += lw >= lv - 1;
+        }
+        cu = wave_sum(cu);
+        cus = wave_sum(cus);
+        live = wave_sum(live);
+        if (lane == 0) {
+            if (lv < 0 || lv >= d.K) {
+                atomicAdd(&bad[4], 1);
+            } else {
+                if (cu != d.up[v] || cus != d.ups[v]) atomicAdd(&bad[0], 1);
+                if (cu > d.up_max[lv / d.L]) atomicAdd(&bad[1], 1);
+                if (lv > 0 && cus < d.dn_min[(lv - 1) / d.L]) atomicAdd(&bad[2], 1);
+                if (d.deg[v] == 0 && lv != 0) atomicAdd(&bad[3], 1);
+                if (live != d.deg[v]) atomicAdd(&bad[5], 1);
+            }
+        }
+    }
+}
+
+__global__ void k_dump_edges(Dev d, int32_t *out, int64_t cap_out) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // thread per slot of the whole used pool is not available; walk vertices
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < d.n; v += stride) {
+        int32_t cap = d.cap[v];
+        const int32_t *s = d.pool + d.off[v];
+        for (int32_t e = 0; e < cap; e++) {
+            int32_t w = s[e];
+            if (w > (int32_t)v) {
+                int64_t k = (int64_t)atomicAdd((unsigned long long *)&d.ctl->m_out, 1ull);
+                if (k < cap_out) {
+                    out[2 * k] = (int32_t)v;
+                    out[2 * k + 1] = w;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_clear_touch(Dev d) {
+    int32_t nt = d.ctl->n_touch;
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) d.addc[d.touch[i]] = 0;
+}
+
+__global__ void k_set_levels(Dev d, const int32_t *lv) {
+    int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) {
+        int32_t x = lv[v];
+        if (x < 0 || x >= d.K) latch(d.ctl, kErrLevel);
+        d.level[v] = x;
+    }
+}
+
+// pool compaction: new offsets by exclusive scan of capacities
+__global__ void k_scan_tiles(const int32_t *in, int64_t n, int64_t *tile_sum) {
+    __shared__ int64_t sh[kBlock];
+    int64_t base = (int64_t)blockIdx.x * kBlock * 4;
+    int64_t s = 0;
+    for (int j = 0; j < 4; j++) {
+        int64_t i = base + j * kBlock + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = sh[0];
+}
+__global__ void k_scan_tile_prefix(int64_t *tile_sum, int64_t ntiles) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t acc = 0;
+        for (int64_t i = 0; i < ntiles; i++) {
+            int64_t x = tile_sum[i];
+            tile_sum[i] = acc;
+            acc += x;
+        }
+        tile_sum[ntiles] = acc;
+    }
+}
+__global__ void k_scan_apply(const int32_t *in, int64_t n, const int64_t *tile_sum, int64_t *out) {
+    if (threadIdx.x != 0) return;
+    int64_t base = (int64_t)blockIdx.x * kBlock * 4;
+    int64_t acc = tile_sum[blockIdx.x];
+    for (int64_t i = base; i < std::min<int64_t>(n, base + kBlock * 4); i++) {
+        out[i] = acc;
+        acc += in[i];
+    }
+}
+__global__ void k_compact_copy(Dev d, const int64_t *newoff, int32_t *newpool) {
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = gridDim.x * blockDim.x / kWave;
+    for (int v = wid; v < d.n; v += nw) {
+        int32_t cap = d.cap[v];
+        const int32_t *s = d.pool + d.off[v];
+        int32_t *t = newpool + newoff[v];
+        for (int32_t e = lane; e < cap; e += kWave) t[e] = s[e];
+    }
+}
+__global__ void k_set_offsets(Dev d, const int64_t *newoff) {
+    int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) d.off[v] = newoff[v];
+}
+
+}  // namespace
+
+// ===================================================================== host
+struct plds {
+    int64_t n = 0, m = 0;
+    double delta = 0, lambda = 0;
+    int32_t t = 0, L = 0, G = 0, K = 0;
+    int device = 0;
+    std::vector<int32_t> h_up_max, h_dn_min;
+    std::vector<double> h_pow;
+    Dev d{};
+    int64_t batch_cap = 0;
+    int64_t pool_top = 0;
+    int64_t *tile = nullptr;
+    int64_t tile_cap = 0;
+    int64_t *newoff = nullptr;
+    int32_t *bad = nullptr;
+    Ctl *h_ctl = nullptr;   // pinned host mirror
+    plds_stats_t stats{};
+    int32_t latched = 0;
+    bool broken = false;
+};
+
+namespace {
+
+#define HIPCHK(x)                      \
+    do {                               \
+        if ((x) != hipSuccess) {       \
+            return PLDS_EHIP;          \
+        }                              \
+    } while (0)
+
+template <class T>
+int dalloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    if (hipMalloc((void **)p, (size_t)count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return PLDS_ENOMEM;
+    }
+    return PLDS_OK;
+}
+
+template <class T>
+void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+int grid_for(int64_t work, int block = kBlock, int cap = 4096) {
+    int64_t g = (work + block - 1) / block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// Levels and groups (Section "Detailed PLDS Algorithm"): t = least integer with
+// (1+delta)^t >= n, L = 4t (or override, at least 1), G = t+1, K = G*L.
+// Thresholds as exact integer rewrites of Invariants 1-2:
+// up_max[g] = floor((2+3/lambda) x_g), dn_min[g] = ceil(x_g), where x_g is
+// (1+delta)^g formed by repeated IEEE double multiplication.
+void build_tables(plds *h, int32_t lpg) {
+    double p = 1.0;
+    int32_t t = 0;
+    while (p < (double)h->n) {
+        p *= 1.0 + h->delta;
+        t++;
+    }
+    h->t = t;
+    h->L = lpg > 0 ? lpg : std::max(1, 4 * t);
+    h->G = t + 1;
+    h->K = h->G * h->L;
+    h->h_up_max.assign(h->G + 1, INT32_MAX);
+    h->h_dn_min.assign(h->G + 1, INT32_MAX);
+    h->h_pow.assign(h->G, 1.0);
+    double coeff = 2.0 + 3.0 / h->lambda, x = 1.0;
+    for (int32_t g = 0; g < h->G; g++) {
+        if (g > 0) x *= 1.0 + h->delta;
+        h->h_pow[g] = x;
+        double ub = std::floor(coeff * x), lb = std::ceil(x);
+        h->h_up_max[g] = ub >= (double)INT32_MAX ? INT32_MAX : (int32_t)ub;
+        h->h_dn_min[g] = lb >= (double)INT32_MAX ? INT32_MAX : (int32_t)lb;
+    }
+}
+
+void free_all(plds *h) {
+    Dev &d = h->d;
+    dfree(d.up_max), dfree(d.dn_min), dfree(d.pow_tab);
+    dfree(d.level), dfree(d.deg), dfree(d.up), dfree(d.ups), dfree(d.cap), dfree(d.fill), dfree(d.off);
+    dfree(d.pool), dfree(d.stay), dfree(d.cnt2), dfree(d.addc), dfree(d.dl), dfree(d.rcstamp), dfree(d.ctl);
+    dfree(d.hset), dfree(d.valid), dfree(d.touch), dfree(d.grow), dfree(d.newcap), dfree(d.oldoff),
+        dfree(d.oldcap);
+    dfree(d.cand), dfree(d.sorted), dfree(d.lvl_cnt), dfree(d.lvl_start), dfree(d.next_nz);
+    dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
+    dfree(h->tile), dfree(h->newoff), dfree(h->bad);
+    if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+    h->h_ctl = nullptr;
+}
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+int sync_ctl(plds *h, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(h->h_ctl, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->stats.host_syncs++;
+    return PLDS_OK;
+}
+
+int ensure_batch(plds *h, int64_t count) {
+    if (count <= h->batch_cap) return PLDS_OK;
+    int64_t cap = std::max<int64_t>(count, 1024);
+    Dev &d = h->d;
+    dfree(d.hset), dfree(d.valid);
+    uint64_t hs = 1;
+    while (hs < (uint64_t)(2 * cap)) hs <<= 1;
+    int rc = dalloc(&d.hset, (int64_t)hs);
+    if (!rc) rc = dalloc(&d.valid, 2 * cap);
+    if (rc) {
+        dfree(d.hset), dfree(d.valid);
+        h->batch_cap = 0;
+        return rc;
+    }
+    d.hmask = hs - 1;
+    h->batch_cap = cap;
+    return PLDS_OK;
+}
+
+int ensure_chunks(plds *h) {
+    // one descriptor per kChunk slots of any slab plus one per vertex
+    int64_t need = h->n + h->d.pool_cap / kChunk + 1;
+    if (need <= h->d.chunk_cap) return PLDS_OK;
+    dfree(h->d.chunks);
+    int rc = dalloc(&h->d.chunks, need);
+    h->d.chunk_cap = rc ? 0 : need;
+    return rc;
+}
+
+// exclusive scan of d.cap into newoff (int64), returns the total
+int scan_caps(plds *h, hipStream_t s, int64_t *total) {
+    int64_t n = h->n, ntiles = (n + kBlock * 4 - 1) / (kBlock * 4);
+    if (ntiles + 1 > h->tile_cap) {
+        dfree(h->tile);
+        if (dalloc(&h->tile, ntiles + 1)) return PLDS_ENOMEM;
+        h->tile_cap = ntiles + 1;
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, h->d.cap, n, h->tile);
+    hipLaunchKernelGGL(k_scan_tile_prefix, dim3(1), dim3(64), 0, s, h->tile, ntiles);
+    hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(64), 0, s, h->d.cap, n, h->tile, h->newoff);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(total, h->tile + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PLDS_OK;
+}
+
+// Make room for `extra` more pool slots: compact live slabs into a new pool
+// sized for the live total plus `extra`, with headroom.
+int ensure_pool(plds *h, hipStream_t s, int64_t extra) {
+    if (h->pool_top + extra <= h->d.pool_cap) return PLDS_OK;
+    int64_t live = 0;
+    int rc = scan_caps(h, s, &live);
+    if (rc) return rc;
+    int64_t want = std::max<int64_t>((live + extra) * 3 / 2, h->d.pool_cap);
+    want = std::max<int64_t>(want, live + extra + (1 << 20));
+    int32_t *np = nullptr;
+    if (dalloc(&np, want)) return PLDS_ENOMEM;
+    hipLaunchKernelGGL(k_compact_copy, dim3(grid_for(h->n * kWave)), dim3(kBlock), 0, s, h->d, h->newoff, np);
+    hipLaunchKernelGGL(k_set_offsets, dim3(grid_for(h->n)), dim3(kBlock), 0, s, h->d, h->newoff);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(h->d.pool);
+    h->d.pool = np;
+    h->d.pool_cap = want;
+    h->pool_top = live;
+    h->h_ctl->pool_top = live;
+    HIPCHK(hipMemcpyAsync(&h->d.ctl->pool_top, &h->h_ctl->pool_top, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ensure_chunks(h);
+}
+
+// reset the per-call fields of the control block (host mirror -> device)
+int ctl_reset_batch(plds *h, hipStream_t s) {
+    Ctl *c = h->h_ctl;
+    c->n_valid = c->n_touch = c->n_grow = c->n_cand = 0;
+    c->grow_req = 0;
+    c->l = 0;
+    c->done = 0;
+    c->cur = 0;
+    c->n_mv = 0;
+    c->casc_n[0] = c->casc_n[1] = 0;
+    c->p_n[0] = c->p_n[1] = 0;
+    c->n_chunks = c->n_rc = 0;
+    c->nm = kInf;
+    c->blocks_done = 0;
+    c->sweeps = c->moves = c->scanned = c->dl_calcs = 0;
+    c->top = 0;
+    c->m_out = 0;
+    c->pool_top = h->pool_top;
+    HIPCHK(hipMemcpyAsync(h->d.ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    return PLDS_OK;
+}
+
+int check_err(plds *h) {
+    int32_t e = h->h_ctl->err;
+    if (e & (kErrFull | kErrLevel | kErrOrder)) {
+        h->broken = true;
+        return PLDS_ESTATE;
+    }
+    if (e & kErrPool) {
+        h->broken = true;
+        return PLDS_ENOMEM;
+    }
+    return PLDS_OK;
+}
+
+// Preprocess one list and apply it to the slabs.  insert=1: keep absent
+// pairs, regrow slabs, insert; insert=0: keep present pairs, delete.
+// On return the touched endpoints are in d.touch (count in ctl).
+int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s, int64_t *applied) {
+    Dev &d = h->d;
+    *applied = 0;
+    int rc = ensure_batch(h, cnt);
+    if (rc) return rc;
+    rc = ctl_reset_batch(h, s);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(d.hset, 0xff, (size_t)(d.hmask + 1) * sizeof(uint64_t), s));
+    hipLaunchKernelGGL(k_dedupe, dim3(grid_for(cnt)), dim3(kBlock), 0, s, d, e, cnt, insert ? 0 : 1);
+    hipLaunchKernelGGL(k_touch, dim3(grid_for(2 * cnt)), dim3(kBlock), 0, s, d);
+    if (insert) hipLaunchKernelGGL(k_plan_growth, dim3(grid_for(2 * cnt)), dim3(kBlock), 0, s, d);
+    HIPCHK(hipGetLastError());
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    *applied = h->h_ctl->n_valid;
+    if (insert) {
+        if (h->h_ctl->n_grow > 0) {
+            int64_t req = h->h_ctl->grow_req;
+            rc = ensure_pool(h, s, req);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_grow_alloc, dim3(grid_for((int64_t)h->h_ctl->n_grow * kWave)), dim3(kBlock), 0,
+                               s, d);
+            hipLaunchKernelGGL(k_grow_move, dim3(grid_for((int64_t)h->h_ctl->n_grow * kWave)), dim3(kBlock), 0,
+                               s, d);
+            h->pool_top += req;
+        }
+        hipLaunchKernelGGL(k_apply_ins, dim3(grid_for(*applied)), dim3(kBlock), 0, s, d);
+    } else {
+        hipLaunchKernelGGL(k_apply_del, dim3(grid_for(*applied)), dim3(kBlock), 0, s, d);
+    }
+    HIPCHK(hipGetLastError());
+    h->m += insert ? *applied : -*applied;
+    return PLDS_OK;
+}
+
+// Algorithm 2 after the edges are in: seed, bucket by level, then run level
+// steps in growing runs until the control block reports done.
+int insertion_sweep(plds *h, hipStream_t s) {
+    Dev &d = h->d;
+    int nt = h->h_ctl->n_touch;
+    HIPCHK(hipMemsetAsync(d.lvl_cnt, 0, (size_t)(h->K + 1) * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_ins_seed, dim3(grid_for(nt)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d);
+    HIPCHK(hipGetLastError());
+    int rc = sync_ctl(h, s);
+    if (rc) return rc;
+    h->stats.viol_ins0 = h->h_ctl->n_cand;
+    int run = 8;
+    int64_t steps = 0;
+    while (!h->h_ctl->done && !h->h_ctl->err) {
+        if (steps > (int64_t)h->K + 1) {    // each step raises the level: at most K steps
+            h->broken = true;
+            return PLDS_ESTATE;
+        }
+        steps += run;
+        for (int i = 0; i < run; i++) {
+            hipLaunchKernelGGL(k_ins_prep, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+            hipLaunchKernelGGL(k_ins_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
+            hipLaunchKernelGGL(k_ins_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+        }
+        HIPCHK(hipGetLastError());
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+        run = std::min(run * 2, 256);
+    }
+    Ctl *c = h->h_ctl;
+    h->stats.sweeps_ins += c->sweeps;
+    h->stats.moves_up += c->moves;
+    h->stats.slots_scanned += c->scanned;
+    h->stats.top_level = std::max(h->stats.top_level, c->top);
+    return check_err(h);
+}
+
+int deletion_sweep(plds *h, hipStream_t s) {
+    Dev &d = h->d;
+    size_t lds = (size_t)(kBlock + 16 + h->K + 1) * sizeof(int32_t);
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)k_dl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return PLDS_EINVAL;
+    hipLaunchKernelGGL(k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 0);
+    HIPCHK(hipGetLastError());
+    int rc = sync_ctl(h, s);
+    if (rc) return rc;
+    h->stats.viol_del0 = h->h_ctl->p_n[0];
+    int run = 4;
+    int64_t steps = 0;
+    while (!h->h_ctl->done && !h->h_ctl->err) {
+        if (steps > (int64_t)h->K + 1) {
+            h->broken = true;
+            return PLDS_ESTATE;
+        }
+        steps += run;
+        for (int i = 0; i < run; i++) {
+            hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+            hipLaunchKernelGGL(k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
+            hipLaunchKernelGGL(k_del_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+            hipLaunchKernelGGL(k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 1);
+        }
+        HIPCHK(hipGetLastError());
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+        run = std::min(run * 2, 128);
+    }
+    Ctl *c = h->h_ctl;
+    h->stats.sweeps_del += c->sweeps;
+    h->stats.moves_down += c->moves;
+    h->stats.slots_scanned += c->scanned;
+    h->stats.dl_calcs += c->dl_calcs;
+    return check_err(h);
+}
+
+int guard(const plds *h) {
+    if (!h) return PLDS_EINVAL;
+    if (h->broken) return PLDS_ESTATE;
+    if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
+    return PLDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *plds_strerror(int code) {
+    switch (code) {
+        case PLDS_OK: return "ok";
+        case PLDS_EINVAL: return "invalid argument";
+        case PLDS_ERANGE: return "vertex id out of range";
+        case PLDS_ENOMEM: return "out of memory";
+        case PLDS_EHIP: return "HIP runtime error";
+        case PLDS_ESTATE: return "internal consistency check failed";
+        default: return "unknown error";
+    }
+}
+
+int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int64_t edge_capacity_hint,
+                   plds_t **out) {
+    if (!out) return PLDS_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > INT32_MAX || !(delta > 0) || !(lambda > 0) || !std::isfinite(delta) ||
+        !std::isfinite(lambda) || levels_per_group < 0 || edge_capacity_hint < 0)
+        return PLDS_EINVAL;
+    plds *h = new (std::nothrow) plds();
+    if (!h) return PLDS_ENOMEM;
+    h->n = n;
+    h->delta = delta;
+    h->lambda = lambda;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return PLDS_EHIP;
+    }
+    build_tables(h, levels_per_group);
+    if ((int64_t)h->G * h->L > INT32_MAX / 2) {
+        delete h;
+        return PLDS_EINVAL;
+    }
+    Dev &d = h->d;
+    d.n = (int32_t)n;
+    d.L = h->L;
+    d.G = h->G;
+    d.K = h->K;
+    int rc = 0;
+    rc |= dalloc(&d.up_max, h->G + 1) | dalloc(&d.dn_min, h->G + 1) | dalloc(&d.pow_tab, h->G);
+    rc |= dalloc(&d.level, n) | dalloc(&d.deg, n) | dalloc(&d.up, n) | dalloc(&d.ups, n);
+    rc |= dalloc(&d.cap, n) | dalloc(&d.fill, n) | dalloc(&d.off, n);
+    rc |= dalloc(&d.stay, n) | dalloc(&d.cnt2, n) | dalloc(&d.addc, n) | dalloc(&d.dl, n) | dalloc(&d.rcstamp, n);
+    rc |= dalloc(&d.ctl, 1);
+    rc |= dalloc(&d.touch, n) | dalloc(&d.grow, n) | dalloc(&d.newcap, n) | dalloc(&d.oldoff, n) |
+          dalloc(&d.oldcap, n);
+    rc |= dalloc(&d.cand, n) | dalloc(&d.sorted, n);
+    rc |= dalloc(&d.lvl_cnt, h->K + 1) | dalloc(&d.lvl_start, h->K + 1) | dalloc(&d.next_nz, h->K + 1);
+    rc |= dalloc(&d.casc0, n) | dalloc(&d.casc1, n) | dalloc(&d.mv, n);
+    rc |= dalloc(&d.p0, n) | dalloc(&d.p1, n) | dalloc(&d.rc, n);
+    rc |= dalloc(&h->newoff, n) | dalloc(&h->bad, 8);
+    int64_t pool = std::max<int64_t>(1 << 20, 12 * n + (edge_capacity_hint * 2 * 5) / 3);
+    rc |= dalloc(&d.pool, pool);
+    if (!rc) {
+        d.pool_cap = pool;
+        rc = ensure_chunks(h);
+    }
+    if (!rc && hipHostMalloc((void **)&h->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) rc = PLDS_ENOMEM;
+    if (rc) {
+        free_all(h);
+        delete h;
+        return PLDS_ENOMEM;
+    }
+    memset(h->h_ctl, 0, sizeof(Ctl));
+    h->h_ctl->nm = kInf;
+    hipStream_t s = 0;
+    bool ok = hipMemcpy(d.up_max, h->h_up_max.data(), (h->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(d.dn_min, h->h_dn_min.data(), (h->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(d.pow_tab, h->h_pow.data(), h->G * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemsetAsync(d.level, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.deg, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.up, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.ups, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.cap, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.fill, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.off, 0, n * sizeof(int64_t), s) == hipSuccess &&
+              hipMemsetAsync(d.stay, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.cnt2, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.addc, 0, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.dl, 0xff, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.rcstamp, 0xff, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemcpy(d.ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) == hipSuccess &&
+              hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        free_all(h);
+        delete h;
+        return PLDS_EHIP;
+    }
+    *out = h;
+    return PLDS_OK;
+}
+
+int plds_create(int64_t n, double delta, double lambda, plds_t **out) {
+    return plds_create_ex(n, delta, lambda, 0, 0, out);
+}
+
+int plds_destroy(plds_t *h) {
+    if (!h) return PLDS_EINVAL;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    free_all(h);
+    delete h;
+    return PLDS_OK;
+}
+
+int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (n_ins < 0 || n_del < 0 || (n_ins && !ins) || (n_del && !del)) return PLDS_EINVAL;
+    if ((uint64_t)n_ins > (uint64_t)INT32_MAX / 2 || (uint64_t)n_del > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    memset(&h->stats, 0, sizeof(h->stats));
+    if (n_ins + n_del == 0) return PLDS_OK;
+    // range check of both lists before anything changes
+    h->h_ctl->err = 0;
+    HIPCHK(hipMemcpyAsync(&h->d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (n_ins) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_ins)), dim3(kBlock), 0, s, ins, n_ins, h->d.n, h->d.ctl);
+    if (n_del) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_del)), dim3(kBlock), 0, s, del, n_del, h->d.n, h->d.ctl);
+    HIPCHK(hipGetLastError());
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    if (h->h_ctl->err & kErrRange) {
+        h->h_ctl->err = 0;
+        HIPCHK(hipMemcpyAsync(&h->d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return PLDS_ERANGE;
+    }
+    if (n_ins) {
+        int64_t applied = 0;
+        rc = apply_list(h, ins, n_ins, 1, s, &applied);
+        if (rc) return rc;
+        h->stats.applied_ins = applied;
+        if (applied) {
+            rc = insertion_sweep(h, s);
+            if (rc) return rc;
+        }
+    }
+    if (n_del) {
+        int64_t applied = 0;
+        rc = apply_list(h, del, n_del, 0, s, &applied);
+        if (rc) return rc;
+        h->stats.applied_del = applied;
+        if (applied) {
+            rc = deletion_sweep(h, s);
+            if (rc) return rc;
+        }
+    }
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    return check_err(h);
+}
+
+int plds_batch_insert(plds_t *h, const int32_t *edges, int64_t count, void *stream) {
+    return plds_update(h, edges, count, nullptr, 0, stream);
+}
+
+int plds_batch_delete(plds_t *h, const int32_t *edges, int64_t count, void *stream) {
+    return plds_update(h, nullptr, 0, edges, count, stream);
+}
+
+int plds_coreness(plds_t *h, const int32_t *vertices, int64_t count, double *out, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!out || (vertices && count < 0)) return PLDS_EINVAL;
+    int64_t cnt = vertices ? count : h->n;
+    if (cnt == 0) return PLDS_OK;
+    hipLaunchKernelGGL(k_coreness, dim3(grid_for(cnt)), dim3(kBlock), 0, S(stream), h->d, vertices, cnt, out);
+    HIPCHK(hipGetLastError());
+    return PLDS_OK;
+}
+
+int plds_levels(plds_t *h, int32_t *out, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!out) return PLDS_EINVAL;
+    HIPCHK(hipMemcpyAsync(out, h->d.level, h->n * sizeof(int32_t), hipMemcpyDeviceToDevice, S(stream)));
+    return PLDS_OK;
+}
+
+int plds_degrees(plds_t *h, int32_t *out, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!out) return PLDS_EINVAL;
+    HIPCHK(hipMemcpyAsync(out, h->d.deg, h->n * sizeof(int32_t), hipMemcpyDeviceToDevice, S(stream)));
+    return PLDS_OK;
+}
+
+int plds_info(const plds_t *h, plds_info_t *out) {
+    if (!h || !out) return PLDS_EINVAL;
+    out->n = h->n;
+    out->m = h->m;
+    out->t = h->t;
+    out->L = h->L;
+    out->G = h->G;
+    out->K = h->K;
+    out->delta = h->delta;
+    out->lambda = h->lambda;
+    out->slab_slots = h->d.pool_cap;
+    out->slab_used = h->pool_top;
+    return PLDS_OK;
+}
+
+int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *pow_tab) {
+    if (!h) return PLDS_EINVAL;
+    for (int32_t g = 0; g < h->G; g++) {
+        if (up_max) up_max[g] = h->h_up_max[g];
+        if (dn_min) dn_min[g] = h->h_dn_min[g];
+        if (pow_tab) pow_tab[g] = h->h_pow[g];
+    }
+    return PLDS_OK;
+}
+
+int plds_stats(const plds_t *h, plds_stats_t *out) {
+    if (!h || !out) return PLDS_EINVAL;
+    *out = h->stats;
+    return PLDS_OK;
+}
+
+int plds_check(plds_t *h, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    HIPCHK(hipMemsetAsync(h->bad, 0, 8 * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_check, dim3(grid_for(h->n * kWave)), dim3(kBlock), 0, s, h->d, h->bad);
+    HIPCHK(hipGetLastError());
+    int32_t bad[8];
+    HIPCHK(hipMemcpyAsync(bad, h->bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < 6; i++)
+        if (bad[i]) return PLDS_ESTATE;
+    return PLDS_OK;
+}
+
+int plds_dump_state(plds_t *h, int32_t *edges, int64_t cap, int64_t *m_out, int32_t *levels, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!m_out || cap < 0 || (cap && !edges)) return PLDS_EINVAL;
+    *m_out = h->m;
+    if (cap < h->m) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    h->h_ctl->m_out = 0;
+    HIPCHK(hipMemcpyAsync(&h->d.ctl->m_out, &h->h_ctl->m_out, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_dump_edges, dim3(grid_for(h->n)), dim3(kBlock), 0, s, h->d, edges, cap);
+    HIPCHK(hipGetLastError());
+    if (levels) HIPCHK(hipMemcpyAsync(levels, h->d.level, h->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    if (h->h_ctl->m_out != h->m) return PLDS_ESTATE;
+    return PLDS_OK;
+}
+
+int plds_load_state(plds_t *h, const int32_t *edges, int64_t m, const int32_t *levels, void *stream) {
+    if (!h) return PLDS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
+    if (m < 0 || (m && !edges) || !levels || (uint64_t)m > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    Dev &d = h->d;
+    // validate ids and levels before touching the state
+    h->h_ctl->err = 0;
+    HIPCHK(hipMemcpyAsync(&d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (m) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * m)), dim3(kBlock), 0, s, edges, m, d.n, d.ctl);
+    HIPCHK(hipGetLastError());
+    int rc = sync_ctl(h, s);
+    if (rc) return rc;
+    if (h->h_ctl->err & kErrRange) return PLDS_ERANGE;
+    // wipe
+    h->broken = false;
+    h->pool_top = 0;
+    h->m = 0;
+    size_t n4 = h->n * sizeof(int32_t);
+    HIPCHK(hipMemsetAsync(d.deg, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.up, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.ups, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.cap, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.fill, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.off, 0, h->n * sizeof(int64_t), s));
+    HIPCHK(hipMemsetAsync(d.addc, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.stay, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.cnt2, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.dl, 0xff, n4, s));
+    hipLaunchKernelGGL(k_set_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d, levels);
+    HIPCHK(hipGetLastError());
+    int64_t applied = 0;
+    if (m) {
+        rc = apply_list(h, edges, m, 1, s, &applied);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_clear_touch, dim3(grid_for(h->h_ctl->n_touch)), dim3(kBlock), 0, s, d);
+    }
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    if (h->h_ctl->err & kErrLevel) {
+        h->broken = true;
+        return PLDS_EINVAL;
+    }
+    rc = check_err(h);
+    if (rc) return rc;
+    return plds_check(h, stream);
+}
+
+int plds_sync(plds_t *h, void *stream) {
+    if (!h) return PLDS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
+    int rc = sync_ctl(h, S(stream));
+    if (rc) return rc;
+    if (h->h_ctl->err & kErrRange) {
+        h->h_ctl->err &= ~kErrRange;
+        HIPCHK(hipMemcpyAsync(&h->d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, S(stream)));
+        HIPCHK(hipStreamSynchronize(S(stream)));
+        return PLDS_ERANGE;
+    }
+    return h->broken ? PLDS_ESTATE : PLDS_OK;
+}
+
+}  // extern "C"

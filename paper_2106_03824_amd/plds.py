@@ -1,0 +1,282 @@
+"""Thin ctypes binding of ``libplds.so`` (C ABI in ``include/plds.h``).
+
+Functions carry the C names; pointers are taken from torch CUDA tensors (or
+raw integer addresses) and streams from ``torch.cuda.current_stream()``.
+Nothing here computes: every step of the path runs in the library's HIP
+kernels.  Loading raises if the library has not been built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libplds.so")
+
+PLDS_OK, PLDS_EINVAL, PLDS_ERANGE, PLDS_ENOMEM, PLDS_EHIP, PLDS_ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class PLDSError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class plds_info_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("t", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("G", ctypes.c_int32), ("K", ctypes.c_int32), ("delta", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("slab_slots", ctypes.c_int64), ("slab_used", ctypes.c_int64)]
+
+
+STAT_FIELDS = ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up", "moves_down", "dl_calcs",
+               "slots_scanned", "top_level", "viol_ins0", "viol_del0", "host_syncs")
+
+
+class plds_stats_t(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS] + [("reserved", ctypes.c_int64 * 4)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2106_03824_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.plds_create.argtypes = [_I64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_VP)]
+        L.plds_create_ex.argtypes = [_I64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _I64,
+                                     ctypes.POINTER(_VP)]
+        L.plds_destroy.argtypes = [_VP]
+        L.plds_update.argtypes = [_VP, _VP, _I64, _VP, _I64, _VP]
+        L.plds_batch_insert.argtypes = [_VP, _VP, _I64, _VP]
+        L.plds_batch_delete.argtypes = [_VP, _VP, _I64, _VP]
+        L.plds_coreness.argtypes = [_VP, _VP, _I64, _VP, _VP]
+        L.plds_levels.argtypes = [_VP, _VP, _VP]
+        L.plds_degrees.argtypes = [_VP, _VP, _VP]
+        L.plds_info.argtypes = [_VP, ctypes.POINTER(plds_info_t)]
+        L.plds_thresholds.argtypes = [_VP, _VP, _VP, _VP]
+        L.plds_stats.argtypes = [_VP, ctypes.POINTER(plds_stats_t)]
+        L.plds_dump_state.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64), _VP, _VP]
+        L.plds_load_state.argtypes = [_VP, _VP, _I64, _VP, _VP]
+        L.plds_check.argtypes = [_VP, _VP]
+        L.plds_sync.argtypes = [_VP, _VP]
+        L.plds_strerror.restype = ctypes.c_char_p
+        L.plds_strerror.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_update", "plds_batch_insert",
+           "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
+           "plds_stats", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror")
+
+
+def strerror(code):
+    try:
+        return lib().plds_strerror(int(code)).decode()
+    except ImportError:
+        return str(code)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _chk(rc, where):
+    if rc != PLDS_OK:
+        raise PLDSError(rc, where)
+    return rc
+
+
+def _edges_arg(e):
+    if e is None:
+        return None, 0
+    assert e.dtype.itemsize == 4 and e.is_cuda and e.is_contiguous() and e.dim() == 2 and e.shape[1] == 2
+    return _ptr(e), int(e.shape[0])
+
+
+# ---------------------------------------------------------------- C names
+def plds_create(n, delta, lam):
+    h = _VP()
+    _chk(lib().plds_create(int(n), float(delta), float(lam), ctypes.byref(h)), "plds_create")
+    return h
+
+
+def plds_create_ex(n, delta, lam, levels_per_group=0, edge_capacity_hint=0):
+    h = _VP()
+    _chk(lib().plds_create_ex(int(n), float(delta), float(lam), int(levels_per_group), int(edge_capacity_hint),
+                              ctypes.byref(h)), "plds_create_ex")
+    return h
+
+
+def plds_destroy(h):
+    return _chk(lib().plds_destroy(h), "plds_destroy")
+
+
+def plds_update(h, ins=None, dele=None, stream=None, check=True):
+    pi, ni = _edges_arg(ins)
+    pd, nd = _edges_arg(dele)
+    rc = lib().plds_update(h, pi, ni, pd, nd, _stream(stream))
+    return _chk(rc, "plds_update") if check else rc
+
+
+def plds_batch_insert(h, edges, stream=None, check=True):
+    p, c = _edges_arg(edges)
+    rc = lib().plds_batch_insert(h, p, c, _stream(stream))
+    return _chk(rc, "plds_batch_insert") if check else rc
+
+
+def plds_batch_delete(h, edges, stream=None, check=True):
+    p, c = _edges_arg(edges)
+    rc = lib().plds_batch_delete(h, p, c, _stream(stream))
+    return _chk(rc, "plds_batch_delete") if check else rc
+
+
+def plds_coreness(h, vertices, out, stream=None):
+    cnt = 0 if vertices is None else int(vertices.numel())
+    return _chk(lib().plds_coreness(h, _ptr(vertices), cnt, _ptr(out), _stream(stream)), "plds_coreness")
+
+
+def plds_levels(h, out, stream=None):
+    return _chk(lib().plds_levels(h, _ptr(out), _stream(stream)), "plds_levels")
+
+
+def plds_degrees(h, out, stream=None):
+    return _chk(lib().plds_degrees(h, _ptr(out), _stream(stream)), "plds_degrees")
+
+
+def plds_info(h):
+    i = plds_info_t()
+    _chk(lib().plds_info(h, ctypes.byref(i)), "plds_info")
+    return {f: getattr(i, f) for f, _ in plds_info_t._fields_}
+
+
+def plds_thresholds(h, G):
+    up = (ctypes.c_int32 * G)()
+    dn = (ctypes.c_int32 * G)()
+    pw = (ctypes.c_double * G)()
+    _chk(lib().plds_thresholds(h, ctypes.addressof(up), ctypes.addressof(dn), ctypes.addressof(pw)),
+         "plds_thresholds")
+    return list(up), list(dn), list(pw)
+
+
+def plds_stats(h):
+    s = plds_stats_t()
+    _chk(lib().plds_stats(h, ctypes.byref(s)), "plds_stats")
+    return {f: getattr(s, f) for f in STAT_FIELDS}
+
+
+def plds_dump_state(h, edges_out, levels_out, stream=None):
+    m = _I64()
+    cap = 0 if edges_out is None else int(edges_out.shape[0])
+    _chk(lib().plds_dump_state(h, _ptr(edges_out), cap, ctypes.byref(m), _ptr(levels_out), _stream(stream)),
+         "plds_dump_state")
+    return m.value
+
+
+def plds_load_state(h, edges, levels, stream=None, check=True):
+    p, c = _edges_arg(edges)
+    rc = lib().plds_load_state(h, p, c, _ptr(levels), _stream(stream))
+    return _chk(rc, "plds_load_state") if check else rc
+
+
+def plds_check(h, stream=None):
+    return lib().plds_check(h, _stream(stream))
+
+
+def plds_sync(h, stream=None):
+    return lib().plds_sync(h, _stream(stream))
+
+
+# ----------------------------------------------------------- convenience
+class PLDS:
+    """Owning wrapper: one handle on the current device."""
+
+    def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, edge_capacity_hint=0):
+        self.h = plds_create_ex(n, delta, lam, levels_per_group, edge_capacity_hint)
+        info = plds_info(self.h)
+        self.n, self.L, self.G, self.K, self.t = info["n"], info["L"], info["G"], info["K"], info["t"]
+
+    def close(self):
+        if getattr(self, "h", None):
+            plds_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, e):
+        import torch
+        if e is None:
+            return None
+        t = torch.as_tensor(e, dtype=torch.int32).reshape(-1, 2)
+        return t.to("cuda").contiguous()
+
+    def update(self, ins=None, dele=None, check=True):
+        return plds_update(self.h, self._dev(ins), self._dev(dele), check=check)
+
+    def insert(self, e, check=True):
+        return self.update(ins=e, check=check)
+
+    def delete(self, e, check=True):
+        return self.update(dele=e, check=check)
+
+    def levels(self):
+        import torch
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        plds_levels(self.h, out)
+        return out
+
+    def degrees(self):
+        import torch
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        plds_degrees(self.h, out)
+        return out
+
+    def coreness(self, vertices=None):
+        import torch
+        cnt = self.n if vertices is None else int(vertices.numel())
+        out = torch.empty(cnt, dtype=torch.float64, device="cuda")
+        plds_coreness(self.h, vertices, out)
+        return out
+
+    def stats(self):
+        return plds_stats(self.h)
+
+    def info(self):
+        return plds_info(self.h)
+
+    def thresholds(self):
+        return plds_thresholds(self.h, self.G)
+
+    def check(self):
+        return plds_check(self.h)
+
+    def dump(self):
+        import torch
+        m = self.info()["m"]
+        e = torch.empty((max(m, 1), 2), dtype=torch.int32, device="cuda")
+        lv = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        got = plds_dump_state(self.h, e, lv)
+        return e[:got], lv
+
+    def load(self, edges, levels, check=True):
+        import torch
+        lv = torch.as_tensor(levels, dtype=torch.int32).to("cuda").contiguous()
+        return plds_load_state(self.h, self._dev(edges), lv, check=check)
