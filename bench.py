@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Edge updates/s of the batch-dynamic PLDS on one MI355X.
+
+Workload: an R-MAT graph of scale 20 (2^20 vertices, 16*2^20 unique edges,
+a=0.57 b=0.19 c=0.19, seed 1), delta=0.4, lambda=3, built by 16 insertion
+batches (not timed).  One step applies three batches of 10^6 updates each
+through the C ABI: new uniform pairs (insertions), sampled existing edges
+(deletions), and a mixed batch of half each.  Batches are generated on the
+host and copied to HBM before the timed region; the value is the number of
+applied updates over the wall time of the K timed steps.
+
+Also reported: the insertion-scan kernel against the HBM roofline (its
+launches timed with HIP events inside the library, on the call's stream),
+parity of the GPU levels with the stored oracle trace of this stream, and the
+CPU oracle (one core) timed on a bounded sample of the same stream.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edge updates/sec (ins, del) at 1e6 batch"
+HBM_PEAK_GBS = 8000.0
+TRACE = os.path.join(ROOT, "tests", "golden", "rmat20_oracle_trace.json")
+LEVELS = os.path.join(ROOT, "tests", "golden", "rmat20_oracle_levels.npz")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def digest(levels):
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(levels, dtype=np.int32).tobytes()).hexdigest()[:32]
+
+
+def cpu_baseline(stream_edges, n, ins_batch, seconds_target):
+    """The oracle, single-threaded, from the stored post-build oracle state,
+    on a prefix of the first timed insertion batch and of a deletion batch."""
+    import numpy as np
+    import oracle as O
+    if not os.path.exists(LEVELS):
+        return None
+    lv = np.load(LEVELS)["levels"].astype(np.int32)
+    o = O.Oracle(n, 0.4, 3.0)
+    t = time.perf_counter()
+    rc = o.load_state(stream_edges, lv)
+    load_s = time.perf_counter() - t
+    if rc != 0:
+        log("oracle rejected the stored state", rc)
+        return None
+    size = 10000
+    done, spent, applied = 0, 0.0, 0
+    while spent < seconds_target and done < len(ins_batch):
+        chunk = ins_batch[done:done + size]
+        t = time.perf_counter()
+        assert o.insert(chunk) == 0
+        spent += time.perf_counter() - t
+        applied += o.stats()["applied_ins"]
+        done += len(chunk)
+        size = min(size * 2, 200000)
+    return {"value": applied / spent, "unit": "edge updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle from the stored post-build state of the same RMAT-20 stream (load {load_s:.1f}s, "
+                      f"not timed), first {done} pairs of the first timed 1e6 insertion batch applied in "
+                      f"growing chunks; {applied} updates in {spent:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=10 ** 6)
+    ap.add_argument("--kernel", default="ins_scan", help="kernel timed for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the structure is not sharded across GPUs",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2106_03824_amd import plds as P
+    from paper_2106_03824_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    scale, B = args.scale, args.batch
+    m0 = 16 * 2 ** scale
+    log("generating R-MAT", scale, m0)
+    st = W.RmatStream(scale, m0, seed=1, build_batches=16, cfg=2)
+    n = st.n
+    g = P.PLDS(n, 0.4, 3.0, 0, 2 * m0)
+    trace = json.load(open(TRACE)) if (scale == 20 and B == 10 ** 6 and os.path.exists(TRACE)) else None
+    parity = {"batches_checked": 0, "mismatches": 0}
+
+    def check(idx):
+        if trace is None or idx >= len(trace["batches"]):
+            return
+        ref = trace["batches"][idx]
+        lv = g.levels().cpu().numpy()
+        ok = digest(lv) == ref["sha"]
+        s = g.stats()
+        for k in ("sweeps_ins", "sweeps_del", "moves_up", "moves_down", "applied_ins", "applied_del"):
+            ok = ok and s[k] == ref[k]
+        parity["batches_checked"] += 1
+        parity["mismatches"] += 0 if ok else 1
+        if not ok:
+            log("PARITY MISMATCH at batch", idx, ref["kind"])
+
+    t_build = time.perf_counter()
+    idx = 0
+    build_updates = 0
+    for i, b in enumerate(st.build):
+        e = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+        P.plds_batch_insert(g.h, e)
+        build_updates += g.stats()["applied_ins"]
+        check(idx)
+        idx += 1
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t_build
+    log(f"build: {build_updates} edges in {t_build:.2f}s")
+
+    rounds = args.warmup + args.steps
+    batches = []
+    for r in range(rounds):
+        ins = st.insert_batch(B)
+        dele = st.delete_batch(B)
+        mi, md = st.mixed_batch(B)
+        batches.append([("ins", torch.from_numpy(ins).to(dev), None),
+                        ("del", None, torch.from_numpy(dele).to(dev)),
+                        ("mix", torch.from_numpy(mi).to(dev), torch.from_numpy(md).to(dev))])
+        if r == 0:
+            first_ins = ins
+    torch.cuda.synchronize()
+    log("batches ready")
+
+    per_kind = {"ins": [0, 0.0], "del": [0, 0.0], "mix": [0, 0.0]}
+    lat = []
+    tot = {"updates": 0, "alg_bytes": 0, "timed_ms": 0.0, "launches": 0, "sweeps": 0, "moves": 0}
+    for r in range(rounds):
+        timed = r >= args.warmup
+        if timed and r == args.warmup:
+            P.plds_set_timing(g.h, args.kernel)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        for kind, ins, dele in batches[r]:
+            tb = time.perf_counter()
+            P.plds_update(g.h, ins, dele)
+            dt = time.perf_counter() - tb
+            s = g.stats()
+            if timed:
+                u = s["applied_ins"] + s["applied_del"]
+                per_kind[kind][0] += u
+                per_kind[kind][1] += dt
+                lat.append(dt)
+                tot["updates"] += u
+                tot["alg_bytes"] += s["alg_bytes_up"]
+                tot["timed_ms"] += s["timed_ms"]
+                tot["launches"] += s["timed_launches"]
+                tot["sweeps"] += s["sweeps_ins"] + s["sweeps_del"]
+                tot["moves"] += s["moves_up"] + s["moves_down"]
+            check(idx)
+            idx += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.plds_set_timing(g.h, 0)
+    wall = t1 - t0
+    value = tot["updates"] / wall
+    log(f"timed: {tot['updates']} updates in {wall:.3f}s -> {value:.3e}/s")
+
+    roof = None
+    if tot["launches"] > 0 and tot["timed_ms"] > 0:
+        avg_ms = tot["timed_ms"] / tot["launches"]
+        per_launch = tot["alg_bytes"] / tot["launches"]
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_ins_scan",
+                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": tot["launches"],
+                "alg_bytes_per_launch": round(per_launch, 1)}
+    lat_ms = sorted(x * 1e3 for x in lat)
+    out = {
+        "metric": METRIC, "value": value, "unit": "edge updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"rmat{scale}-ef16-build16-then-ins/del/mix-{B}", "n": n, "m0": m0,
+                   "delta": 0.4, "lambda": 3.0, "batch": B, "step": "1 insertion + 1 deletion + 1 mixed batch"},
+        "rates": {k: (v[0] / v[1] if v[1] else None) for k, v in per_kind.items()},
+        "batch_latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1,
+                                                                              int(0.99 * len(lat_ms)))]},
+        "sweeps_per_step": tot["sweeps"] / args.steps, "moves_per_step": tot["moves"] / args.steps,
+        "build_updates_per_s": build_updates / t_build,
+        "roofline": roof,
+        "parity_vs_oracle_trace": parity if trace is not None else None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, first_ins, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def st_edges_after_build(st):
+    """Edge set right after the build (the stream tracks later batches)."""
+    import numpy as np
+    return np.concatenate(st.build)
+
+
+if __name__ == "__main__":
+    main()

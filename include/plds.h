@@ -66,7 +66,12 @@ typedef struct {
     int64_t viol_ins0;     /* Invariant-1 violators right after the insertions           */
     int64_t viol_del0;     /* Invariant-2 violators right after the deletions            */
     int64_t host_syncs;    /* host round trips made by the call                          */
-    int64_t reserved[4];
+    int64_t alg_bytes_up;  /* algorithmic bytes of the up-moves: 8 per up-neighbour read,
+                              8 per counter update of a neighbour one level up, 4 per
+                              level write (the paper's U[v] scan model)                 */
+    int64_t timed_launches;/* launches of the kernel selected by plds_set_timing         */
+    double timed_ms;       /* their summed duration in ms, from HIP events on `stream`   */
+    int64_t reserved;
 } plds_stats_t;
 
 /* Create an empty structure on the current HIP device: all n vertices at
@@ -119,6 +124,19 @@ int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *p
 
 /* Statistics of the last batch call. */
 int plds_stats(const plds_t *h, plds_stats_t *out);
+
+/* Per-step record of the last batch call, up to 2K rows of 4 int64 each,
+ * copied to host memory `out` [cap][4]; *rows receives the number written by
+ * the call.  Insertion step: (l, level the movers left, movers, cumulative
+ * slots scanned), the movers landing at l+1.  Deletion step: (-1-l, -1,
+ * movers, cumulative slots scanned), the movers landing at l. */
+int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
+
+/* Time one kernel of the level sweeps with HIP events recorded around each of
+ * its launches (0 = off, 1 = insertion scan, 2 = deletion scan,
+ * 3 = desire-level, 4 = insertion step preparation, 5 = insertion step
+ * finish).  Results appear in plds_stats (timed_launches, timed_ms). */
+int plds_set_timing(plds_t *h, int32_t kernel);
 
 /* Checkpoint.  plds_dump_state writes the edge list (u < v, unordered) to the
  * device buffer edges [cap][2] and the levels to device int32 [n]; *m_out

@@ -37,7 +37,12 @@ constexpr int32_t kChunk = 256;      // slab slots per work item of a sweep
 constexpr int32_t kMinCap = 8;       // smallest slab, slots
 constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels
 constexpr int kDlGrid = 1024;        // blocks of the desire-level kernel
+constexpr int kListGrid = 256;       // blocks of the per-mover list kernels
 constexpr int32_t kInf = INT32_MAX;
+// During an insertion step the movers carry this bit in level[] (set by the
+// step's preparation, cleared when they take their new level), so one gather
+// of a neighbour's level also tells whether it moves.
+constexpr int32_t kMoverBit = 1 << 30;
 
 // error bits latched on device
 constexpr int32_t kErrRange = 1;     // id out of range
@@ -54,6 +59,8 @@ struct Ctl {
     int32_t casc_n[2];    // cascade list sizes
     int32_t p_n[2];       // pending list sizes (deletion)
     int32_t n_chunks;     // work items of the current step
+    int32_t n_cls[4];     // movers per slab-size class
+    int32_t n_log;        // rows written to the step log in the current call
     int32_t n_rc;         // desire-level recomputations of the current step
     int32_t nm;           // running minimum of pending desire-levels
     int32_t blocks_done;  // last-block election
@@ -63,10 +70,12 @@ struct Ctl {
     int32_t n_grow;       // slabs to regrow
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
-    int32_t pad[2];
+    int32_t phys;         // level the movers of the current insertion step sit at
+    int32_t jump;         // 1 if they land at l+1 from below l (a multi-level step)
     int64_t grow_req;     // slots requested by regrowth
     int64_t pool_top;     // next free pool slot
     int64_t sweeps, moves, scanned, dl_calcs, top, m_out;
+    int64_t alg_U, alg_up1;   // up-neighbours read, neighbours one level up (insertion scans)
 };
 
 // Everything a kernel needs, passed by value.
@@ -91,8 +100,13 @@ struct Dev {
     // level loop scratch
     int32_t *cand, *sorted;           // [n]
     int32_t *lvl_cnt, *lvl_start, *next_nz;   // [K+1]
+    int32_t *occ;                     // [K+1] number of vertices at each level
+    int32_t *lvl_fill;                // [K+1] scatter cursors
     int32_t *casc0, *casc1;           // [n]
     int32_t *mv;                      // [n]
+    int32_t *cls[4];                  // [n] movers with slabs of <= 8, 16, 32, 64 slots
+    int64_t *steplog;                 // [2K][4] per-step record of the last call
+    int64_t *part;                    // [kSweepGrid][3] per-block statistics of a scan
     int64_t *chunks;                  // [chunk_cap]
     int64_t chunk_cap;
     int32_t *p0, *p1;                 // [n]
@@ -137,6 +151,97 @@ __device__ __forceinline__ void push(int32_t *list, int32_t *n, int32_t cap, int
     if (k < cap) list[k] = x;
     else latch(c, kErrLevel);
 }
+
+// Wavefront-aggregated append: every active lane calls it; lanes with `pred`
+// append x, with one atomic per wavefront.
+__device__ __forceinline__ void wpush(int32_t *list, int32_t *n, int32_t cap, bool pred, int32_t x, Ctl *c) {
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    int lane = __lane_id();
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(n, __popcll(mask));
+    base = __shfl(base, leader, kWave);
+    if (pred) {
+        int32_t k = base + __popcll(mask & ((1ull << lane) - 1));
+        if (k < cap) list[k] = x;
+        else latch(c, kErrLevel);
+    }
+}
+
+// Every active lane calls it; lanes with key >= 0 add one to arr[key].  Lanes
+// that share a key are served by one atomic; each gets a distinct slot
+// (the counter value before its own increment), -1 for key < 0.
+__device__ __forceinline__ int32_t wadd_key(int32_t *arr, int32_t key) {
+    int lane = __lane_id();
+    int32_t res = -1;
+    uint64_t todo = __ballot(key >= 0);
+    while (todo) {
+        int leader = __ffsll((unsigned long long)todo) - 1;
+        int32_t k = __shfl(key, leader, kWave);
+        uint64_t same = __ballot(key == k) & todo;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&arr[k], __popcll(same));
+        base = __shfl(base, leader, kWave);
+        if ((same >> lane) & 1) res = base + __popcll(same & ((1ull << lane) - 1));
+        todo &= ~same;
+    }
+    return res;
+}
+
+// exclusive prefix sum over the wavefront; *total receives the sum
+__device__ __forceinline__ int32_t wave_excl(int32_t x, int32_t *total) {
+    int lane = __lane_id();
+    int32_t v = x;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int32_t y = __shfl_up(v, o, kWave);
+        if (lane >= o) v += y;
+    }
+    *total = __shfl(v, kWave - 1, kWave);
+    return v - x;
+}
+
+// Block-wide exclusive prefix sum (every thread of the block calls it);
+// *total receives the block sum.  sh: LDS of at least kBlock/kWave+1 ints.
+__device__ __forceinline__ int32_t block_excl(int32_t x, int32_t *total, int32_t *sh) {
+    int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nwv = blockDim.x / kWave;
+    int32_t wt = 0;
+    int32_t off = wave_excl(x, &wt);
+    if (lane == 0) sh[wv] = wt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int i = 0; i < nwv; i++) {
+            int32_t t = sh[i];
+            sh[i] = acc;
+            acc += t;
+        }
+        sh[nwv] = acc;
+    }
+    __syncthreads();
+    int32_t r = sh[wv] + off;
+    *total = sh[nwv];
+    __syncthreads();
+    return r;
+}
+
+// Block-wide append with one atomic per block (every thread calls it).
+__device__ __forceinline__ void bpush(int32_t *list, int32_t *n, int32_t cap, bool pred, int32_t x, Ctl *c,
+                                      int32_t *sh) {
+    int32_t total = 0;
+    int32_t r = block_excl(pred ? 1 : 0, &total, sh);
+    if (total == 0) return;
+    if (threadIdx.x == 0) sh[kBlock / kWave + 1] = atomicAdd(n, total);
+    __syncthreads();
+    int32_t base = sh[kBlock / kWave + 1];
+    if (pred) {
+        if (base + r < cap) list[base + r] = x;
+        else latch(c, kErrLevel);
+    }
+    __syncthreads();
+}
+
 
 // ----------------------------------------------------------------- slabs
 __device__ bool slab_has(const int32_t *s, int32_t cap, int32_t key) {
@@ -259,33 +364,33 @@ __global__ void k_plan_growth(Dev d) {
     }
 }
 
-// allocate the new slabs from the pool and clear them
+// Allocate the new slabs from the pool, one atomic per wavefront.  All slabs
+// of one batch are carved from one contiguous region that the host has
+// already filled with empty slots.
 __global__ void k_grow_alloc(Dev d) {
     int32_t ng = d.ctl->n_grow;
-    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
-    int nw = gridDim.x * blockDim.x / kWave;
-    for (int g = wid; g < ng; g += nw) {
-        int32_t x = d.grow[g], nc = d.newcap[g];
+    int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
+    int stride = gridDim.x * blockDim.x;
+    for (int g0 = gid - lane; g0 < ng; g0 += stride) {
+        int g = g0 + lane;
+        int32_t nc = g < ng ? d.newcap[g] : 0;
+        int32_t total = 0;
+        int32_t off = wave_excl(nc, &total);
         int64_t base = 0;
-        if (lane == 0) {
-            base = (int64_t)atomicAdd((unsigned long long *)&d.ctl->pool_top, (unsigned long long)nc);
-            d.oldoff[g] = d.off[x];
-            d.oldcap[g] = d.cap[x];
-        }
+        if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)&d.ctl->pool_top, (unsigned long long)total);
         base = __shfl(base, 0, kWave);
-        if (base + nc > d.pool_cap) {
-            if (lane == 0) {
-                latch(d.ctl, kErrPool);
-                d.newcap[g] = 0;
-            }
+        if (g >= ng) continue;
+        int32_t x = d.grow[g];
+        d.oldoff[g] = d.off[x];
+        d.oldcap[g] = d.cap[x];
+        if (base + off + nc > d.pool_cap) {
+            latch(d.ctl, kErrPool);
+            d.newcap[g] = 0;
             continue;
         }
-        for (int32_t s = lane; s < nc; s += kWave) d.pool[base + s] = kEmpty;
-        if (lane == 0) {
-            d.off[x] = base;
-            d.cap[x] = nc;
-            d.fill[x] = 0;
-        }
+        d.off[x] = base + off;
+        d.cap[x] = nc;
+        d.fill[x] = 0;
     }
 }
 
@@ -350,54 +455,70 @@ __global__ void k_apply_del(Dev d) {
 __global__ void k_ins_seed(Dev d) {
     int32_t nt = d.ctl->n_touch;
     int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
-        int32_t x = d.touch[i];
-        d.addc[x] = 0;
-        int32_t lx = d.level[x];
-        if (d.up[x] > d.up_max[lx / d.L]) {
-            push(d.cand, &d.ctl->n_cand, d.n, x, d.ctl);
-            atomicAdd(&d.lvl_cnt[lx], 1);
+    int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
+    for (int i0 = gid - lane; i0 < nt; i0 += stride) {
+        int i = i0 + lane;
+        int32_t x = -1, key = -1;
+        if (i < nt) {
+            x = d.touch[i];
+            d.addc[x] = 0;
+            int32_t lx = d.level[x];
+            if (d.up[x] > d.up_max[lx / d.L]) key = lx;
         }
+        wpush(d.cand, &d.ctl->n_cand, d.n, key >= 0, x, d.ctl);
+        wadd_key(d.lvl_cnt, key);
     }
 }
 
-// single block: exclusive scan of the per-level counts, next non-empty level
+// One block of 1024 threads: exclusive scan of the per-level candidate
+// counts (bucket starts and scatter cursors) and, for every level, the next
+// level at or above it that has candidates.
 __global__ void k_level_scan(Dev d) {
-    __shared__ int32_t part[1024];
+    __shared__ int32_t part[1024], first[1024];
     int K = d.K, tid = threadIdx.x, nt = blockDim.x;
     int per = (K + nt - 1) / nt, lo = min(K, tid * per), hi = min(K, lo + per);
-    int32_t s = 0;
-    for (int i = lo; i < hi; i++) s += d.lvl_cnt[i];
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        int32_t acc = 0;
-        for (int t = 0; t < nt; t++) {
-            int32_t x = part[t];
-            part[t] = acc;
-            acc += x;
-        }
+    int32_t sum = 0, f = K;
+    for (int i = lo; i < hi; i++) {
+        int32_t x = d.lvl_cnt[i];
+        sum += x;
+        if (x > 0 && f == K) f = i;
     }
+    part[tid] = sum;
+    first[tid] = f;
     __syncthreads();
-    int32_t acc = part[tid];
+    for (int o = 1; o < nt; o <<= 1) {          // inclusive prefix sums, suffix minima
+        int32_t a = tid >= o ? part[tid - o] : 0;
+        int32_t b = tid + o < nt ? first[tid + o] : K;
+        __syncthreads();
+        part[tid] += a;
+        first[tid] = min(first[tid], b);
+        __syncthreads();
+    }
+    int32_t acc = part[tid] - sum;
+    int32_t nz = tid + 1 < nt ? first[tid + 1] : K;
     for (int i = lo; i < hi; i++) {
         d.lvl_start[i] = acc;
+        d.lvl_fill[i] = acc;
         acc += d.lvl_cnt[i];
     }
-    if (tid == nt - 1) d.lvl_start[K] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        int32_t nz = K;
+    for (int i = hi - 1; i >= lo; i--) {
+        if (d.lvl_cnt[i] > 0) nz = i;
+        d.next_nz[i] = nz;
+    }
+    if (tid == nt - 1) {
+        d.lvl_start[K] = part[nt - 1];
         d.next_nz[K] = K;
-        for (int i = K - 1; i >= 0; i--) {
-            if (d.lvl_cnt[i] > 0) nz = i;
-            d.next_nz[i] = nz;
-        }
-        d.ctl->l = nz;
-        d.ctl->done = nz >= K;
+    }
+    if (tid == 0) {
+        int32_t z = first[0];
+        d.ctl->l = z;
+        d.ctl->phys = z;
+        d.ctl->jump = 0;
+        d.ctl->done = z >= K;
         d.ctl->cur = 0;
         d.ctl->casc_n[0] = d.ctl->casc_n[1] = 0;
         d.ctl->n_chunks = 0;
+        d.ctl->n_cls[0] = d.ctl->n_cls[1] = d.ctl->n_cls[2] = d.ctl->n_cls[3] = 0;
         d.ctl->blocks_done = 0;
     }
 }
@@ -405,137 +526,295 @@ __global__ void k_level_scan(Dev d) {
 __global__ void k_level_scatter(Dev d) {
     int32_t nc = d.ctl->n_cand;
     int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
-        int32_t x = d.cand[i];
-        int32_t lx = d.level[x];
-        int32_t pos = d.lvl_start[lx] + atomicSub(&d.lvl_cnt[lx], 1) - 1;
-        d.sorted[pos] = x;
+    int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
+    for (int i0 = gid - lane; i0 < nc; i0 += stride) {
+        int i = i0 + lane;
+        int32_t x = i < nc ? d.cand[i] : -1;
+        int32_t pos = wadd_key(d.lvl_fill, x >= 0 ? d.level[x] : -1);
+        if (x >= 0) d.sorted[pos] = x;
     }
 }
 
-__device__ __forceinline__ void add_chunks(Dev &d, int32_t v) {
-    int32_t c = d.cap[v];
-    int32_t nch = (c + kChunk - 1) / kChunk;
-    if (nch == 0) return;
-    int32_t base = atomicAdd(&d.ctl->n_chunks, nch);
-    if (base + nch > d.chunk_cap) {
-        latch(d.ctl, kErrPool);
+// Work items of a step: kChunk-slot pieces of the movers' slabs, appended
+// with one atomic per block.  Every thread of the block calls it; threads
+// with v < 0 add nothing.
+__device__ __forceinline__ void add_chunks_b(Dev &d, int32_t v, int32_t *sh) {
+    int32_t nch = v >= 0 ? (d.cap[v] + kChunk - 1) / kChunk : 0;
+    int32_t total = 0;
+    int32_t off = block_excl(nch, &total, sh);
+    if (total == 0) return;
+    if (threadIdx.x == 0) sh[kBlock / kWave + 1] = atomicAdd(&d.ctl->n_chunks, total);
+    __syncthreads();
+    int32_t base = sh[kBlock / kWave + 1];
+    __syncthreads();
+    if (base + total > d.chunk_cap) {
+        if (threadIdx.x == 0) latch(d.ctl, kErrPool);
         return;
     }
-    for (int32_t k = 0; k < nch; k++) d.chunks[base + k] = ((int64_t)v << 32) | (uint32_t)k;
+    for (int32_t k = 0; k < nch; k++) d.chunks[base + off + k] = ((int64_t)v << 32) | (uint32_t)k;
 }
 
-// Step of Algorithm 2 at level l, part 1: the movers S_l are the sorted
-// candidates of level l and the cascade (vertices marked at level l).
+// Work items of a step: kChunk-slot pieces of the movers' slabs, appended
+// with one atomic per wavefront.  All lanes of the wave call it; lanes with
+// v < 0 add nothing.
+__device__ __forceinline__ void add_chunks_w(Dev &d, int32_t v) {
+    int32_t nch = v >= 0 ? (d.cap[v] + kChunk - 1) / kChunk : 0;
+    int32_t total = 0;
+    int32_t off = wave_excl(nch, &total);
+    if (total == 0) return;
+    int lane = __lane_id();
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(&d.ctl->n_chunks, total);
+    base = __shfl(base, 0, kWave);
+    if (base + total > d.chunk_cap) {
+        if (lane == 0) latch(d.ctl, kErrPool);
+        return;
+    }
+    for (int32_t k = 0; k < nch; k++) d.chunks[base + off + k] = ((int64_t)v << 32) | (uint32_t)k;
+}
+
+// Step of Algorithm 2, part 1.  The step moves the set S of every vertex of
+// level `phys` that violates Invariant 1 (the sorted candidates of that
+// level plus the vertices marked there) up to level l+1.  Normally
+// phys == l; phys < l is a multi-level step (see k_ins_next).
 __global__ void k_ins_prep(Dev d) {
     if (d.ctl->done) return;
-    int32_t l = d.ctl->l, cur = d.ctl->cur;
+    int32_t l = d.ctl->l, phys = d.ctl->phys, cur = d.ctl->cur;
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < 0 || l + 1 >= d.K) {
+    if (phys < 0 || phys > l || l + 1 >= d.K) {
         if (gid == 0) latch(d.ctl, kErrLevel);
         return;
     }
-    int32_t a0 = d.lvl_start[l], a1 = d.lvl_start[l + 1];
-    int32_t nA = a1 - a0, nB = min(d.ctl->casc_n[cur], d.n);
+    int32_t a0 = d.lvl_start[phys], a1 = d.lvl_start[phys + 1];
+    int32_t nA = a1 - a0, nB = d.ctl->casc_n[cur];
     const int32_t *casc = cur ? d.casc1 : d.casc0;
-    int stride = gridDim.x * blockDim.x;
     if (nA + nB > d.n) {
         if (gid == 0) latch(d.ctl, kErrLevel);
         return;
     }
-    for (int i = gid; i < nA + nB; i += stride) {
-        int32_t v = i < nA ? d.sorted[a0 + i] : casc[i - nA];
-        d.mv[i] = v;
-        add_chunks(d, v);
+    __shared__ int32_t sh[kBlock / kWave + 2];
+    int stride = gridDim.x * blockDim.x;
+    for (int i0 = blockIdx.x * blockDim.x; i0 < nA + nB; i0 += stride) {
+        int i = i0 + threadIdx.x;
+        int32_t v = -1, cl = -1;
+        if (i < nA + nB) {
+            v = i < nA ? d.sorted[a0 + i] : casc[i - nA];
+            d.mv[i] = v;
+            d.level[v] = phys | kMoverBit;
+            int32_t cap = d.cap[v];
+            cl = cap <= 8 ? 0 : cap <= 16 ? 1 : cap <= 32 ? 2 : cap <= 64 ? 3 : 4;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) bpush(d.cls[k], &d.ctl->n_cls[k], d.n, cl == k, v, d.ctl, sh);
+        add_chunks_b(d, cl == 4 ? v : -1, sh);
     }
     if (gid == 0) d.ctl->n_mv = nA + nB;
 }
 
 // Part 2: every mover v scans its slab.  Neighbour w at level l stays iff it
-// does not violate Invariant 1 (its up-degree is untouched in this step);
-// w at l+1 gains v as up-neighbour and is marked if that makes it exceed the
-// cap of level l+1; w at l+2 gains v as up*-neighbour.
+// is not itself a mover (every violator of level l moves);
+// w at l+1 gains v as up-neighbour (and, in a multi-level step, as
+// up*-neighbour) and is marked if that makes it exceed the cap of level l+1;
+// w at l+2 gains v as up*-neighbour.
+// Work items: movers with slabs of at most 8/16/32/64 slots are served by
+// lane groups of that width (8/4/2/1 movers per wavefront); larger slabs are
+// cut into kChunk-slot pieces served by a whole wavefront each.
 __global__ void k_ins_scan(Dev d) {
     if (d.ctl->done) return;
-    int32_t l = d.ctl->l, nxt = d.ctl->cur ^ 1, nch = d.ctl->n_chunks;
+    int32_t l = d.ctl->l, nxt = d.ctl->cur ^ 1, jump = d.ctl->jump;
     int32_t *casc = nxt ? d.casc1 : d.casc0;
-    int32_t ub0 = d.up_max[l / d.L], ub1 = d.up_max[(l + 1) / d.L];
+    int32_t ub1 = d.up_max[(l + 1) / d.L];
     int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     int nw = gridDim.x * blockDim.x / kWave;
-    int32_t scanned = 0;
-    for (int c = wid; c < nch; c += nw) {
-        int64_t desc = d.chunks[c];
-        int32_t v = (int32_t)(desc >> 32), k = (int32_t)(desc & 0xffffffff);
-        int32_t cap = d.cap[v];
-        const int32_t *s = d.pool + d.off[v];
-        int32_t lo = k * kChunk, hi = min(lo + kChunk, cap);
+    int32_t items[5];
+    items[0] = (d.ctl->n_cls[0] + 7) / 8;
+    items[1] = (d.ctl->n_cls[1] + 3) / 4;
+    items[2] = (d.ctl->n_cls[2] + 1) / 2;
+    items[3] = d.ctl->n_cls[3];
+    items[4] = d.ctl->n_chunks;
+    int32_t total = items[0] + items[1] + items[2] + items[3] + items[4];
+    int32_t scanned = 0, nU = 0, n1 = 0;
+    for (int t = wid; t < total; t += nw) {
+        int cl = 0;
+        int32_t tl = t;
+        while (cl < 4 && tl >= items[cl]) tl -= items[cl++];
+        int W = cl == 4 ? kWave : (8 << cl);
+        int grp = lane / W, q = lane % W;
+        int32_t v = -1, lo = 0, hi = 0;
+        if (cl < 4) {
+            int32_t j = tl * (kWave / W) + grp;
+            if (j < d.ctl->n_cls[cl]) {
+                v = d.cls[cl][j];
+                hi = d.cap[v];
+            }
+        } else {
+            int64_t desc = d.chunks[tl];
+            v = (int32_t)(desc >> 32);
+            lo = (int32_t)(desc & 0xffffffff) * kChunk;
+            hi = min(lo + kChunk, d.cap[v]);
+        }
+        const int32_t *s = v >= 0 ? d.pool + d.off[v] : d.pool;
         int32_t stay = 0;
-        for (int32_t e = lo + lane; e < hi; e += kWave) {
-            int32_t w = s[e];
-            if (w < 0) continue;
-            int32_t lw = d.level[w];
+        int iters = cl == 4 ? kChunk / kWave : 1;
+        for (int it = 0; it < iters; it++) {
+            int32_t e = lo + it * W + q;
+            int32_t w = v >= 0 && e < hi ? s[e] : -1;
+            int32_t raw = w >= 0 ? d.level[w] : -1;
+            bool cross = false;
+            // a fellow mover stays in v's up-set; it is neither counted nor updated
+            int32_t lw = (raw & kMoverBit) ? -1 : raw;
+            nU += lw >= l || (raw >= 0 && (raw & kMoverBit));
             if (lw == l) {
-                stay += d.up[w] <= ub0;
+                stay++;
             } else if (lw == l + 1) {
+                n1++;
                 int32_t old = atomicAdd(&d.up[w], 1);
-                if (old == ub1) push(casc, &d.ctl->casc_n[nxt], d.n, w, d.ctl);
+                cross = old == ub1;
+                if (jump) atomicAdd(&d.ups[w], 1);
             } else if (lw == l + 2) {
                 atomicAdd(&d.ups[w], 1);
             }
+            wpush(casc, &d.ctl->casc_n[nxt], d.n, cross, w, d.ctl);
         }
-        scanned += hi - lo;
-        stay = wave_sum(stay);
-        if (lane == 0 && stay) atomicAdd(&d.stay[v], stay);
+        if (v >= 0) scanned += (q == 0) ? hi - lo : 0;
+        for (int o = W / 2; o > 0; o >>= 1) stay += __shfl_xor(stay, o, kWave);
+        if (q == 0 && v >= 0 && stay) atomicAdd(&d.stay[v], stay);
     }
-    if (lane == 0 && scanned) atomicAdd((unsigned long long *)&d.ctl->scanned, (unsigned long long)scanned);
+    // per-block statistics, summed by the step's decision kernel
+    __shared__ int32_t red[3][kBlock / kWave];
+    nU = wave_sum(nU);
+    n1 = wave_sum(n1);
+    scanned = wave_sum(scanned);
+    if (lane == 0) {
+        red[0][threadIdx.x / kWave] = scanned;
+        red[1][threadIdx.x / kWave] = nU;
+        red[2][threadIdx.x / kWave] = n1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int64_t t = 0;
+        for (int i = 0; i < kBlock / kWave; i++) t += red[threadIdx.x][i];
+        d.part[3 * blockIdx.x + threadIdx.x] = t;
+    }
 }
 
 // Part 3: movers take level l+1 with up*(v) = old up(v) and up(v) = old up(v)
 // minus the neighbours that stayed at l; a mover still above the cap of l+1
-// stays marked.  The last block picks the next level.
+// stays marked.
 __global__ void k_ins_fin(Dev d) {
     if (d.ctl->done) return;
-    int32_t l = d.ctl->l, cur = d.ctl->cur, nxt = cur ^ 1, nmv = d.ctl->n_mv;
+    int32_t l = d.ctl->l, nxt = d.ctl->cur ^ 1, nmv = d.ctl->n_mv;
     int32_t *casc = nxt ? d.casc1 : d.casc0;
     int32_t ub1 = d.up_max[(l + 1) / d.L];
+    __shared__ int32_t sh[kBlock / kWave + 2];
     int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmv; i += stride) {
-        int32_t v = d.mv[i];
-        d.level[v] = l + 1;
-        int32_t u = d.up[v];
-        d.ups[v] = u;
-        u -= d.stay[v];
-        d.stay[v] = 0;
-        d.up[v] = u;
-        if (u > ub1) push(casc, &d.ctl->casc_n[nxt], d.n, v, d.ctl);
+    for (int i0 = blockIdx.x * blockDim.x; i0 < nmv; i0 += stride) {
+        int i = i0 + threadIdx.x;
+        bool viol = false;
+        int32_t v = -1;
+        if (i < nmv) {
+            v = d.mv[i];
+            d.level[v] = l + 1;
+            int32_t u = d.up[v];
+            d.ups[v] = u;
+            u -= d.stay[v];
+            d.stay[v] = 0;
+            d.up[v] = u;
+            viol = u > ub1;
+        }
+        bpush(casc, &d.ctl->casc_n[nxt], d.n, viol, v, d.ctl, sh);
     }
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&d.ctl->blocks_done, 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        Ctl *c = d.ctl;
-        c->sweeps += 1;
-        c->moves += nmv;
+}
+
+// Part 4 (one block): account the step and choose the next one.  The next
+// movers sit at level z0: the marked vertices at l+1, else the next level with
+// sorted candidates.  If they are every vertex of z0 and the levels above z0
+// are empty up to level y (bounded by the first level of the next group),
+// they climb in lockstep: at each of those levels their up-degree counts the
+// same set (themselves and the vertices at or above y) against the same cap,
+// and no other vertex is at or next to those levels.  The next step then
+// moves them from z0 to y in one go, with the step's level set to y-1 and the
+// moves and sweeps of the skipped levels counted.
+__global__ void k_ins_next(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    __shared__ int32_t sh_z0, sh_all, sh_e;
+    __shared__ int64_t ps[3][kBlock];
+    int tid = threadIdx.x;
+    int32_t l = c->l, phys = c->phys, nmv = c->n_mv, cur = c->cur, nxt = cur ^ 1;
+    {
+        int64_t a = 0, b = 0, e = 0;
+        for (int i = tid; i < kSweepGrid; i += blockDim.x) {
+            a += d.part[3 * i];
+            b += d.part[3 * i + 1];
+            e += d.part[3 * i + 2];
+        }
+        ps[0][tid] = a;
+        ps[1][tid] = b;
+        ps[2][tid] = e;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if (tid < o)
+                for (int k = 0; k < 3; k++) ps[k][tid] += ps[k][tid + o];
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        c->scanned += ps[0][0];
+        c->alg_U += ps[1][0];
+        c->alg_up1 += ps[2][0];
+        int64_t steps = l + 1 - phys;
+        c->sweeps += steps;
+        c->moves += (int64_t)nmv * steps;
+        d.occ[phys] -= nmv;
+        d.occ[l + 1] += nmv;
         c->top = max(c->top, (int64_t)(l + 1));
-        int32_t cn = atomicAdd(&c->casc_n[nxt], 0);
+        if (c->n_log < 2 * d.K) {
+            int64_t *row = d.steplog + 4 * c->n_log++;
+            row[0] = l;
+            row[1] = phys;
+            row[2] = nmv;
+            row[3] = c->scanned;
+        }
+        int32_t cn = c->casc_n[nxt];
         c->casc_n[cur] = 0;
         c->cur = nxt;
         c->n_chunks = 0;
+        c->n_cls[0] = c->n_cls[1] = c->n_cls[2] = c->n_cls[3] = 0;
         c->n_mv = 0;
-        c->blocks_done = 0;
-        if (cn > 0) {
-            if (l + 2 >= d.K) {     // no vertex may pass the first level of the top group
-                latch(c, kErrLevel);
-                c->done = 1;
-            }
-            c->l = l + 1;
+        c->jump = 0;
+        int32_t z0 = cn > 0 ? l + 1 : (l + 1 < d.K ? d.next_nz[l + 1] : d.K);
+        sh_z0 = z0;
+        sh_all = 0;
+        sh_e = INT32_MAX;
+        if (z0 < d.K) {
+            int32_t ns = d.lvl_start[z0 + 1] - d.lvl_start[z0];
+            int32_t movers = (z0 == l + 1 ? cn : 0) + ns;
+            sh_all = d.occ[z0] == movers;
+        }
+        if (cn > 0 && l + 2 >= d.K) latch(c, kErrLevel);
+    }
+    __syncthreads();
+    int32_t z0 = sh_z0;
+    if (z0 >= d.K) {
+        if (tid == 0) c->done = 1;
+        return;
+    }
+    int32_t limit = min((z0 / d.L + 1) * d.L, d.K - 1);   // first level of the next group
+    if (sh_all && z0 + 2 <= limit) {
+        for (int32_t z = z0 + 1 + tid; z < limit; z += blockDim.x)
+            if (d.occ[z] > 0) atomicMin(&sh_e, z);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int32_t y = min(sh_e, limit);
+        if (sh_all && y >= z0 + 2) {
+            c->l = y - 1;
+            c->phys = z0;
+            c->jump = 1;
         } else {
-            int32_t nl = l + 1 < d.K ? d.next_nz[l + 1] : d.K;
-            if (nl >= d.K) c->done = 1;
-            else c->l = nl;
+            c->l = z0;
+            c->phys = z0;
         }
     }
 }
@@ -620,31 +899,35 @@ __global__ void k_dl(Dev d, int mode) {
         }
     }
     if (threadIdx.x == 0 && ncalc) atomicAdd((unsigned long long *)&c->dl_calcs, (unsigned long long)ncalc);
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&c->blocks_done, 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        c->blocks_done = 0;
-        if (mode == 1 && !skip) {
-            c->sweeps += 1;
-            c->moves += c->n_mv;
-            c->p_n[cur] = 0;
-            c->cur = cur ^ 1;
-            c->n_mv = 0;
-            c->n_chunks = 0;
-            c->n_rc = 0;
-            c->step_id += 1;
+}
+
+// One thread: close a deletion step (mode 1) or the seeding (mode 0), and
+// set the next level to the smallest pending desire-level.
+__global__ void k_del_next(Dev d, int mode) {
+    Ctl *c = d.ctl;
+    if (mode == 1 && c->done) return;
+    if (mode == 1) {
+        int32_t cur = c->cur;
+        if (c->n_log < 2 * d.K) {
+            int64_t *row = d.steplog + 4 * c->n_log++;
+            row[0] = -1 - c->l;
+            row[1] = -1;
+            row[2] = c->n_mv;
+            row[3] = c->scanned;
         }
-        if (!skip) {
-            int32_t nm = atomicAdd(&c->nm, 0);
-            c->nm = kInf;
-            if (nm == kInf) c->done = 1;
-            else c->l = nm;
-        }
+        c->sweeps += 1;
+        c->moves += c->n_mv;
+        c->p_n[cur] = 0;
+        c->cur = cur ^ 1;
+        c->n_mv = 0;
+        c->n_chunks = 0;
+        c->n_rc = 0;
+        c->step_id += 1;
     }
+    int32_t nm = c->nm;
+    c->nm = kInf;
+    if (nm == kInf) c->done = 1;
+    else c->l = nm;
 }
 
 // Step of Algorithm 3 at level l, part 1: the movers are the pending
@@ -655,17 +938,23 @@ __global__ void k_del_select(Dev d) {
     int32_t l = c->l, cur = c->cur, nxt = cur ^ 1, np = c->p_n[cur];
     const int32_t *P = cur ? d.p1 : d.p0;
     int32_t *Q = nxt ? d.p1 : d.p0;
+    int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
     int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += stride) {
-        int32_t v = P[i], dv = d.dl[v];
-        if (dv == l) {
-            push(d.mv, &c->n_mv, d.n, v, c);
-            add_chunks(d, v);
-        } else {
-            if (dv < l) latch(c, kErrOrder);
-            push(Q, &c->p_n[nxt], d.n, v, c);
-            atomicMin(&c->nm, dv);
+    for (int i0 = gid - lane; i0 < np; i0 += stride) {
+        int i = i0 + lane;
+        int32_t v = -1, dv = -1;
+        if (i < np) {
+            v = P[i];
+            dv = d.dl[v];
+            if (dv != l) {
+                if (dv < l) latch(c, kErrOrder);
+                atomicMin(&c->nm, dv);
+            }
         }
+        bool mover = i < np && dv == l;
+        wpush(d.mv, &c->n_mv, d.n, mover, v, c);
+        wpush(Q, &c->p_n[nxt], d.n, i < np && dv != l, v, c);
+        add_chunks_w(d, mover ? v : -1);
     }
 }
 
@@ -689,25 +978,29 @@ __global__ void k_del_scan(Dev d) {
         const int32_t *s = d.pool + d.off[v];
         int32_t lo = k * kChunk, hi = min(lo + kChunk, cap);
         int32_t cu = 0, cus = 0;
-        for (int32_t e = lo + lane; e < hi; e += kWave) {
-            int32_t w = s[e];
-            if (w < 0) continue;
-            int32_t dw = d.dl[w];
-            if (dw == l) {
-                cu++;
-                cus++;
-                continue;
+        for (int32_t e0 = lo; e0 < hi; e0 += kWave) {
+            int32_t e = e0 + lane;
+            int32_t w = e < hi ? s[e] : -1;
+            bool fresh = false;
+            if (w >= 0) {
+                int32_t dw = d.dl[w];
+                if (dw == l) {
+                    cu++;
+                    cus++;
+                } else {
+                    int32_t lw = d.level[w];
+                    cu += lw >= l;
+                    cus += lw >= l - 1;
+                    bool again = dw >= 0;
+                    if (lw > l && lw <= pv) atomicSub(&d.up[w], 1);
+                    if (lw > l + 1 && lw <= pv + 1) {
+                        int32_t old = atomicSub(&d.ups[w], 1);
+                        if (old == d.dn_min[(lw - 1) / d.L]) again = true;
+                    }
+                    fresh = again && atomicExch(&d.rcstamp[w], sid) != sid;
+                }
             }
-            int32_t lw = d.level[w];
-            cu += lw >= l;
-            cus += lw >= l - 1;
-            bool again = dw >= 0;
-            if (lw > l && lw <= pv) atomicSub(&d.up[w], 1);
-            if (lw > l + 1 && lw <= pv + 1) {
-                int32_t old = atomicSub(&d.ups[w], 1);
-                if (old == d.dn_min[(lw - 1) / d.L]) again = true;
-            }
-            if (again && atomicExch(&d.rcstamp[w], sid) != sid) push(d.rc, &c->n_rc, d.n, w, c);
+            wpush(d.rc, &c->n_rc, d.n, fresh, w, c);
         }
         scanned += hi - lo;
         cu = wave_sum(cu);
@@ -729,6 +1022,8 @@ __global__ void k_del_fin(Dev d) {
     int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmv; i += stride) {
         int32_t v = d.mv[i];
+        atomicSub(&d.occ[d.level[v]], 1);
+        atomicAdd(&d.occ[l], 1);
         d.level[v] = l;
         d.up[v] = d.stay[v];
         d.ups[v] = d.cnt2[v];
@@ -806,6 +1101,21 @@ __global__ void k_dump_edges(Dev d, int32_t *out, int64_t cap_out) {
             }
         }
     }
+}
+
+// number of vertices per level
+__global__ void k_count_levels(Dev d, int32_t *occ) {
+    int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) {
+        int32_t x = d.level[v];
+        if (x >= 0 && x < d.K) atomicAdd(&occ[x], 1);
+    }
+}
+
+__global__ void k_compare(const int32_t *a, const int32_t *b, int32_t cnt, int32_t *bad) {
+    int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+        if (a[i] != b[i]) atomicAdd(bad, 1);
 }
 
 __global__ void k_clear_touch(Dev d) {
@@ -896,6 +1206,10 @@ struct plds {
     plds_stats_t stats{};
     int32_t latched = 0;
     bool broken = false;
+    // optional event timing of one sweep kernel
+    int32_t timed_kind = 0;
+    std::vector<hipEvent_t> ev;   // pairs (start, stop)
+    int32_t ev_used = 0;
 };
 
 namespace {
@@ -966,19 +1280,44 @@ void free_all(plds *h) {
     dfree(d.pool), dfree(d.stay), dfree(d.cnt2), dfree(d.addc), dfree(d.dl), dfree(d.rcstamp), dfree(d.ctl);
     dfree(d.hset), dfree(d.valid), dfree(d.touch), dfree(d.grow), dfree(d.newcap), dfree(d.oldoff),
         dfree(d.oldcap);
-    dfree(d.cand), dfree(d.sorted), dfree(d.lvl_cnt), dfree(d.lvl_start), dfree(d.next_nz);
+    dfree(d.cand), dfree(d.sorted), dfree(d.lvl_cnt), dfree(d.lvl_start), dfree(d.next_nz), dfree(d.occ), dfree(d.lvl_fill), dfree(d.steplog), dfree(d.part);
+    for (int k = 0; k < 4; k++) dfree(d.cls[k]);
     dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
     dfree(h->tile), dfree(h->newoff), dfree(h->bad);
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    h->ev.clear();
     if (h->h_ctl) (void)hipHostFree(h->h_ctl);
     h->h_ctl = nullptr;
 }
 
 hipStream_t S(void *s) { return (hipStream_t)s; }
 
+constexpr int kEvPairs = 512;
+
+// record the start event of a timed launch of `kind` (no-op otherwise)
+inline void tstart(plds *h, int kind, hipStream_t s) {
+    if (h->timed_kind != kind || h->ev_used >= kEvPairs) return;
+    (void)hipEventRecord(h->ev[2 * h->ev_used], s);
+}
+inline void tstop(plds *h, int kind, hipStream_t s) {
+    if (h->timed_kind != kind || h->ev_used >= kEvPairs) return;
+    (void)hipEventRecord(h->ev[2 * h->ev_used + 1], s);
+    h->ev_used++;
+}
+
 int sync_ctl(plds *h, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(h->h_ctl, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     h->stats.host_syncs++;
+    for (int i = 0; i < h->ev_used; i++) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
+            h->stats.timed_ms += ms;
+            h->stats.timed_launches++;
+        }
+    }
+    h->ev_used = 0;
     return PLDS_OK;
 }
 
@@ -1065,9 +1404,11 @@ int ctl_reset_batch(plds *h, hipStream_t s) {
     c->casc_n[0] = c->casc_n[1] = 0;
     c->p_n[0] = c->p_n[1] = 0;
     c->n_chunks = c->n_rc = 0;
+    c->n_cls[0] = c->n_cls[1] = c->n_cls[2] = c->n_cls[3] = 0;
     c->nm = kInf;
     c->blocks_done = 0;
     c->sweeps = c->moves = c->scanned = c->dl_calcs = 0;
+    c->alg_U = c->alg_up1 = 0;
     c->top = 0;
     c->m_out = 0;
     c->pool_top = h->pool_top;
@@ -1111,8 +1452,8 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
             int64_t req = h->h_ctl->grow_req;
             rc = ensure_pool(h, s, req);
             if (rc) return rc;
-            hipLaunchKernelGGL(k_grow_alloc, dim3(grid_for((int64_t)h->h_ctl->n_grow * kWave)), dim3(kBlock), 0,
-                               s, d);
+            HIPCHK(hipMemsetAsync(d.pool + h->pool_top, 0xff, (size_t)req * sizeof(int32_t), s));
+            hipLaunchKernelGGL(k_grow_alloc, dim3(grid_for(h->h_ctl->n_grow)), dim3(kBlock), 0, s, d);
             hipLaunchKernelGGL(k_grow_move, dim3(grid_for((int64_t)h->h_ctl->n_grow * kWave)), dim3(kBlock), 0,
                                s, d);
             h->pool_top += req;
@@ -1148,9 +1489,16 @@ int insertion_sweep(plds *h, hipStream_t s) {
         }
         steps += run;
         for (int i = 0; i < run; i++) {
-            hipLaunchKernelGGL(k_ins_prep, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+            tstart(h, 4, s);
+            hipLaunchKernelGGL(k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d);
+            tstop(h, 4, s);
+            tstart(h, 1, s);
             hipLaunchKernelGGL(k_ins_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
-            hipLaunchKernelGGL(k_ins_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+            tstop(h, 1, s);
+            tstart(h, 5, s);
+            hipLaunchKernelGGL(k_ins_fin, dim3(kListGrid), dim3(kBlock), 0, s, d);
+            tstop(h, 5, s);
+            hipLaunchKernelGGL(k_ins_next, dim3(1), dim3(kBlock), 0, s, d);
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
@@ -1160,6 +1508,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
     Ctl *c = h->h_ctl;
     h->stats.sweeps_ins += c->sweeps;
     h->stats.moves_up += c->moves;
+    h->stats.alg_bytes_up += 8 * (c->alg_U + c->alg_up1) + 4 * c->moves;
     h->stats.slots_scanned += c->scanned;
     h->stats.top_level = std::max(h->stats.top_level, c->top);
     return check_err(h);
@@ -1171,7 +1520,10 @@ int deletion_sweep(plds *h, hipStream_t s) {
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void *)k_dl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return PLDS_EINVAL;
+    tstart(h, 3, s);
     hipLaunchKernelGGL(k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 0);
+    tstop(h, 3, s);
+    hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 0);
     HIPCHK(hipGetLastError());
     int rc = sync_ctl(h, s);
     if (rc) return rc;
@@ -1186,9 +1538,14 @@ int deletion_sweep(plds *h, hipStream_t s) {
         steps += run;
         for (int i = 0; i < run; i++) {
             hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+            tstart(h, 2, s);
             hipLaunchKernelGGL(k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
+            tstop(h, 2, s);
             hipLaunchKernelGGL(k_del_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+            tstart(h, 3, s);
             hipLaunchKernelGGL(k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 1);
+            tstop(h, 3, s);
+            hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 1);
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
@@ -1262,7 +1619,10 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
           dalloc(&d.oldcap, n);
     rc |= dalloc(&d.cand, n) | dalloc(&d.sorted, n);
     rc |= dalloc(&d.lvl_cnt, h->K + 1) | dalloc(&d.lvl_start, h->K + 1) | dalloc(&d.next_nz, h->K + 1);
+    rc |= dalloc(&d.occ, h->K + 1) | dalloc(&d.lvl_fill, h->K + 1);
+    rc |= dalloc(&d.steplog, 8 * (int64_t)h->K) | dalloc(&d.part, 3 * kSweepGrid);
     rc |= dalloc(&d.casc0, n) | dalloc(&d.casc1, n) | dalloc(&d.mv, n);
+    for (int k = 0; k < 4; k++) rc |= dalloc(&d.cls[k], n);
     rc |= dalloc(&d.p0, n) | dalloc(&d.p1, n) | dalloc(&d.rc, n);
     rc |= dalloc(&h->newoff, n) | dalloc(&h->bad, 8);
     int64_t pool = std::max<int64_t>(1 << 20, 12 * n + (edge_capacity_hint * 2 * 5) / 3);
@@ -1280,6 +1640,7 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
     memset(h->h_ctl, 0, sizeof(Ctl));
     h->h_ctl->nm = kInf;
     hipStream_t s = 0;
+    int32_t n32 = (int32_t)n;
     bool ok = hipMemcpy(d.up_max, h->h_up_max.data(), (h->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice) ==
                   hipSuccess &&
               hipMemcpy(d.dn_min, h->h_dn_min.data(), (h->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice) ==
@@ -1297,6 +1658,8 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
               hipMemsetAsync(d.addc, 0, n * sizeof(int32_t), s) == hipSuccess &&
               hipMemsetAsync(d.dl, 0xff, n * sizeof(int32_t), s) == hipSuccess &&
               hipMemsetAsync(d.rcstamp, 0xff, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.occ, 0, (h->K + 1) * sizeof(int32_t), s) == hipSuccess &&
+              hipMemcpy(d.occ, &n32, sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(d.ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) == hipSuccess &&
               hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
@@ -1331,6 +1694,8 @@ int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del
     if (n_ins + n_del == 0) return PLDS_OK;
     // range check of both lists before anything changes
     h->h_ctl->err = 0;
+    h->h_ctl->n_log = 0;
+    HIPCHK(hipMemcpyAsync(&h->d.ctl->n_log, &h->h_ctl->n_log, sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(&h->d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (n_ins) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_ins)), dim3(kBlock), 0, s, ins, n_ins, h->d.n, h->d.ctl);
     if (n_del) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_del)), dim3(kBlock), 0, s, del, n_del, h->d.n, h->d.ctl);
@@ -1428,6 +1793,28 @@ int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *p
     return PLDS_OK;
 }
 
+int plds_set_timing(plds_t *h, int32_t kernel) {
+    if (!h || kernel < 0 || kernel > 5) return PLDS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
+    if (kernel && h->ev.empty()) {
+        h->ev.assign(2 * kEvPairs, nullptr);
+        for (auto &e : h->ev)
+            if (hipEventCreate(&e) != hipSuccess) return PLDS_EHIP;
+    }
+    h->timed_kind = kernel;
+    h->ev_used = 0;
+    return PLDS_OK;
+}
+
+int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows) {
+    if (!h || !rows || cap < 0 || (cap && !out)) return PLDS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
+    int64_t k = std::min<int64_t>(h->h_ctl->n_log, cap);
+    *rows = h->h_ctl->n_log;
+    if (k > 0) HIPCHK(hipMemcpy(out, h->d.steplog, (size_t)k * 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
+    return PLDS_OK;
+}
+
 int plds_stats(const plds_t *h, plds_stats_t *out) {
     if (!h || !out) return PLDS_EINVAL;
     *out = h->stats;
@@ -1440,11 +1827,15 @@ int plds_check(plds_t *h, void *stream) {
     hipStream_t s = S(stream);
     HIPCHK(hipMemsetAsync(h->bad, 0, 8 * sizeof(int32_t), s));
     hipLaunchKernelGGL(k_check, dim3(grid_for(h->n * kWave)), dim3(kBlock), 0, s, h->d, h->bad);
+    HIPCHK(hipMemsetAsync(h->d.lvl_cnt, 0, (h->K + 1) * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_count_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, h->d, h->d.lvl_cnt);
+    hipLaunchKernelGGL(k_compare, dim3(grid_for(h->K)), dim3(kBlock), 0, s, h->d.lvl_cnt, h->d.occ, h->K,
+                       h->bad + 6);
     HIPCHK(hipGetLastError());
     int32_t bad[8];
     HIPCHK(hipMemcpyAsync(bad, h->bad, sizeof(bad), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (int i = 0; i < 6; i++)
+    for (int i = 0; i < 7; i++)
         if (bad[i]) return PLDS_ESTATE;
     return PLDS_OK;
 }
@@ -1497,6 +1888,8 @@ int plds_load_state(plds_t *h, const int32_t *edges, int64_t m, const int32_t *l
     HIPCHK(hipMemsetAsync(d.cnt2, 0, n4, s));
     HIPCHK(hipMemsetAsync(d.dl, 0xff, n4, s));
     hipLaunchKernelGGL(k_set_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d, levels);
+    HIPCHK(hipMemsetAsync(d.occ, 0, (h->K + 1) * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_count_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d, d.occ);
     HIPCHK(hipGetLastError());
     int64_t applied = 0;
     if (m) {

@@ -27,11 +27,15 @@ class plds_info_t(ctypes.Structure):
 
 
 STAT_FIELDS = ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up", "moves_down", "dl_calcs",
-               "slots_scanned", "top_level", "viol_ins0", "viol_del0", "host_syncs")
+               "slots_scanned", "top_level", "viol_ins0", "viol_del0", "host_syncs", "alg_bytes_up",
+               "timed_launches", "timed_ms")
 
 
 class plds_stats_t(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS] + [("reserved", ctypes.c_int64 * 4)]
+    _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS[:-1]] + [("timed_ms", ctypes.c_double),
+                                                                   ("reserved", ctypes.c_int64)]
+
+TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "ins_fin": 5}
 
 
 _lib = None
@@ -58,6 +62,8 @@ def lib():
         L.plds_info.argtypes = [_VP, ctypes.POINTER(plds_info_t)]
         L.plds_thresholds.argtypes = [_VP, _VP, _VP, _VP]
         L.plds_stats.argtypes = [_VP, ctypes.POINTER(plds_stats_t)]
+        L.plds_set_timing.argtypes = [_VP, ctypes.c_int32]
+        L.plds_step_log.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64)]
         L.plds_dump_state.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64), _VP, _VP]
         L.plds_load_state.argtypes = [_VP, _VP, _I64, _VP, _VP]
         L.plds_check.argtypes = [_VP, _VP]
@@ -70,7 +76,7 @@ def lib():
 
 EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_update", "plds_batch_insert",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
-           "plds_stats", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror")
+           "plds_stats", "plds_set_timing", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror")
 
 
 def strerror(code):
@@ -177,6 +183,19 @@ def plds_stats(h):
     s = plds_stats_t()
     _chk(lib().plds_stats(h, ctypes.byref(s)), "plds_stats")
     return {f: getattr(s, f) for f in STAT_FIELDS}
+
+
+def plds_set_timing(h, kernel):
+    k = TIMED_KERNELS.get(kernel, kernel) if isinstance(kernel, str) else int(kernel)
+    return _chk(lib().plds_set_timing(h, k), "plds_set_timing")
+
+
+def plds_step_log(h, cap=100000):
+    import numpy as np
+    out = np.zeros((cap, 4), dtype=np.int64)
+    rows = _I64()
+    _chk(lib().plds_step_log(h, out.ctypes.data, cap, ctypes.byref(rows)), "plds_step_log")
+    return out[:min(rows.value, cap)]
 
 
 def plds_dump_state(h, edges_out, levels_out, stream=None):

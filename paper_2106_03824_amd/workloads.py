@@ -130,3 +130,62 @@ def draws(seed, stream, count):
 
 def uniforms(seed, stream, count):
     return (draws(seed, stream, count) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+# ------------------------------------------------------------ update streams
+def _keys(e):
+    e = np.asarray(e, dtype=np.int64).reshape(-1, 2)
+    a, b = np.minimum(e[:, 0], e[:, 1]), np.maximum(e[:, 0], e[:, 1])
+    return (a << 32) | b
+
+
+def _unkeys(k):
+    return np.stack([(k >> 32).astype(np.int32), (k & 0xffffffff).astype(np.int32)], axis=1)
+
+
+class RmatStream:
+    """An R-MAT graph built by insertion batches, followed by update batches.
+
+    The graph: ``m`` unique edges on ``2**scale`` vertices (a=0.57, b=0.19,
+    c=0.19, seed ``seed``), inserted as ``build_batches`` batches of a seeded
+    random permutation (seed ``1000*cfg + 1``).  Update batch ``j`` uses seed
+    ``1000*cfg + 100 + j``: insertions are new uniform pairs absent from the
+    current graph, deletions are current edges sampled uniformly without
+    replacement, mixed batches are half of each.  The current edge set is
+    tracked here so every batch is a pure function of (cfg, seed, j).
+    """
+
+    def __init__(self, scale, m, seed=1, build_batches=16, cfg=2):
+        self.n = 2 ** scale
+        self.cfg = cfg
+        e = rmat(scale, m, seed=seed)
+        perm = permute_edges(e, 1000 * cfg + 1)
+        self.build = np.array_split(perm, build_batches)
+        self.cur = np.sort(_keys(e))
+        self.j = 0
+
+    def edges(self):
+        return _unkeys(self.cur)
+
+    def _seed(self):
+        s = 1000 * self.cfg + 100 + self.j
+        self.j += 1
+        return s
+
+    def insert_batch(self, count):
+        ins = new_pairs(self.n, self.edges(), count, self._seed())
+        self.cur = np.sort(np.concatenate([self.cur, _keys(ins)]))
+        return ins
+
+    def delete_batch(self, count):
+        dele = sample_edges(self.edges(), count, self._seed())
+        self.cur = np.setdiff1d(self.cur, _keys(dele), assume_unique=True)
+        return dele
+
+    def mixed_batch(self, count):
+        half = count // 2
+        ins = new_pairs(self.n, self.edges(), count - half, self._seed())
+        dele = sample_edges(self.edges(), half, self._seed())
+        cur = np.setdiff1d(self.cur, _keys(dele), assume_unique=True)
+        self.cur = np.sort(np.concatenate([cur, _keys(ins)]))
+        return ins, dele
