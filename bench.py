@@ -10,9 +10,12 @@ host and copied to HBM before the timed region; the value is the number of
 applied updates over the wall time of the K timed steps.
 
 Also reported: the insertion-scan kernel against the HBM roofline (its
-launches timed with HIP events inside the library, on the call's stream),
+launches timed with HIP events inside the library, on the call's stream;
+HBM traffic per launch from the committed counter summary under profiles/
+when it matches the current kernel source),
 parity of the GPU levels with the stored oracle trace of this stream, and the
-CPU oracle (one core) timed on a bounded sample of the same stream.
+CPU oracle (one core) timed on a bounded sample of the same stream (one
+deletion and one mixed batch of 1e6 from the post-build state).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -28,6 +31,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge updates/sec (ins, del) at 1e6 batch"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 2 << 30
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_ins_scan_rmat20_hbm_counters.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_03824_amd", "csrc", "plds.hip")
+
+
+def source_digest():
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_ins_scan launch from the committed counter summary, if
+    it was taken on the current kernel source; else None."""
+    if not os.path.exists(PROFILE_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PROFILE_SUMMARY):
+        if ":" in line and not line.startswith(" "):
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 TRACE = os.path.join(ROOT, "tests", "golden", "rmat20_oracle_trace.json")
 LEVELS = os.path.join(ROOT, "tests", "golden", "rmat20_oracle_levels.npz")
 
@@ -41,35 +69,44 @@ def digest(levels):
     return hashlib.sha256(np.ascontiguousarray(levels, dtype=np.int32).tobytes()).hexdigest()[:32]
 
 
-def cpu_baseline(stream_edges, n, ins_batch, seconds_target):
-    """The oracle, single-threaded, from the stored post-build oracle state,
-    on a prefix of the first timed insertion batch and of a deletion batch."""
+def cpu_baseline(build_edges, n, seconds_target):
+    """The oracle, single-threaded, on a bounded sample of the same stream:
+    from the stored post-build oracle state, one 1e6 deletion batch and one
+    1e6 mixed batch (half new pairs, half sampled edges) drawn from the
+    post-build graph with the stream's generators."""
     import numpy as np
     import oracle as O
+    from paper_2106_03824_amd import workloads as W
     if not os.path.exists(LEVELS):
         return None
     lv = np.load(LEVELS)["levels"].astype(np.int32)
     o = O.Oracle(n, 0.4, 3.0)
     t = time.perf_counter()
-    rc = o.load_state(stream_edges, lv)
+    rc = o.load_state(build_edges, lv)
     load_s = time.perf_counter() - t
     if rc != 0:
         log("oracle rejected the stored state", rc)
         return None
-    size = 10000
-    done, spent, applied = 0, 0.0, 0
-    while spent < seconds_target and done < len(ins_batch):
-        chunk = ins_batch[done:done + size]
-        t = time.perf_counter()
-        assert o.insert(chunk) == 0
-        spent += time.perf_counter() - t
-        applied += o.stats()["applied_ins"]
-        done += len(chunk)
-        size = min(size * 2, 200000)
-    return {"value": applied / spent, "unit": "edge updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle from the stored post-build state of the same RMAT-20 stream (load {load_s:.1f}s, "
-                      f"not timed), first {done} pairs of the first timed 1e6 insertion batch applied in "
-                      f"growing chunks; {applied} updates in {spent:.1f}s"}
+    dele = W.sample_edges(build_edges, 10 ** 6, 2900)
+    t = time.perf_counter()
+    assert o.delete(dele) == 0
+    t_del = time.perf_counter() - t
+    u_del = o.stats()["applied_del"]
+    rest = o.edges()
+    mi = W.new_pairs(n, rest, 5 * 10 ** 5, 2901)
+    md = W.sample_edges(rest, 5 * 10 ** 5, 2902)
+    t = time.perf_counter()
+    assert o.update(mi, md) == 0
+    t_mix = time.perf_counter() - t
+    s = o.stats()
+    u_mix = s["applied_ins"] + s["applied_del"]
+    total = t_del + t_mix
+    return {"value": (u_del + u_mix) / total, "unit": "edge updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle (one core) loaded with the stored post-build oracle state of this RMAT-20 stream "
+                      f"(load {load_s:.1f}s, not timed); one 1e6 deletion batch ({t_del:.2f}s) and one 1e6 "
+                      f"mixed batch ({t_mix:.1f}s) drawn from the post-build graph; a 1e6 insertion batch "
+                      f"(over 2 min on the oracle) is left out of the sample",
+            "rates": {"del": u_del / t_del, "mix": u_mix / t_mix}}
 
 
 def main():
@@ -80,6 +117,8 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--batch", type=int, default=10 ** 6)
     ap.add_argument("--kernel", default="ins_scan", help="kernel timed for the roofline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 2 GiB (reference for the HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -94,6 +133,14 @@ def main():
     from paper_2106_03824_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": COPY_BYTES, "note": "one device-to-device copy kernel, read+write"}))
+        return
     dev = torch.device("cuda", 0)
     scale, B = args.scale, args.batch
     m0 = 16 * 2 ** scale
@@ -140,8 +187,6 @@ def main():
         batches.append([("ins", torch.from_numpy(ins).to(dev), None),
                         ("del", None, torch.from_numpy(dele).to(dev)),
                         ("mix", torch.from_numpy(mi).to(dev), torch.from_numpy(md).to(dev))])
-        if r == 0:
-            first_ins = ins
     torch.cuda.synchronize()
     log("batches ready")
 
@@ -185,7 +230,8 @@ def main():
         per_launch = tot["alg_bytes"] / tot["launches"]
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_ins_scan",
+                "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic() if args.kernel == "ins_scan" else None, "kernel": "k_" + args.kernel,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": tot["launches"],
                 "alg_bytes_per_launch": round(per_launch, 1)}
     lat_ms = sorted(x * 1e3 for x in lat)
@@ -204,7 +250,7 @@ def main():
         "parity_vs_oracle_trace": parity if trace is not None else None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, first_ins, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -132,10 +132,16 @@ int plds_stats(const plds_t *h, plds_stats_t *out);
  * movers, cumulative slots scanned), the movers landing at l. */
 int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
 
+/* How the insertion level loop runs: 0 = the whole loop in one cooperative
+ * launch with grid barriers between its parts (when the device supports it,
+ * else as 1); 1 (default) = one kernel per part.  Results are identical. */
+int plds_set_sweep_mode(plds_t *h, int32_t mode);
+
 /* Time one kernel of the level sweeps with HIP events recorded around each of
  * its launches (0 = off, 1 = insertion scan, 2 = deletion scan,
  * 3 = desire-level, 4 = insertion step preparation, 5 = insertion step
- * finish).  Results appear in plds_stats (timed_launches, timed_ms). */
+ * finish, 6 = the cooperative insertion sweep).  Results appear in plds_stats
+ * (timed_launches, timed_ms). */
 int plds_set_timing(plds_t *h, int32_t kernel);
 
 /* Checkpoint.  plds_dump_state writes the edge list (u < v, unordered) to the

@@ -50,6 +50,7 @@ constexpr int32_t kErrFull = 2;      // slab insert found no free slot
 constexpr int32_t kErrLevel = 4;     // a level left [0, K)
 constexpr int32_t kErrOrder = 8;     // a desire-level not above the processed level
 constexpr int32_t kErrPool = 16;     // pool exhausted
+constexpr int32_t kErrHang = 32;     // a grid barrier wait gave up
 
 struct Ctl {
     int32_t l;            // level of the current step
@@ -61,6 +62,7 @@ struct Ctl {
     int32_t n_chunks;     // work items of the current step
     int32_t n_cls[4];     // movers per slab-size class
     int32_t n_log;        // rows written to the step log in the current call
+    int32_t nmvb[2];      // movers of the step that consumed cascade list 0 / 1
     int32_t n_rc;         // desire-level recomputations of the current step
     int32_t nm;           // running minimum of pending desire-levels
     int32_t blocks_done;  // last-block election
@@ -573,28 +575,32 @@ __device__ __forceinline__ void add_chunks_w(Dev &d, int32_t v) {
     for (int32_t k = 0; k < nch; k++) d.chunks[base + off + k] = ((int64_t)v << 32) | (uint32_t)k;
 }
 
-// Step of Algorithm 2, part 1.  The step moves the set S of every vertex of
-// level `phys` that violates Invariant 1 (the sorted candidates of that
-// level plus the vertices marked there) up to level l+1.  Normally
-// phys == l; phys < l is a multi-level step (see k_ins_next).
-__global__ void k_ins_prep(Dev d) {
-    if (d.ctl->done) return;
-    int32_t l = d.ctl->l, phys = d.ctl->phys, cur = d.ctl->cur;
-    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+// State of one insertion step: the movers sit at level `phys` (the vertices
+// of that level that violate Invariant 1: its sorted candidates and its
+// marked vertices, kept in cascade list `cur`) and land at level l+1.
+// Normally phys == l; phys < l is a multi-level step (see ins_decide).
+struct InsStep {
+    int32_t l, phys, jump, cur, done;
+};
+
+// Step of Algorithm 2, part 1: gather the movers, flag them in level[], and
+// sort them into work lists by slab size.  Returns false (on every block
+// alike) if the step is out of range.
+__device__ bool ins_prep_phase(Dev &d, const InsStep &st, int bid, int nblk, int32_t *sh) {
+    int32_t l = st.l, phys = st.phys, cur = st.cur;
     if (phys < 0 || phys > l || l + 1 >= d.K) {
-        if (gid == 0) latch(d.ctl, kErrLevel);
-        return;
+        if (bid == 0 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
+        return false;
     }
     int32_t a0 = d.lvl_start[phys], a1 = d.lvl_start[phys + 1];
     int32_t nA = a1 - a0, nB = d.ctl->casc_n[cur];
     const int32_t *casc = cur ? d.casc1 : d.casc0;
     if (nA + nB > d.n) {
-        if (gid == 0) latch(d.ctl, kErrLevel);
-        return;
+        if (bid == 0 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
+        return false;
     }
-    __shared__ int32_t sh[kBlock / kWave + 2];
-    int stride = gridDim.x * blockDim.x;
-    for (int i0 = blockIdx.x * blockDim.x; i0 < nA + nB; i0 += stride) {
+    int stride = nblk * blockDim.x;
+    for (int i0 = bid * blockDim.x; i0 < nA + nB; i0 += stride) {
         int i = i0 + threadIdx.x;
         int32_t v = -1, cl = -1;
         if (i < nA + nB) {
@@ -608,42 +614,46 @@ __global__ void k_ins_prep(Dev d) {
         for (int k = 0; k < 4; k++) bpush(d.cls[k], &d.ctl->n_cls[k], d.n, cl == k, v, d.ctl, sh);
         add_chunks_b(d, cl == 4 ? v : -1, sh);
     }
-    if (gid == 0) d.ctl->n_mv = nA + nB;
+    if (bid == 0 && threadIdx.x == 0) d.ctl->nmvb[cur] = nA + nB;
+    return true;
 }
 
 // Part 2: every mover v scans its slab.  Neighbour w at level l stays iff it
-// is not itself a mover (every violator of level l moves);
-// w at l+1 gains v as up-neighbour (and, in a multi-level step, as
-// up*-neighbour) and is marked if that makes it exceed the cap of level l+1;
-// w at l+2 gains v as up*-neighbour.
-// Work items: movers with slabs of at most 8/16/32/64 slots are served by
-// lane groups of that width (8/4/2/1 movers per wavefront); larger slabs are
-// cut into kChunk-slot pieces served by a whole wavefront each.
-__global__ void k_ins_scan(Dev d) {
-    if (d.ctl->done) return;
-    int32_t l = d.ctl->l, nxt = d.ctl->cur ^ 1, jump = d.ctl->jump;
+// is not itself a mover (every violator of level l moves); w at l+1 gains v
+// as up-neighbour (and, in a multi-level step, as up*-neighbour) and is
+// marked if that makes it exceed the cap of level l+1; w at l+2 gains v as
+// up*-neighbour.  Work items: movers with slabs of at most 8/16/32/64 slots
+// are served by lane groups of that width (8/4/2/1 movers per wavefront);
+// larger slabs are cut into kChunk-slot pieces, a wavefront each.  Per-block
+// statistics go to d.part[3*bid..] (stored, or added when `accum`).
+__device__ void ins_scan_phase(Dev &d, const InsStep &st, int bid, int nblk, bool accum) {
+    int32_t l = st.l, nxt = st.cur ^ 1, jump = st.jump;
     int32_t *casc = nxt ? d.casc1 : d.casc0;
     int32_t ub1 = d.up_max[(l + 1) / d.L];
-    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
-    int nw = gridDim.x * blockDim.x / kWave;
-    int32_t items[5];
-    items[0] = (d.ctl->n_cls[0] + 7) / 8;
-    items[1] = (d.ctl->n_cls[1] + 3) / 4;
-    items[2] = (d.ctl->n_cls[2] + 1) / 2;
-    items[3] = d.ctl->n_cls[3];
-    items[4] = d.ctl->n_chunks;
-    int32_t total = items[0] + items[1] + items[2] + items[3] + items[4];
+    int wid = (bid * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = nblk * blockDim.x / kWave;
+    int32_t n0 = d.ctl->n_cls[0], n1c = d.ctl->n_cls[1], n2 = d.ctl->n_cls[2], n3 = d.ctl->n_cls[3];
+    int32_t i0 = (n0 + 7) / 8, i1 = (n1c + 3) / 4, i2 = (n2 + 1) / 2, i3 = n3, i4 = d.ctl->n_chunks;
+    int32_t total = i0 + i1 + i2 + i3 + i4;
     int32_t scanned = 0, nU = 0, n1 = 0;
     for (int t = wid; t < total; t += nw) {
-        int cl = 0;
+        int cl;
         int32_t tl = t;
-        while (cl < 4 && tl >= items[cl]) tl -= items[cl++];
+        if (tl < i0) cl = 0;
+        else if ((tl -= i0) < i1) cl = 1;
+        else if ((tl -= i1) < i2) cl = 2;
+        else if ((tl -= i2) < i3) cl = 3;
+        else {
+            tl -= i3;
+            cl = 4;
+        }
         int W = cl == 4 ? kWave : (8 << cl);
         int grp = lane / W, q = lane % W;
         int32_t v = -1, lo = 0, hi = 0;
         if (cl < 4) {
+            int32_t ncl = cl == 0 ? n0 : cl == 1 ? n1c : cl == 2 ? n2 : n3;
             int32_t j = tl * (kWave / W) + grp;
-            if (j < d.ctl->n_cls[cl]) {
+            if (j < ncl) {
                 v = d.cls[cl][j];
                 hi = d.cap[v];
             }
@@ -680,7 +690,6 @@ __global__ void k_ins_scan(Dev d) {
         for (int o = W / 2; o > 0; o >>= 1) stay += __shfl_xor(stay, o, kWave);
         if (q == 0 && v >= 0 && stay) atomicAdd(&d.stay[v], stay);
     }
-    // per-block statistics, summed by the step's decision kernel
     __shared__ int32_t red[3][kBlock / kWave];
     nU = wave_sum(nU);
     n1 = wave_sum(n1);
@@ -694,21 +703,21 @@ __global__ void k_ins_scan(Dev d) {
     if (threadIdx.x < 3) {
         int64_t t = 0;
         for (int i = 0; i < kBlock / kWave; i++) t += red[threadIdx.x][i];
-        d.part[3 * blockIdx.x + threadIdx.x] = t;
+        if (accum) d.part[3 * bid + threadIdx.x] += t;
+        else d.part[3 * bid + threadIdx.x] = t;
     }
+    __syncthreads();
 }
 
 // Part 3: movers take level l+1 with up*(v) = old up(v) and up(v) = old up(v)
 // minus the neighbours that stayed at l; a mover still above the cap of l+1
 // stays marked.
-__global__ void k_ins_fin(Dev d) {
-    if (d.ctl->done) return;
-    int32_t l = d.ctl->l, nxt = d.ctl->cur ^ 1, nmv = d.ctl->n_mv;
+__device__ void ins_fin_phase(Dev &d, const InsStep &st, int bid, int nblk, int32_t *sh) {
+    int32_t l = st.l, nxt = st.cur ^ 1, nmv = d.ctl->nmvb[st.cur];
     int32_t *casc = nxt ? d.casc1 : d.casc0;
     int32_t ub1 = d.up_max[(l + 1) / d.L];
-    __shared__ int32_t sh[kBlock / kWave + 2];
-    int stride = gridDim.x * blockDim.x;
-    for (int i0 = blockIdx.x * blockDim.x; i0 < nmv; i0 += stride) {
+    int stride = nblk * blockDim.x;
+    for (int i0 = bid * blockDim.x; i0 < nmv; i0 += stride) {
         int i = i0 + threadIdx.x;
         bool viol = false;
         int32_t v = -1;
@@ -726,96 +735,265 @@ __global__ void k_ins_fin(Dev d) {
     }
 }
 
-// Part 4 (one block): account the step and choose the next one.  The next
-// movers sit at level z0: the marked vertices at l+1, else the next level with
-// sorted candidates.  If they are every vertex of z0 and the levels above z0
-// are empty up to level y (bounded by the first level of the next group),
-// they climb in lockstep: at each of those levels their up-degree counts the
-// same set (themselves and the vertices at or above y) against the same cap,
-// and no other vertex is at or next to those levels.  The next step then
-// moves them from z0 to y in one go, with the step's level set to y-1 and the
-// moves and sweeps of the skipped levels counted.
-__global__ void k_ins_next(Dev d) {
-    Ctl *c = d.ctl;
-    if (c->done) return;
-    __shared__ int32_t sh_z0, sh_all, sh_e;
-    __shared__ int64_t ps[3][kBlock];
-    int tid = threadIdx.x;
-    int32_t l = c->l, phys = c->phys, nmv = c->n_mv, cur = c->cur, nxt = cur ^ 1;
-    {
-        int64_t a = 0, b = 0, e = 0;
-        for (int i = tid; i < kSweepGrid; i += blockDim.x) {
-            a += d.part[3 * i];
-            b += d.part[3 * i + 1];
-            e += d.part[3 * i + 2];
-        }
-        ps[0][tid] = a;
-        ps[1][tid] = b;
-        ps[2][tid] = e;
-        __syncthreads();
-        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-            if (tid < o)
-                for (int k = 0; k < 3; k++) ps[k][tid] += ps[k][tid + o];
-            __syncthreads();
-        }
+// Part 4: the next step after step `st` (every thread of a block calls it and
+// gets the same answer).  The next movers sit at level z0: the marked
+// vertices at l+1, else the next level with sorted candidates.  If they are
+// every vertex of z0 and the levels above z0 are empty up to level y (at most
+// the first level of the next group), they climb in lockstep: at each of
+// those levels their up-degree counts the same set (themselves and the
+// vertices at or above y) against the same cap, and no other vertex is at or
+// next to those levels.  The next step then moves them from z0 to y in one
+// go, its level set to y-1; the skipped sweeps and moves are counted by the
+// caller.  occ[] is read without this step's own update (applied later by
+// the caller): occ[z0] after the step is occ[z0] + (z0 == l+1 ? movers : 0).
+__device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn, int32_t *sh1) {
+    InsStep nx;
+    nx.cur = st.cur ^ 1;
+    nx.jump = 0;
+    nx.done = 0;
+    int32_t l = st.l;
+    int32_t z0 = cn > 0 ? l + 1 : (l + 1 < d.K ? d.next_nz[l + 1] : d.K);
+    if (z0 >= d.K - 1) {       // nothing left (no vertex of the top group can violate Invariant 1)
+        if (z0 == d.K - 1 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
+        nx.done = 1;
+        nx.l = nx.phys = d.K;
+        return nx;
     }
-    if (tid == 0) {
-        c->scanned += ps[0][0];
-        c->alg_U += ps[1][0];
-        c->alg_up1 += ps[2][0];
-        int64_t steps = l + 1 - phys;
-        c->sweeps += steps;
-        c->moves += (int64_t)nmv * steps;
-        d.occ[phys] -= nmv;
-        d.occ[l + 1] += nmv;
-        c->top = max(c->top, (int64_t)(l + 1));
-        if (c->n_log < 2 * d.K) {
-            int64_t *row = d.steplog + 4 * c->n_log++;
-            row[0] = l;
-            row[1] = phys;
-            row[2] = nmv;
-            row[3] = c->scanned;
-        }
-        int32_t cn = c->casc_n[nxt];
-        c->casc_n[cur] = 0;
-        c->cur = nxt;
+    int32_t ns = d.lvl_start[z0 + 1] - d.lvl_start[z0];
+    int32_t movers = (z0 == l + 1 ? cn : 0) + ns;
+    int32_t occz = d.occ[z0] + (z0 == l + 1 ? nmv : 0);
+    bool all = occz == movers;
+    int32_t limit = min((z0 / d.L + 1) * d.L, d.K - 1);   // first level of the next group
+    __syncthreads();
+    if (threadIdx.x == 0) sh1[0] = INT32_MAX;
+    __syncthreads();
+    if (all && z0 + 2 <= limit)
+        for (int32_t z = z0 + 1 + threadIdx.x; z < limit; z += blockDim.x)
+            if (d.occ[z] > 0) atomicMin(&sh1[0], z);
+    __syncthreads();
+    int32_t y = min(sh1[0], limit);
+    __syncthreads();
+    if (all && y >= z0 + 2) {
+        nx.l = y - 1;
+        nx.phys = z0;
+        nx.jump = 1;
+    } else {
+        nx.l = z0;
+        nx.phys = z0;
+    }
+    return nx;
+}
+
+// Sum of the scans' per-block statistics over nparts blocks (all threads of
+// one block call it; the result is valid in thread 0).
+__device__ void sum_parts(Dev &d, int nparts, int64_t out[3]) {
+    __shared__ int64_t ps[3][kBlock];
+    int64_t a = 0, b = 0, e = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        a += d.part[3 * i];
+        b += d.part[3 * i + 1];
+        e += d.part[3 * i + 2];
+    }
+    ps[0][threadIdx.x] = a;
+    ps[1][threadIdx.x] = b;
+    ps[2][threadIdx.x] = e;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int k = 0; k < 3; k++) ps[k][threadIdx.x] += ps[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    for (int k = 0; k < 3; k++) out[k] = ps[k][0];
+    __syncthreads();
+}
+
+// Bookkeeping of a finished step (one thread): statistics, step log, and the
+// reset of the cascade list the step consumed.  sums: the step's scan
+// statistics, or NULL when they are summed at the end of the sweep.
+__device__ void ins_account(Dev &d, const InsStep &st, int32_t nmv, const int64_t *sums) {
+    Ctl *c = d.ctl;
+    if (sums) {
+        c->scanned += sums[0];
+        c->alg_U += sums[1];
+        c->alg_up1 += sums[2];
+    } else {
+        c->scanned = -1;   // no per-step slot count in the step log
+    }
+    int64_t steps = st.l + 1 - st.phys;
+    c->sweeps += steps;
+    c->moves += (int64_t)nmv * steps;
+    c->top = max(c->top, (int64_t)(st.l + 1));
+    if (c->n_log < 2 * d.K) {
+        int64_t *row = d.steplog + 4 * c->n_log++;
+        row[0] = st.l;
+        row[1] = st.phys;
+        row[2] = nmv;
+        row[3] = c->scanned;
+    }
+    c->casc_n[st.cur] = 0;
+}
+
+__device__ __forceinline__ void ins_store(Ctl *c, const InsStep &nx) {
+    c->l = nx.l;
+    c->phys = nx.phys;
+    c->jump = nx.jump;
+    c->cur = nx.cur;
+    c->done = nx.done;
+}
+
+__device__ __forceinline__ InsStep ins_load(const Ctl *c) { return InsStep{c->l, c->phys, c->jump, c->cur, c->done}; }
+
+// ---- one kernel per part (used when a cooperative launch is not available)
+__global__ void k_ins_prep(Dev d) {
+    __shared__ int32_t sh[kBlock / kWave + 2];
+    InsStep st = ins_load(d.ctl);
+    if (st.done) return;
+    ins_prep_phase(d, st, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ void k_ins_scan(Dev d) {
+    InsStep st = ins_load(d.ctl);
+    if (st.done) return;
+    ins_scan_phase(d, st, blockIdx.x, gridDim.x, false);
+}
+
+__global__ void k_ins_fin(Dev d) {
+    __shared__ int32_t sh[kBlock / kWave + 2];
+    InsStep st = ins_load(d.ctl);
+    if (st.done) return;
+    ins_fin_phase(d, st, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ void k_ins_next(Dev d, int nparts) {
+    __shared__ int32_t sh1[2];
+    Ctl *c = d.ctl;
+    InsStep st = ins_load(c);
+    if (st.done) return;
+    int32_t nmv = c->nmvb[st.cur], cn = c->casc_n[st.cur ^ 1];
+    InsStep nx = ins_decide(d, st, nmv, cn, sh1);
+    int64_t sums[3];
+    sum_parts(d, nparts, sums);
+    if (threadIdx.x == 0) {
+        ins_account(d, st, nmv, sums);
+        d.occ[st.phys] -= nmv;
+        d.occ[st.l + 1] += nmv;
         c->n_chunks = 0;
         c->n_cls[0] = c->n_cls[1] = c->n_cls[2] = c->n_cls[3] = 0;
-        c->n_mv = 0;
-        c->jump = 0;
-        int32_t z0 = cn > 0 ? l + 1 : (l + 1 < d.K ? d.next_nz[l + 1] : d.K);
-        sh_z0 = z0;
-        sh_all = 0;
-        sh_e = INT32_MAX;
-        if (z0 < d.K) {
-            int32_t ns = d.lvl_start[z0 + 1] - d.lvl_start[z0];
-            int32_t movers = (z0 == l + 1 ? cn : 0) + ns;
-            sh_all = d.occ[z0] == movers;
-        }
-        if (cn > 0 && l + 2 >= d.K) latch(c, kErrLevel);
+        ins_store(c, nx);
     }
+}
+
+// ---- the whole level loop in one cooperative launch
+struct Bar {
+    unsigned count, gen;
+    int abort;
+};
+
+constexpr long kSpinLimit = 1L << 22;
+
+// Grid-wide barrier for a cooperative launch (all blocks co-resident).
+// Agent-scope fences make every block's writes visible to all XCDs.  A wait
+// gives up after kSpinLimit polls, raises `abort`, and every block then
+// leaves the loop at its next barrier.  Returns false once aborted.
+__device__ bool grid_sync(Bar *b, unsigned nblk) {
+    __shared__ int ab;
     __syncthreads();
-    int32_t z0 = sh_z0;
-    if (z0 >= d.K) {
-        if (tid == 0) c->done = 1;
-        return;
-    }
-    int32_t limit = min((z0 / d.L + 1) * d.L, d.K - 1);   // first level of the next group
-    if (sh_all && z0 + 2 <= limit) {
-        for (int32_t z = z0 + 1 + tid; z < limit; z += blockDim.x)
-            if (d.occ[z] > 0) atomicMin(&sh_e, z);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int32_t y = min(sh_e, limit);
-        if (sh_all && y >= z0 + 2) {
-            c->l = y - 1;
-            c->phys = z0;
-            c->jump = 1;
+    if (threadIdx.x == 0) {
+        int aborted = 0;
+        unsigned g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        unsigned arrived = atomicAdd(&b->count, 1u);
+        if (arrived == nblk - 1) {
+            __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(&b->gen, 1u);
         } else {
-            c->l = z0;
-            c->phys = z0;
+            long spins = 0;
+            while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    aborted = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) {
+                    atomicExch(&b->abort, 1);
+                    aborted = 1;
+                    break;
+                }
+            }
         }
+        __threadfence();
+        ab = aborted || __hip_atomic_load(&b->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return !ab;
+}
+
+// Every step is prep | scan | fin with a grid barrier after each part; the
+// decision for the next step is taken by every block on its own (same inputs,
+// same answer) at the start of the next iteration.  Block 0 does the
+// bookkeeping, applies each step's occupancy change one phase later (when no
+// block reads occ), and resets the work-list counters during fin.
+__global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
+    __shared__ int32_t sh[kBlock / kWave + 2];
+    __shared__ int32_t sh1[2];
+    const int bid = blockIdx.x, nblk = gridDim.x;
+    const bool writer = bid == 0 && threadIdx.x == 0;
+    Ctl *c = d.ctl;
+    InsStep st = ins_load(c);
+    InsStep prev{};
+    int32_t prev_nmv = 0;
+    bool have_prev = false, occ_pending = false;
+    while (true) {
+        if (have_prev) {
+            int32_t cn = c->casc_n[prev.cur ^ 1];
+            st = ins_decide(d, prev, prev_nmv, cn, sh1);
+            if (writer) {
+                ins_account(d, prev, prev_nmv, nullptr);
+                ins_store(c, st);
+            }
+            occ_pending = true;
+        }
+        if (st.done) break;
+        if (!ins_prep_phase(d, st, bid, nblk, sh)) {
+            if (writer) c->done = 1;
+            break;
+        }
+        if (!grid_sync(bar, nblk)) break;
+        if (writer && occ_pending) {
+            d.occ[prev.phys] -= prev_nmv;
+            d.occ[prev.l + 1] += prev_nmv;
+            occ_pending = false;
+        }
+        ins_scan_phase(d, st, bid, nblk, true);
+        if (!grid_sync(bar, nblk)) break;
+        if (writer) {
+            c->n_chunks = 0;
+            c->n_cls[0] = c->n_cls[1] = c->n_cls[2] = c->n_cls[3] = 0;
+        }
+        ins_fin_phase(d, st, bid, nblk, sh);
+        if (!grid_sync(bar, nblk)) break;
+        prev_nmv = c->nmvb[st.cur];
+        prev = st;
+        have_prev = true;
+    }
+    if (writer && occ_pending) {
+        d.occ[prev.phys] -= prev_nmv;
+        d.occ[prev.l + 1] += prev_nmv;
+    }
+    // statistics accumulated per block over all steps
+    if (grid_sync(bar, nblk) && bid == 0) {
+        int64_t sums[3];
+        sum_parts(d, nblk, sums);
+        if (threadIdx.x == 0) {
+            c->scanned = sums[0];
+            c->alg_U = sums[1];
+            c->alg_up1 = sums[2];
+        }
+    }
+    if (writer && __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        latch(c, kErrHang);
+        c->done = 1;
     }
 }
 
@@ -1206,6 +1384,10 @@ struct plds {
     plds_stats_t stats{};
     int32_t latched = 0;
     bool broken = false;
+    // insertion sweep as one cooperative launch (0 blocks = not available)
+    int sweep_mode = 1;          // 0: cooperative when possible, 1: one kernel per part
+    int coop_blocks = -1;        // -1 = not yet determined
+    Bar *bar = nullptr;
     // optional event timing of one sweep kernel
     int32_t timed_kind = 0;
     std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -1283,7 +1465,7 @@ void free_all(plds *h) {
     dfree(d.cand), dfree(d.sorted), dfree(d.lvl_cnt), dfree(d.lvl_start), dfree(d.next_nz), dfree(d.occ), dfree(d.lvl_fill), dfree(d.steplog), dfree(d.part);
     for (int k = 0; k < 4; k++) dfree(d.cls[k]);
     dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
-    dfree(h->tile), dfree(h->newoff), dfree(h->bad);
+    dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     h->ev.clear();
@@ -1467,8 +1649,27 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
     return PLDS_OK;
 }
 
-// Algorithm 2 after the edges are in: seed, bucket by level, then run level
-// steps in growing runs until the control block reports done.
+// Blocks of the cooperative sweep: up to 4 resident blocks per compute unit
+// (fewer if the occupancy calculator says so), at most kSweepGrid.
+int coop_blocks(plds *h) {
+    if (h->coop_blocks >= 0) return h->coop_blocks;
+    h->coop_blocks = 0;
+    int coop = 0, ncu = 0, per = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device) != hipSuccess || !coop)
+        return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || ncu <= 0)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_ins_sweep, kBlock, 0) != hipSuccess ||
+        per <= 0)
+        return 0;
+    if (!h->bar && dalloc(&h->bar, 1)) return 0;
+    h->coop_blocks = std::min(std::min(per, 4) * ncu, kSweepGrid);
+    return h->coop_blocks;
+}
+
+// Algorithm 2 after the edges are in: seed, bucket by level, then run the
+// level loop: one cooperative launch, or (fallback) one kernel per part in
+// growing runs until the control block reports done.
 int insertion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
     int nt = h->h_ctl->n_touch;
@@ -1480,6 +1681,23 @@ int insertion_sweep(plds *h, hipStream_t s) {
     int rc = sync_ctl(h, s);
     if (rc) return rc;
     h->stats.viol_ins0 = h->h_ctl->n_cand;
+    if (!h->h_ctl->done && h->sweep_mode == 0 && coop_blocks(h) > 0) {
+        HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(Bar), s));
+        HIPCHK(hipMemsetAsync(d.part, 0, 3 * kSweepGrid * sizeof(int64_t), s));
+        Bar *bar = h->bar;
+        void *args[] = {(void *)&d, (void *)&bar};
+        tstart(h, 6, s);
+        hipError_t e = hipLaunchCooperativeKernel((const void *)k_ins_sweep, dim3(h->coop_blocks), dim3(kBlock), args,
+                                                  0, s);
+        tstop(h, 6, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->coop_blocks = 0;          // use the per-part kernels from now on
+        } else {
+            rc = sync_ctl(h, s);
+            if (rc) return rc;
+        }
+    }
     int run = 8;
     int64_t steps = 0;
     while (!h->h_ctl->done && !h->h_ctl->err) {
@@ -1498,7 +1716,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
             tstart(h, 5, s);
             hipLaunchKernelGGL(k_ins_fin, dim3(kListGrid), dim3(kBlock), 0, s, d);
             tstop(h, 5, s);
-            hipLaunchKernelGGL(k_ins_next, dim3(1), dim3(kBlock), 0, s, d);
+            hipLaunchKernelGGL(k_ins_next, dim3(1), dim3(kBlock), 0, s, d, kSweepGrid);
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
@@ -1793,8 +2011,14 @@ int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *p
     return PLDS_OK;
 }
 
+int plds_set_sweep_mode(plds_t *h, int32_t mode) {
+    if (!h || mode < 0 || mode > 1) return PLDS_EINVAL;
+    h->sweep_mode = mode;
+    return PLDS_OK;
+}
+
 int plds_set_timing(plds_t *h, int32_t kernel) {
-    if (!h || kernel < 0 || kernel > 5) return PLDS_EINVAL;
+    if (!h || kernel < 0 || kernel > 6) return PLDS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
     if (kernel && h->ev.empty()) {
         h->ev.assign(2 * kEvPairs, nullptr);

@@ -35,7 +35,7 @@ class plds_stats_t(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS[:-1]] + [("timed_ms", ctypes.c_double),
                                                                    ("reserved", ctypes.c_int64)]
 
-TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "ins_fin": 5}
+TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "ins_fin": 5, "ins_sweep": 6}
 
 
 _lib = None
@@ -64,6 +64,7 @@ def lib():
         L.plds_stats.argtypes = [_VP, ctypes.POINTER(plds_stats_t)]
         L.plds_set_timing.argtypes = [_VP, ctypes.c_int32]
         L.plds_step_log.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64)]
+        L.plds_set_sweep_mode.argtypes = [_VP, ctypes.c_int32]
         L.plds_dump_state.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64), _VP, _VP]
         L.plds_load_state.argtypes = [_VP, _VP, _I64, _VP, _VP]
         L.plds_check.argtypes = [_VP, _VP]
@@ -76,7 +77,7 @@ def lib():
 
 EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_update", "plds_batch_insert",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
-           "plds_stats", "plds_set_timing", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror")
+           "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror")
 
 
 def strerror(code):
@@ -183,6 +184,10 @@ def plds_stats(h):
     s = plds_stats_t()
     _chk(lib().plds_stats(h, ctypes.byref(s)), "plds_stats")
     return {f: getattr(s, f) for f in STAT_FIELDS}
+
+
+def plds_set_sweep_mode(h, mode):
+    return _chk(lib().plds_set_sweep_mode(h, int(mode)), "plds_set_sweep_mode")
 
 
 def plds_set_timing(h, kernel):

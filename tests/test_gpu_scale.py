@@ -1,0 +1,83 @@
+"""Full-size parity: the RMAT scale-20 stream of the benchmark (16*2^20 edges
+built by 16 insertion batches, then rounds of 10^6 insertions, deletions and
+mixed updates) against the stored oracle trace of the same stream
+(tests/golden/rmat20_oracle_trace.json, written by make_rmat20_oracle.py
+from the oracle alone): after every batch, the SHA-256 of all 2^20 levels and
+the sweep/move counts must be identical.  Also the post-build levels against
+the stored oracle levels, element by element."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRACE = os.path.join(HERE, "golden", "rmat20_oracle_trace.json")
+LEVELS = os.path.join(HERE, "golden", "rmat20_oracle_levels.npz")
+
+
+def digest(levels):
+    return hashlib.sha256(np.ascontiguousarray(levels, dtype=np.int32).tobytes()).hexdigest()[:32]
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("mode", [1])
+def test_rmat20_stream_against_oracle_trace(mode):
+    from paper_2106_03824_amd import plds as P
+    from paper_2106_03824_amd import workloads as W
+    trace = json.load(open(TRACE))["batches"]
+    st = W.RmatStream(20, 16 * 2 ** 20, seed=1, build_batches=16, cfg=2)
+    g = P.PLDS(st.n, 0.4, 3.0, 0, 2 * 16 * 2 ** 20)
+    P.plds_set_sweep_mode(g.h, mode)
+    idx = 0
+
+    def check(kind):
+        nonlocal idx
+        ref = trace[idx]
+        assert ref["kind"] == kind
+        lv = g.levels().cpu().numpy()
+        s = g.stats()
+        assert digest(lv) == ref["sha"], f"levels differ after {kind}"
+        for k in ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up", "moves_down",
+                  "viol_ins0", "viol_del0"):
+            assert s[k] == ref[k], (kind, k, s[k], ref[k])
+        idx += 1
+        return lv
+
+    for i, b in enumerate(st.build):
+        say("rmat20 build", i)
+        P.plds_batch_insert(g.h, torch.from_numpy(np.ascontiguousarray(b)).cuda())
+        lv = check(f"build{i}")
+    ref_lv = np.load(LEVELS)["levels"].astype(np.int32)
+    assert np.array_equal(lv, ref_lv)
+    assert g.check() == 0
+    r = 0
+    while idx + 3 <= len(trace):
+        say("rmat20 round", r)
+        P.plds_update(g.h, torch.from_numpy(st.insert_batch(10 ** 6)).cuda(), None)
+        check(f"ins{r}")
+        P.plds_update(g.h, None, torch.from_numpy(st.delete_batch(10 ** 6)).cuda())
+        check(f"del{r}")
+        mi, md = st.mixed_batch(10 ** 6)
+        P.plds_update(g.h, torch.from_numpy(mi).cuda(), torch.from_numpy(md).cuda())
+        check(f"mix{r}")
+        r += 1
+    assert g.check() == 0
+    # coreness estimates of a sample of vertices against the definition
+    vs = torch.arange(0, st.n, 997, dtype=torch.int32, device="cuda")
+    est = g.coreness(vs).cpu().numpy()
+    lvs = g.levels().cpu().numpy()[vs.cpu().numpy()]
+    deg = g.degrees().cpu().numpy()[vs.cpu().numpy()]
+    info = g.info()
+    up, dn, pw = g.thresholds()
+    exp = np.array([0.0 if d == 0 else pw[max((l + 1) // info["L"] - 1, 0)] for l, d in zip(lvs, deg)])
+    assert np.array_equal(est, exp)
