@@ -151,13 +151,13 @@ def main():
     trace = json.load(open(TRACE)) if (scale == 20 and B == 10 ** 6 and os.path.exists(TRACE)) else None
     parity = {"batches_checked": 0, "mismatches": 0}
 
-    def check(idx):
+    def check(idx, lv=None, s=None):
         if trace is None or idx >= len(trace["batches"]):
             return
         ref = trace["batches"][idx]
-        lv = g.levels().cpu().numpy()
+        lv = g.levels().cpu().numpy() if lv is None else lv
         ok = digest(lv) == ref["sha"]
-        s = g.stats()
+        s = g.stats() if s is None else s
         for k in ("sweeps_ins", "sweeps_del", "moves_up", "moves_down", "applied_ins", "applied_del"):
             ok = ok and s[k] == ref[k]
         parity["batches_checked"] += 1
@@ -193,6 +193,7 @@ def main():
     per_kind = {"ins": [0, 0.0], "del": [0, 0.0], "mix": [0, 0.0]}
     lat = []
     tot = {"updates": 0, "alg_bytes": 0, "timed_ms": 0.0, "launches": 0, "sweeps": 0, "moves": 0}
+    snaps = []          # (batch index, device copy of the levels, stats) for the parity check after timing
     for r in range(rounds):
         timed = r >= args.warmup
         if timed and r == args.warmup:
@@ -215,7 +216,11 @@ def main():
                 tot["launches"] += s["timed_launches"]
                 tot["sweeps"] += s["sweeps_ins"] + s["sweeps_del"]
                 tot["moves"] += s["moves_up"] + s["moves_down"]
-            check(idx)
+                snaps.append((idx, g.levels(), s))
+                log(f"batch {idx} {kind}: {u} updates in {dt * 1e3:.2f} ms, sweeps {s['sweeps_ins'] + s['sweeps_del']}, "
+                    f"host syncs {s['host_syncs']}")
+            else:
+                check(idx)
             idx += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -223,6 +228,8 @@ def main():
     wall = t1 - t0
     value = tot["updates"] / wall
     log(f"timed: {tot['updates']} updates in {wall:.3f}s -> {value:.3e}/s")
+    for i, lv, s in snaps:
+        check(i, lv.cpu().numpy(), s)
 
     roof = None
     if tot["launches"] > 0 and tot["timed_ms"] > 0:

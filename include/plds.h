@@ -138,9 +138,9 @@ int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
 int plds_set_sweep_mode(plds_t *h, int32_t mode);
 
 /* Time one kernel of the level sweeps with HIP events recorded around each of
- * its launches (0 = off, 1 = insertion scan, 2 = deletion scan,
- * 3 = desire-level, 4 = insertion step preparation, 5 = insertion step
- * finish, 6 = the cooperative insertion sweep).  Results appear in plds_stats
+ * its launches (0 = off, 1 = insertion scan (which also finishes the
+ * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
+ * preparation, 5 = unused, 6 = the cooperative insertion sweep).  Results appear in plds_stats
  * (timed_launches, timed_ms). */
 int plds_set_timing(plds_t *h, int32_t kernel);
 

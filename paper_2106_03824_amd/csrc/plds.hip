@@ -39,10 +39,12 @@ constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels
 constexpr int kDlGrid = 1024;        // blocks of the desire-level kernel
 constexpr int kListGrid = 256;       // blocks of the per-mover list kernels
 constexpr int32_t kInf = INT32_MAX;
-// During an insertion step the movers carry this bit in level[] (set by the
-// step's preparation, cleared when they take their new level), so one gather
-// of a neighbour's level also tells whether it moves.
-constexpr int32_t kMoverBit = 1 << 30;
+// During an insertion step its movers carry a bit in level[] that depends on
+// the step's parity (set by the step's preparation, cleared by the next
+// one), so one gather of a neighbour's level also tells whether it moves.
+constexpr int32_t kMover0 = 1 << 30;   // mover of an insertion step of parity 0
+constexpr int32_t kMover1 = 1 << 29;   // mover of an insertion step of parity 1
+constexpr int32_t kLevelMask = (1 << 29) - 1;
 
 // error bits latched on device
 constexpr int32_t kErrRange = 1;     // id out of range
@@ -52,6 +54,16 @@ constexpr int32_t kErrOrder = 8;     // a desire-level not above the processed l
 constexpr int32_t kErrPool = 16;     // pool exhausted
 constexpr int32_t kErrHang = 32;     // a grid barrier wait gave up
 
+// State of one insertion step: the movers sit at level `phys` (the vertices
+// of that level that violate Invariant 1: its sorted candidates and its
+// marked vertices, kept in cascade list `cur`) and land at level l+1.
+// Normally phys == l; phys < l is a multi-level step (see ins_decide).
+// `fresh` marks the first step of a sweep (chosen by the seeding, not by a
+// decision).
+struct InsStep {
+    int32_t l, phys, jump, cur, done, fresh;
+};
+
 struct Ctl {
     int32_t l;            // level of the current step
     int32_t done;         // loop finished
@@ -60,9 +72,13 @@ struct Ctl {
     int32_t casc_n[2];    // cascade list sizes
     int32_t p_n[2];       // pending list sizes (deletion)
     int32_t n_chunks;     // work items of the current step
-    int32_t n_cls[4];     // movers per slab-size class
+    int32_t n_cls[4];     // movers per slab-size class (deletion work lists unused)
+    int32_t n_cls2[2][4]; // insertion: movers per slab-size class, by step parity
+    int32_t n_chunks2[2]; // insertion: large-slab work items, by step parity
     int32_t n_log;        // rows written to the step log in the current call
-    int32_t nmvb[2];      // movers of the step that consumed cascade list 0 / 1
+    int32_t nmvb[2];      // movers of the last insertion step of parity 0 / 1
+    InsStep st[2];        // insertion step state by step parity
+    int32_t pend_phys, pend_l1, pend_n;   // occupancy change of the last step, applied one kernel later
     int32_t n_rc;         // desire-level recomputations of the current step
     int32_t nm;           // running minimum of pending desire-levels
     int32_t blocks_done;  // last-block election
@@ -105,7 +121,9 @@ struct Dev {
     int32_t *occ;                     // [K+1] number of vertices at each level
     int32_t *lvl_fill;                // [K+1] scatter cursors
     int32_t *casc0, *casc1;           // [n]
-    int32_t *mv;                      // [n]
+    int32_t *mv;                      // [n] movers (deletion; insertion steps of parity 0)
+    int32_t *mv1;                     // [n] movers of insertion steps of parity 1
+    int64_t *sp;                      // [n] packed (stay << 32 | work items left) of insertion movers
     int32_t *cls[4];                  // [n] movers with slabs of <= 8, 16, 32, 64 slots
     int64_t *steplog;                 // [2K][4] per-step record of the last call
     int64_t *part;                    // [kSweepGrid][3] per-block statistics of a scan
@@ -135,6 +153,11 @@ __device__ __forceinline__ uint32_t home(int32_t key, int32_t cap) {
 }
 
 __device__ __forceinline__ int32_t wave_sum(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
@@ -245,6 +268,53 @@ __device__ __forceinline__ void bpush(int32_t *list, int32_t *n, int32_t cap, bo
 }
 
 
+// Block-staged append.  Lanes add entries to a queue in LDS (one LDS atomic
+// per wavefront); the block moves the queue to the global list with a single
+// atomic on the list's counter, when fewer than `room` free entries are left
+// or at the end (room = kStage).  Same-address atomics on a global counter
+// are serialised by the memory system, so a hot loop that appends from many
+// wavefronts pays one per block and flush instead of one per wavefront.
+constexpr int kStage = 4096;
+struct Stage {
+    int32_t n, base;
+    int32_t buf[kStage];
+};
+
+__device__ __forceinline__ void stage_init(Stage &q) {
+    if (threadIdx.x == 0) q.n = 0;
+    __syncthreads();
+}
+
+// every active lane calls it; lanes with `pred` stage x (the caller keeps
+// the number staged since the last flush under kStage)
+__device__ __forceinline__ void stage_push(Stage &q, bool pred, int32_t x) {
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    int lane = __lane_id();
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&q.n, __popcll(mask));
+    base = __shfl(base, leader, kWave);
+    if (pred) q.buf[base + __popcll(mask & ((1ull << lane) - 1))] = x;
+}
+
+// every thread of the block calls it (block-uniform control flow)
+__device__ void stage_flush(Stage &q, int32_t room, int32_t *list, int32_t *n, int32_t cap, Ctl *c) {
+    __syncthreads();
+    int32_t k = q.n;
+    __syncthreads();
+    if (k == 0 || k + room <= kStage) return;
+    if (threadIdx.x == 0) q.base = atomicAdd(n, k);
+    __syncthreads();
+    int32_t b = q.base;
+    if (b + k > cap && threadIdx.x == 0) latch(c, kErrLevel);
+    for (int i = threadIdx.x; i < k; i += blockDim.x)
+        if (b + i < cap) list[b + i] = q.buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) q.n = 0;
+    __syncthreads();
+}
+
 // ----------------------------------------------------------------- slabs
 __device__ bool slab_has(const int32_t *s, int32_t cap, int32_t key) {
     if (cap == 0) return false;
@@ -305,64 +375,103 @@ __global__ void k_range_check(const int32_t *e, int64_t cnt, int32_t n, Ctl *ctl
 // graph equals want_present (insertions: absent, deletions: present).
 __global__ void k_dedupe(Dev d, const int32_t *e, int64_t cnt, int want_present) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
-        int32_t a = e[2 * i], b = e[2 * i + 1];
-        if (a == b) continue;
-        int32_t u = min(a, b), v = max(a, b);
-        uint64_t key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
-        uint64_t j = mix64(key) & d.hmask;
-        bool fresh = false;
-        for (uint64_t p = 0; p <= d.hmask; p++) {
-            uint64_t x = d.hset[j];
-            if (x == key) break;
-            if (x == kEmpty64) {
-                uint64_t prev = atomicCAS((unsigned long long *)&d.hset[j], (unsigned long long)kEmpty64,
-                                          (unsigned long long)key);
-                if (prev == kEmpty64) {
-                    fresh = true;
-                    break;
+    int lane = threadIdx.x % kWave;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - lane; i0 < cnt; i0 += stride) {
+        int64_t i = i0 + lane;
+        bool keep = false;
+        int32_t u = 0, v = 0;
+        if (i < cnt) {
+            int32_t a = e[2 * i], b = e[2 * i + 1];
+            u = min(a, b);
+            v = max(a, b);
+            if (a != b) {
+                uint64_t key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
+                uint64_t j = mix64(key) & d.hmask;
+                bool fresh = false;
+                for (uint64_t p = 0; p <= d.hmask; p++) {
+                    uint64_t x = d.hset[j];
+                    if (x == key) break;
+                    if (x == kEmpty64) {
+                        uint64_t prev = atomicCAS((unsigned long long *)&d.hset[j], (unsigned long long)kEmpty64,
+                                                  (unsigned long long)key);
+                        if (prev == kEmpty64) {
+                            fresh = true;
+                            break;
+                        }
+                        if (prev == key) break;
+                    }
+                    j = (j + 1) & d.hmask;
                 }
-                if (prev == key) break;
+                if (fresh) {
+                    // probe the smaller slab of the two endpoints
+                    int32_t s = d.cap[u] <= d.cap[v] ? u : v, t = s == u ? v : u;
+                    bool present = slab_has(d.pool + d.off[s], d.cap[s], t);
+                    keep = (int)present == want_present;
+                }
             }
-            j = (j + 1) & d.hmask;
         }
-        if (!fresh) continue;
-        // probe the smaller slab of the two endpoints
-        int32_t s = d.cap[u] <= d.cap[v] ? u : v, t = s == u ? v : u;
-        bool present = slab_has(d.pool + d.off[s], d.cap[s], t);
-        if ((int)present != want_present) continue;
-        int32_t k = atomicAdd(&d.ctl->n_valid, 1);
-        d.valid[2 * k] = u;
-        d.valid[2 * k + 1] = v;
+        uint64_t mask = __ballot(keep);
+        if (mask == 0) continue;
+        int leader = __ffsll((unsigned long long)mask) - 1;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&d.ctl->n_valid, __popcll(mask));
+        base = __shfl(base, leader, kWave);
+        if (keep) {
+            int32_t k = base + __popcll(mask & ((1ull << lane) - 1));
+            d.valid[2 * k] = u;
+            d.valid[2 * k + 1] = v;
+        }
     }
 }
 
 // count new slots per endpoint; first touch records the vertex
 __global__ void k_touch(Dev d) {
     int32_t nv = d.ctl->n_valid;
-    int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * nv; i += stride) {
-        int32_t x = d.valid[i];
-        if (atomicAdd(&d.addc[x], 1) == 0) push(d.touch, &d.ctl->n_touch, d.n, x, d.ctl);
+    int stride = gridDim.x * blockDim.x, lane = threadIdx.x % kWave;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < 2 * nv; i0 += stride) {
+        int i = i0 + lane;
+        int32_t x = i < 2 * nv ? d.valid[i] : -1;
+        bool first = x >= 0 && atomicAdd(&d.addc[x], 1) == 0;
+        wpush(d.touch, &d.ctl->n_touch, d.n, first, x, d.ctl);
     }
 }
 
 // slabs that would exceed 80% occupancy are regrown to 60% of the new size
 __global__ void k_plan_growth(Dev d) {
     int32_t nt = d.ctl->n_touch;
-    int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
-        int32_t x = d.touch[i];
-        int64_t k = d.addc[x], c = d.cap[x];
-        if ((d.fill[x] + k) * 5 <= c * 4) continue;
-        int64_t live = d.deg[x] + k;
-        int64_t nc = (live * 5 + 2) / 3;
-        nc = ((std::max<int64_t>(nc, kMinCap) + 7) / 8) * 8;
-        if (nc > INT32_MAX / 2) latch(d.ctl, kErrPool);
-        int32_t g = atomicAdd(&d.ctl->n_grow, 1);
-        d.grow[g] = x;
-        d.newcap[g] = (int32_t)nc;
-        atomicAdd((unsigned long long *)&d.ctl->grow_req, (unsigned long long)nc);
+    int stride = gridDim.x * blockDim.x, lane = threadIdx.x % kWave;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < nt; i0 += stride) {
+        int i = i0 + lane;
+        bool grow = false;
+        int32_t x = -1, ncap = 0;
+        if (i < nt) {
+            x = d.touch[i];
+            int64_t k = d.addc[x], c = d.cap[x];
+            if ((d.fill[x] + k) * 5 > c * 4) {
+                int64_t live = d.deg[x] + k;
+                int64_t nc = (live * 5 + 2) / 3;
+                nc = ((std::max<int64_t>(nc, kMinCap) + 7) / 8) * 8;
+                if (nc > INT32_MAX / 2) {
+                    latch(d.ctl, kErrPool);
+                    nc = 8;
+                }
+                grow = true;
+                ncap = (int32_t)nc;
+            }
+        }
+        uint64_t mask = __ballot(grow);
+        if (mask == 0) continue;
+        int leader = __ffsll((unsigned long long)mask) - 1;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&d.ctl->n_grow, __popcll(mask));
+        base = __shfl(base, leader, kWave);
+        int64_t tot = wave_sum64(ncap);
+        if (lane == leader) atomicAdd((unsigned long long *)&d.ctl->grow_req, (unsigned long long)tot);
+        if (grow) {
+            int32_t g = base + __popcll(mask & ((1ull << lane) - 1));
+            d.grow[g] = x;
+            d.newcap[g] = ncap;
+        }
     }
 }
 
@@ -518,6 +627,13 @@ __global__ void k_level_scan(Dev d) {
         d.ctl->jump = 0;
         d.ctl->done = z >= K;
         d.ctl->cur = 0;
+        d.ctl->st[1] = InsStep{z, z, 0, 0, z >= K, 1};
+        d.ctl->pend_n = 0;
+        d.ctl->nmvb[0] = d.ctl->nmvb[1] = 0;
+        for (int q = 0; q < 2; q++) {
+            d.ctl->n_chunks2[q] = 0;
+            d.ctl->n_cls2[q][0] = d.ctl->n_cls2[q][1] = d.ctl->n_cls2[q][2] = d.ctl->n_cls2[q][3] = 0;
+        }
         d.ctl->casc_n[0] = d.ctl->casc_n[1] = 0;
         d.ctl->n_chunks = 0;
         d.ctl->n_cls[0] = d.ctl->n_cls[1] = d.ctl->n_cls[2] = d.ctl->n_cls[3] = 0;
@@ -540,12 +656,12 @@ __global__ void k_level_scatter(Dev d) {
 // Work items of a step: kChunk-slot pieces of the movers' slabs, appended
 // with one atomic per block.  Every thread of the block calls it; threads
 // with v < 0 add nothing.
-__device__ __forceinline__ void add_chunks_b(Dev &d, int32_t v, int32_t *sh) {
+__device__ __forceinline__ void add_chunks_b(Dev &d, int32_t v, int32_t *counter, int32_t *sh) {
     int32_t nch = v >= 0 ? (d.cap[v] + kChunk - 1) / kChunk : 0;
     int32_t total = 0;
     int32_t off = block_excl(nch, &total, sh);
     if (total == 0) return;
-    if (threadIdx.x == 0) sh[kBlock / kWave + 1] = atomicAdd(&d.ctl->n_chunks, total);
+    if (threadIdx.x == 0) sh[kBlock / kWave + 1] = atomicAdd(counter, total);
     __syncthreads();
     int32_t base = sh[kBlock / kWave + 1];
     __syncthreads();
@@ -575,18 +691,28 @@ __device__ __forceinline__ void add_chunks_w(Dev &d, int32_t v) {
     for (int32_t k = 0; k < nch; k++) d.chunks[base + off + k] = ((int64_t)v << 32) | (uint32_t)k;
 }
 
-// State of one insertion step: the movers sit at level `phys` (the vertices
-// of that level that violate Invariant 1: its sorted candidates and its
-// marked vertices, kept in cascade list `cur`) and land at level l+1.
-// Normally phys == l; phys < l is a multi-level step (see ins_decide).
-struct InsStep {
-    int32_t l, phys, jump, cur, done;
-};
 
-// Step of Algorithm 2, part 1: gather the movers, flag them in level[], and
-// sort them into work lists by slab size.  Returns false (on every block
+// Step of Algorithm 2, part 1 (step parity p): take the previous step's
+// flag off its movers, gather this step's movers, flag them with the
+// parity-p bit in level[], give each mover whose slab is cut into chunks its
+// packed (stay, chunks left) counter, and sort the movers into work lists by
+// slab size.  All level[] writes are plain stores: a previous mover that
+// moves again was already given the parity-p bit by the scan that finished
+// it, so the clearing (which keeps that bit) and the flagging write the same
+// value to it.  When `st.done`, only clears.  Returns false (on every block
 // alike) if the step is out of range.
-__device__ bool ins_prep_phase(Dev &d, const InsStep &st, int bid, int nblk, int32_t *sh) {
+__device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, int32_t *sh) {
+    int32_t Mp = p ? kMover1 : kMover0, Mq = p ? kMover0 : kMover1;
+    int stride = nblk * blockDim.x;
+    {
+        const int32_t *prev = p ? d.mv : d.mv1;
+        int32_t np = d.ctl->nmvb[p ^ 1];
+        for (int i = bid * blockDim.x + threadIdx.x; i < np; i += stride) {
+            int32_t u = prev[i];
+            d.level[u] = d.level[u] & ~Mq;
+        }
+    }
+    if (st.done) return true;
     int32_t l = st.l, phys = st.phys, cur = st.cur;
     if (phys < 0 || phys > l || l + 1 >= d.K) {
         if (bid == 0 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
@@ -599,46 +725,63 @@ __device__ bool ins_prep_phase(Dev &d, const InsStep &st, int bid, int nblk, int
         if (bid == 0 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
         return false;
     }
-    int stride = nblk * blockDim.x;
+    int32_t *mv = p ? d.mv1 : d.mv;
+    int32_t *ncls = d.ctl->n_cls2[p];
     for (int i0 = bid * blockDim.x; i0 < nA + nB; i0 += stride) {
         int i = i0 + threadIdx.x;
         int32_t v = -1, cl = -1;
         if (i < nA + nB) {
             v = i < nA ? d.sorted[a0 + i] : casc[i - nA];
-            d.mv[i] = v;
-            d.level[v] = phys | kMoverBit;
+            mv[i] = v;
+            d.level[v] = phys | Mp;
             int32_t cap = d.cap[v];
             cl = cap <= 8 ? 0 : cap <= 16 ? 1 : cap <= 32 ? 2 : cap <= 64 ? 3 : 4;
+            if (cl == 4) d.sp[v] = (cap + kChunk - 1) / kChunk;
         }
 #pragma unroll
-        for (int k = 0; k < 4; k++) bpush(d.cls[k], &d.ctl->n_cls[k], d.n, cl == k, v, d.ctl, sh);
-        add_chunks_b(d, cl == 4 ? v : -1, sh);
+        for (int k = 0; k < 4; k++) bpush(d.cls[k], &ncls[k], d.n, cl == k, v, d.ctl, sh);
+        add_chunks_b(d, cl == 4 ? v : -1, &d.ctl->n_chunks2[p], sh);
     }
-    if (bid == 0 && threadIdx.x == 0) d.ctl->nmvb[cur] = nA + nB;
+    if (bid == 0 && threadIdx.x == 0) d.ctl->nmvb[p] = nA + nB;
     return true;
 }
 
-// Part 2: every mover v scans its slab.  Neighbour w at level l stays iff it
-// is not itself a mover (every violator of level l moves); w at l+1 gains v
-// as up-neighbour (and, in a multi-level step, as up*-neighbour) and is
+// Part 2: every mover v scans its slab.  A neighbour flagged as a mover of
+// this step stays in v's up-set and is neither counted nor updated; a
+// neighbour w at level l stays behind (counted in v's `stay`); w at l+1 gains
+// v as up-neighbour (and, in a multi-level step, as up*-neighbour) and is
 // marked if that makes it exceed the cap of level l+1; w at l+2 gains v as
 // up*-neighbour.  Work items: movers with slabs of at most 8/16/32/64 slots
 // are served by lane groups of that width (8/4/2/1 movers per wavefront);
-// larger slabs are cut into kChunk-slot pieces, a wavefront each.  Per-block
-// statistics go to d.part[3*bid..] (stored, or added when `accum`).
-__device__ void ins_scan_phase(Dev &d, const InsStep &st, int bid, int nblk, bool accum) {
+// larger slabs are cut into kChunk-slot pieces, a wavefront each.  The work
+// item that completes a mover's slab finishes it (a lone item at once, a
+// chunked slab through one atomic on its packed counter): level l+1, up*(v)
+// = old up(v), up(v) = old up(v) - stay; a mover still above the cap of l+1
+// stays marked and also gets the next step's flag, since it moves again.
+// The flag of this step stays on, so other scans never touch its counters.
+// Per-block statistics go to d.part[3*bid..] (stored, or added when accum).
+__device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, bool accum) {
     int32_t l = st.l, nxt = st.cur ^ 1, jump = st.jump;
+    int32_t Mp = p ? kMover1 : kMover0, Mn = p ? kMover0 : kMover1;
     int32_t *casc = nxt ? d.casc1 : d.casc0;
     int32_t ub1 = d.up_max[(l + 1) / d.L];
-    int wid = (bid * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
-    int nw = nblk * blockDim.x / kWave;
-    int32_t n0 = d.ctl->n_cls[0], n1c = d.ctl->n_cls[1], n2 = d.ctl->n_cls[2], n3 = d.ctl->n_cls[3];
-    int32_t i0 = (n0 + 7) / 8, i1 = (n1c + 3) / 4, i2 = (n2 + 1) / 2, i3 = n3, i4 = d.ctl->n_chunks;
+    int lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
+    int nw = nblk * wpb;
+    const int32_t *ncls = d.ctl->n_cls2[p];
+    int32_t n0 = ncls[0], n1c = ncls[1], n2 = ncls[2], n3 = ncls[3];
+    int32_t i0 = (n0 + 7) / 8, i1 = (n1c + 3) / 4, i2 = (n2 + 1) / 2, i3 = n3, i4 = d.ctl->n_chunks2[p];
     int32_t total = i0 + i1 + i2 + i3 + i4;
     int32_t scanned = 0, nU = 0, n1 = 0;
-    for (int t = wid; t < total; t += nw) {
-        int cl;
-        int32_t tl = t;
+    // pushes of one round: per wavefront up to kChunk neighbours plus 8 movers
+    const int32_t room = wpb * (kChunk + kWave / 8);
+    __shared__ Stage q_casc;
+    stage_init(q_casc);
+    // rounds are block-uniform (every wavefront of the block runs the same
+    // number), so the staged pushes can be flushed between rounds
+    for (int tb = bid * wpb; tb < total; tb += nw) {
+        int32_t t = tb + threadIdx.x / kWave;
+        int cl = 0;
+        int32_t tl = t < total ? t : INT32_MAX;
         if (tl < i0) cl = 0;
         else if ((tl -= i0) < i1) cl = 1;
         else if ((tl -= i1) < i2) cl = 2;
@@ -647,10 +790,13 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int bid, int nblk, boo
             tl -= i3;
             cl = 4;
         }
+        if (t >= total) cl = 0;
         int W = cl == 4 ? kWave : (8 << cl);
         int grp = lane / W, q = lane % W;
         int32_t v = -1, lo = 0, hi = 0;
-        if (cl < 4) {
+        if (t >= total) {
+            // no work item for this wavefront in the last round
+        } else if (cl < 4) {
             int32_t ncl = cl == 0 ? n0 : cl == 1 ? n1c : cl == 2 ? n2 : n3;
             int32_t j = tl * (kWave / W) + grp;
             if (j < ncl) {
@@ -670,10 +816,10 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int bid, int nblk, boo
             int32_t e = lo + it * W + q;
             int32_t w = v >= 0 && e < hi ? s[e] : -1;
             int32_t raw = w >= 0 ? d.level[w] : -1;
+            bool comover = w >= 0 && (raw & Mp);
+            int32_t lw = (w < 0 || comover) ? -1 : (raw & kLevelMask);
             bool cross = false;
-            // a fellow mover stays in v's up-set; it is neither counted nor updated
-            int32_t lw = (raw & kMoverBit) ? -1 : raw;
-            nU += lw >= l || (raw >= 0 && (raw & kMoverBit));
+            nU += comover || lw >= l;
             if (lw == l) {
                 stay++;
             } else if (lw == l + 1) {
@@ -684,12 +830,33 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int bid, int nblk, boo
             } else if (lw == l + 2) {
                 atomicAdd(&d.ups[w], 1);
             }
-            wpush(casc, &d.ctl->casc_n[nxt], d.n, cross, w, d.ctl);
+            stage_push(q_casc, cross, w);
         }
         if (v >= 0) scanned += (q == 0) ? hi - lo : 0;
         for (int o = W / 2; o > 0; o >>= 1) stay += __shfl_xor(stay, o, kWave);
-        if (q == 0 && v >= 0 && stay) atomicAdd(&d.stay[v], stay);
+        bool viol = false;
+        if (q == 0 && v >= 0) {
+            bool last = true;
+            int32_t total_stay = stay;
+            if (cl == 4) {
+                unsigned long long delta = ((unsigned long long)(uint32_t)stay << 32) - 1ull;
+                unsigned long long old = atomicAdd((unsigned long long *)&d.sp[v], delta);
+                last = (old & 0xffffffffull) == 1;
+                total_stay += (int32_t)(old >> 32);
+            }
+            if (last) {
+                int32_t u = d.up[v];
+                d.ups[v] = u;
+                u -= total_stay;
+                d.up[v] = u;
+                viol = u > ub1;
+                d.level[v] = (l + 1) | Mp | (viol ? Mn : 0);
+            }
+        }
+        stage_push(q_casc, viol, v);
+        stage_flush(q_casc, room, casc, &d.ctl->casc_n[nxt], d.n, d.ctl);
     }
+    stage_flush(q_casc, kStage, casc, &d.ctl->casc_n[nxt], d.n, d.ctl);
     __shared__ int32_t red[3][kBlock / kWave];
     nU = wave_sum(nU);
     n1 = wave_sum(n1);
@@ -709,32 +876,6 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int bid, int nblk, boo
     __syncthreads();
 }
 
-// Part 3: movers take level l+1 with up*(v) = old up(v) and up(v) = old up(v)
-// minus the neighbours that stayed at l; a mover still above the cap of l+1
-// stays marked.
-__device__ void ins_fin_phase(Dev &d, const InsStep &st, int bid, int nblk, int32_t *sh) {
-    int32_t l = st.l, nxt = st.cur ^ 1, nmv = d.ctl->nmvb[st.cur];
-    int32_t *casc = nxt ? d.casc1 : d.casc0;
-    int32_t ub1 = d.up_max[(l + 1) / d.L];
-    int stride = nblk * blockDim.x;
-    for (int i0 = bid * blockDim.x; i0 < nmv; i0 += stride) {
-        int i = i0 + threadIdx.x;
-        bool viol = false;
-        int32_t v = -1;
-        if (i < nmv) {
-            v = d.mv[i];
-            d.level[v] = l + 1;
-            int32_t u = d.up[v];
-            d.ups[v] = u;
-            u -= d.stay[v];
-            d.stay[v] = 0;
-            d.up[v] = u;
-            viol = u > ub1;
-        }
-        bpush(casc, &d.ctl->casc_n[nxt], d.n, viol, v, d.ctl, sh);
-    }
-}
-
 // Part 4: the next step after step `st` (every thread of a block calls it and
 // gets the same answer).  The next movers sit at level z0: the marked
 // vertices at l+1, else the next level with sorted candidates.  If they are
@@ -751,6 +892,7 @@ __device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn
     nx.cur = st.cur ^ 1;
     nx.jump = 0;
     nx.done = 0;
+    nx.fresh = 0;
     int32_t l = st.l;
     int32_t z0 = cn > 0 ? l + 1 : (l + 1 < d.K ? d.next_nz[l + 1] : d.K);
     if (z0 >= d.K - 1) {       // nothing left (no vertex of the top group can violate Invariant 1)
@@ -841,46 +983,65 @@ __device__ __forceinline__ void ins_store(Ctl *c, const InsStep &nx) {
     c->done = nx.done;
 }
 
-__device__ __forceinline__ InsStep ins_load(const Ctl *c) { return InsStep{c->l, c->phys, c->jump, c->cur, c->done}; }
+__device__ __forceinline__ InsStep ins_load(const Ctl *c) {
+    return InsStep{c->l, c->phys, c->jump, c->cur, c->done, 0};
+}
 
-// ---- one kernel per part (used when a cooperative launch is not available)
-__global__ void k_ins_prep(Dev d) {
+// ---- one kernel per part.  A step of parity p is two kernels: decide+prep
+// and scan.  Kernels of parity p read the step state st[p]; decide+prep
+// computes it from st[p^1] (the previous step, or the seeding's first step)
+// in every block alike and block 0 stores it, so no block reads a slot that
+// is written during the same kernel.  Block 0 also does the previous step's
+// bookkeeping and resets the work-list counters of parity p^1; the step's
+// occupancy change is applied by the next kernel (the scan), when no block
+// reads occ any more.
+__global__ void k_ins_prep(Dev d, int p) {
     __shared__ int32_t sh[kBlock / kWave + 2];
-    InsStep st = ins_load(d.ctl);
-    if (st.done) return;
-    ins_prep_phase(d, st, blockIdx.x, gridDim.x, sh);
-}
-
-__global__ void k_ins_scan(Dev d) {
-    InsStep st = ins_load(d.ctl);
-    if (st.done) return;
-    ins_scan_phase(d, st, blockIdx.x, gridDim.x, false);
-}
-
-__global__ void k_ins_fin(Dev d) {
-    __shared__ int32_t sh[kBlock / kWave + 2];
-    InsStep st = ins_load(d.ctl);
-    if (st.done) return;
-    ins_fin_phase(d, st, blockIdx.x, gridDim.x, sh);
-}
-
-__global__ void k_ins_next(Dev d, int nparts) {
     __shared__ int32_t sh1[2];
     Ctl *c = d.ctl;
-    InsStep st = ins_load(c);
-    if (st.done) return;
-    int32_t nmv = c->nmvb[st.cur], cn = c->casc_n[st.cur ^ 1];
-    InsStep nx = ins_decide(d, st, nmv, cn, sh1);
-    int64_t sums[3];
-    sum_parts(d, nparts, sums);
-    if (threadIdx.x == 0) {
-        ins_account(d, st, nmv, sums);
-        d.occ[st.phys] -= nmv;
-        d.occ[st.l + 1] += nmv;
-        c->n_chunks = 0;
-        c->n_cls[0] = c->n_cls[1] = c->n_cls[2] = c->n_cls[3] = 0;
-        ins_store(c, nx);
+    const bool b0 = blockIdx.x == 0, writer = b0 && threadIdx.x == 0;
+    InsStep prv = c->st[p ^ 1];
+    if (prv.done) {
+        if (writer) c->st[p] = prv;
+        return;
     }
+    InsStep cur;
+    if (prv.fresh) {
+        cur = prv;
+        cur.fresh = 0;
+    } else {
+        int32_t nmv = c->nmvb[p ^ 1], cn = c->casc_n[prv.cur ^ 1];
+        cur = ins_decide(d, prv, nmv, cn, sh1);
+        if (b0) {
+            int64_t sums[3];
+            sum_parts(d, kSweepGrid, sums);
+            if (writer) {
+                ins_account(d, prv, nmv, sums);
+                c->pend_phys = prv.phys;
+                c->pend_l1 = prv.l + 1;
+                c->pend_n = nmv;
+            }
+        }
+    }
+    if (writer) {
+        c->st[p] = cur;
+        ins_store(c, cur);
+        c->n_chunks2[p ^ 1] = 0;
+        c->n_cls2[p ^ 1][0] = c->n_cls2[p ^ 1][1] = c->n_cls2[p ^ 1][2] = c->n_cls2[p ^ 1][3] = 0;
+    }
+    ins_prep_phase(d, cur, p, blockIdx.x, gridDim.x, sh);
+}
+
+__global__ void k_ins_scan(Dev d, int p) {
+    Ctl *c = d.ctl;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && c->pend_n) {
+        d.occ[c->pend_phys] -= c->pend_n;
+        d.occ[c->pend_l1] += c->pend_n;
+        c->pend_n = 0;
+    }
+    InsStep st = c->st[p];
+    if (st.done) return;
+    ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, false);
 }
 
 // ---- the whole level loop in one cooperative launch
@@ -929,11 +1090,11 @@ __device__ bool grid_sync(Bar *b, unsigned nblk) {
     return !ab;
 }
 
-// Every step is prep | scan | fin with a grid barrier after each part; the
+// Every step is prep | scan with a grid barrier after each part; the
 // decision for the next step is taken by every block on its own (same inputs,
 // same answer) at the start of the next iteration.  Block 0 does the
 // bookkeeping, applies each step's occupancy change one phase later (when no
-// block reads occ), and resets the work-list counters during fin.
+// block reads occ) and resets the work-list counters of the other parity.
 __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
     __shared__ int32_t sh[kBlock / kWave + 2];
     __shared__ int32_t sh1[2];
@@ -943,6 +1104,7 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
     InsStep st = ins_load(c);
     InsStep prev{};
     int32_t prev_nmv = 0;
+    int p = 0;
     bool have_prev = false, occ_pending = false;
     while (true) {
         if (have_prev) {
@@ -951,31 +1113,28 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
             if (writer) {
                 ins_account(d, prev, prev_nmv, nullptr);
                 ins_store(c, st);
+                c->n_chunks2[p ^ 1] = 0;
+                c->n_cls2[p ^ 1][0] = c->n_cls2[p ^ 1][1] = c->n_cls2[p ^ 1][2] = c->n_cls2[p ^ 1][3] = 0;
             }
             occ_pending = true;
         }
-        if (st.done) break;
-        if (!ins_prep_phase(d, st, bid, nblk, sh)) {
+        if (!ins_prep_phase(d, st, p, bid, nblk, sh)) {
             if (writer) c->done = 1;
             break;
         }
+        if (st.done) break;
         if (!grid_sync(bar, nblk)) break;
         if (writer && occ_pending) {
             d.occ[prev.phys] -= prev_nmv;
             d.occ[prev.l + 1] += prev_nmv;
             occ_pending = false;
         }
-        ins_scan_phase(d, st, bid, nblk, true);
+        ins_scan_phase(d, st, p, bid, nblk, true);
         if (!grid_sync(bar, nblk)) break;
-        if (writer) {
-            c->n_chunks = 0;
-            c->n_cls[0] = c->n_cls[1] = c->n_cls[2] = c->n_cls[3] = 0;
-        }
-        ins_fin_phase(d, st, bid, nblk, sh);
-        if (!grid_sync(bar, nblk)) break;
-        prev_nmv = c->nmvb[st.cur];
+        prev_nmv = c->nmvb[p];
         prev = st;
         have_prev = true;
+        p ^= 1;
     }
     if (writer && occ_pending) {
         d.occ[prev.phys] -= prev_nmv;
@@ -1388,6 +1547,12 @@ struct plds {
     int sweep_mode = 1;          // 0: cooperative when possible, 1: one kernel per part
     int coop_blocks = -1;        // -1 = not yet determined
     Bar *bar = nullptr;
+    // the insertion step sequence as a prebuilt graph of kGraphSteps steps
+    hipGraph_t ins_graph = nullptr;
+    hipGraphExec_t ins_exec = nullptr;
+    Dev ins_graph_dev{};
+    int par[2] = {0, 1};
+    int ins_graph_timed = -1;
     // optional event timing of one sweep kernel
     int32_t timed_kind = 0;
     std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -1464,8 +1629,12 @@ void free_all(plds *h) {
         dfree(d.oldcap);
     dfree(d.cand), dfree(d.sorted), dfree(d.lvl_cnt), dfree(d.lvl_start), dfree(d.next_nz), dfree(d.occ), dfree(d.lvl_fill), dfree(d.steplog), dfree(d.part);
     for (int k = 0; k < 4; k++) dfree(d.cls[k]);
-    dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
+    dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.mv1), dfree(d.sp), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
     dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
+    if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
+    if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
+    h->ins_exec = nullptr;
+    h->ins_graph = nullptr;
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     h->ev.clear();
@@ -1488,11 +1657,10 @@ inline void tstop(plds *h, int kind, hipStream_t s) {
     h->ev_used++;
 }
 
-int sync_ctl(plds *h, hipStream_t s) {
-    HIPCHK(hipMemcpyAsync(h->h_ctl, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    h->stats.host_syncs++;
-    for (int i = 0; i < h->ev_used; i++) {
+// Add the durations of the first `count` recorded launches (the ones that
+// did work) to the statistics and free the event pairs.  After sync only.
+void take_timing(plds *h, int count) {
+    for (int i = 0; i < std::min(count, h->ev_used); i++) {
         float ms = 0;
         if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
             h->stats.timed_ms += ms;
@@ -1500,6 +1668,12 @@ int sync_ctl(plds *h, hipStream_t s) {
         }
     }
     h->ev_used = 0;
+}
+
+int sync_ctl(plds *h, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(h->h_ctl, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->stats.host_syncs++;
     return PLDS_OK;
 }
 
@@ -1587,6 +1761,10 @@ int ctl_reset_batch(plds *h, hipStream_t s) {
     c->p_n[0] = c->p_n[1] = 0;
     c->n_chunks = c->n_rc = 0;
     c->n_cls[0] = c->n_cls[1] = c->n_cls[2] = c->n_cls[3] = 0;
+    for (int q = 0; q < 2; q++) {
+        c->n_chunks2[q] = 0;
+        c->n_cls2[q][0] = c->n_cls2[q][1] = c->n_cls2[q][2] = c->n_cls2[q][3] = 0;
+    }
     c->nm = kInf;
     c->blocks_done = 0;
     c->sweeps = c->moves = c->scanned = c->dl_calcs = 0;
@@ -1649,6 +1827,59 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
     return PLDS_OK;
 }
 
+constexpr int kGraphSteps = 16;
+
+// The insertion step sequence (prep, scan, fin, next) x kGraphSteps as one
+// graph of kernel nodes, rebuilt when the device buffers move.  With timing
+// of the scan (kind 1), event record nodes bracket every scan node.
+int ins_graph(plds *h) {
+    int timed = h->timed_kind == 1 ? 1 : 0;
+    if (h->ins_exec && timed == h->ins_graph_timed && !memcmp(&h->ins_graph_dev, &h->d, sizeof(Dev))) return 0;
+    if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
+    if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
+    h->ins_exec = nullptr;
+    h->ins_graph = nullptr;
+    h->ins_graph_dev = h->d;
+    h->ins_graph_timed = timed;
+    if (hipGraphCreate(&h->ins_graph, 0) != hipSuccess) return PLDS_EHIP;
+    Dev *dv = &h->ins_graph_dev;
+    void *a0[] = {(void *)dv, (void *)&h->par[0]};
+    void *a1[] = {(void *)dv, (void *)&h->par[1]};
+    struct K {
+        const void *f;
+        int grid;
+    } ks[2] = {{(const void *)k_ins_prep, kListGrid}, {(const void *)k_ins_scan, kSweepGrid}};
+    hipGraphNode_t prev = nullptr;
+    for (int i = 0; i < kGraphSteps; i++) {
+        for (int k = 0; k < 2; k++) {
+            hipGraphNode_t node;
+            if (timed && k == 1) {
+                if (hipGraphAddEventRecordNode(&node, h->ins_graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                               h->ev[2 * i]) != hipSuccess)
+                    return PLDS_EHIP;
+                prev = node;
+            }
+            hipKernelNodeParams p{};
+            p.func = const_cast<void *>(ks[k].f);
+            p.gridDim = dim3(ks[k].grid);
+            p.blockDim = dim3(kBlock);
+            p.sharedMemBytes = 0;
+            p.kernelParams = (i & 1) ? a1 : a0;
+            p.extra = nullptr;
+            if (hipGraphAddKernelNode(&node, h->ins_graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+                return PLDS_EHIP;
+            prev = node;
+            if (timed && k == 1) {
+                if (hipGraphAddEventRecordNode(&node, h->ins_graph, &prev, 1, h->ev[2 * i + 1]) != hipSuccess)
+                    return PLDS_EHIP;
+                prev = node;
+            }
+        }
+    }
+    if (hipGraphInstantiate(&h->ins_exec, h->ins_graph, nullptr, nullptr, 0) != hipSuccess) return PLDS_EHIP;
+    return 0;
+}
+
 // Blocks of the cooperative sweep: up to 4 resident blocks per compute unit
 // (fewer if the occupancy calculator says so), at most kSweepGrid.
 int coop_blocks(plds *h) {
@@ -1696,32 +1927,41 @@ int insertion_sweep(plds *h, hipStream_t s) {
         } else {
             rc = sync_ctl(h, s);
             if (rc) return rc;
+            take_timing(h, 1);
         }
     }
-    int run = 8;
     int64_t steps = 0;
+    bool use_graph = h->timed_kind != 4;
+    int run = use_graph ? kGraphSteps : 8;
     while (!h->h_ctl->done && !h->h_ctl->err) {
         if (steps > (int64_t)h->K + 1) {    // each step raises the level: at most K steps
             h->broken = true;
             return PLDS_ESTATE;
         }
-        steps += run;
-        for (int i = 0; i < run; i++) {
-            tstart(h, 4, s);
-            hipLaunchKernelGGL(k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d);
-            tstop(h, 4, s);
-            tstart(h, 1, s);
-            hipLaunchKernelGGL(k_ins_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
-            tstop(h, 1, s);
-            tstart(h, 5, s);
-            hipLaunchKernelGGL(k_ins_fin, dim3(kListGrid), dim3(kBlock), 0, s, d);
-            tstop(h, 5, s);
-            hipLaunchKernelGGL(k_ins_next, dim3(1), dim3(kBlock), 0, s, d, kSweepGrid);
+        int32_t log0 = h->h_ctl->n_log;
+        if (use_graph) {
+            rc = ins_graph(h);
+            if (rc) return rc;
+            if (h->timed_kind == 1) h->ev_used = kGraphSteps;
+            HIPCHK(hipGraphLaunch(h->ins_exec, s));
+            steps += kGraphSteps;
+        } else {
+            steps += run;
+            for (int i = 0; i < run; i++) {      // run is even: every run starts at parity 0
+                int par = i & 1;
+                tstart(h, 4, s);
+                hipLaunchKernelGGL(k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d, par);
+                tstop(h, 4, s);
+                tstart(h, 1, s);
+                hipLaunchKernelGGL(k_ins_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d, par);
+                tstop(h, 1, s);
+            }
+            run = std::min(run * 2, 256);
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
-        run = std::min(run * 2, 256);
+        take_timing(h, h->h_ctl->n_log - log0);   // steps that did work
     }
     Ctl *c = h->h_ctl;
     h->stats.sweeps_ins += c->sweeps;
@@ -1745,6 +1985,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
     HIPCHK(hipGetLastError());
     int rc = sync_ctl(h, s);
     if (rc) return rc;
+    take_timing(h, h->ev_used);
     h->stats.viol_del0 = h->h_ctl->p_n[0];
     int run = 4;
     int64_t steps = 0;
@@ -1753,6 +1994,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
             h->broken = true;
             return PLDS_ESTATE;
         }
+        int32_t log0 = h->h_ctl->n_log;
         steps += run;
         for (int i = 0; i < run; i++) {
             hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
@@ -1768,6 +2010,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
+        take_timing(h, h->h_ctl->n_log - log0);   // steps that did work
         run = std::min(run * 2, 128);
     }
     Ctl *c = h->h_ctl;
@@ -1818,7 +2061,7 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
         return PLDS_EHIP;
     }
     build_tables(h, levels_per_group);
-    if ((int64_t)h->G * h->L > INT32_MAX / 2) {
+    if ((int64_t)h->G * h->L >= (int64_t)kLevelMask) {   // levels must fit under the mover flags
         delete h;
         return PLDS_EINVAL;
     }
@@ -1839,7 +2082,7 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
     rc |= dalloc(&d.lvl_cnt, h->K + 1) | dalloc(&d.lvl_start, h->K + 1) | dalloc(&d.next_nz, h->K + 1);
     rc |= dalloc(&d.occ, h->K + 1) | dalloc(&d.lvl_fill, h->K + 1);
     rc |= dalloc(&d.steplog, 8 * (int64_t)h->K) | dalloc(&d.part, 3 * kSweepGrid);
-    rc |= dalloc(&d.casc0, n) | dalloc(&d.casc1, n) | dalloc(&d.mv, n);
+    rc |= dalloc(&d.casc0, n) | dalloc(&d.casc1, n) | dalloc(&d.mv, n) | dalloc(&d.mv1, n) | dalloc(&d.sp, n);
     for (int k = 0; k < 4; k++) rc |= dalloc(&d.cls[k], n);
     rc |= dalloc(&d.p0, n) | dalloc(&d.p1, n) | dalloc(&d.rc, n);
     rc |= dalloc(&h->newoff, n) | dalloc(&h->bad, 8);
@@ -1876,6 +2119,7 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
               hipMemsetAsync(d.addc, 0, n * sizeof(int32_t), s) == hipSuccess &&
               hipMemsetAsync(d.dl, 0xff, n * sizeof(int32_t), s) == hipSuccess &&
               hipMemsetAsync(d.rcstamp, 0xff, n * sizeof(int32_t), s) == hipSuccess &&
+              hipMemsetAsync(d.sp, 0, n * sizeof(int64_t), s) == hipSuccess &&
               hipMemsetAsync(d.occ, 0, (h->K + 1) * sizeof(int32_t), s) == hipSuccess &&
               hipMemcpy(d.occ, &n32, sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(d.ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) == hipSuccess &&
@@ -2110,6 +2354,7 @@ int plds_load_state(plds_t *h, const int32_t *edges, int64_t m, const int32_t *l
     HIPCHK(hipMemsetAsync(d.addc, 0, n4, s));
     HIPCHK(hipMemsetAsync(d.stay, 0, n4, s));
     HIPCHK(hipMemsetAsync(d.cnt2, 0, n4, s));
+    HIPCHK(hipMemsetAsync(d.sp, 0, h->n * sizeof(int64_t), s));
     HIPCHK(hipMemsetAsync(d.dl, 0xff, n4, s));
     hipLaunchKernelGGL(k_set_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d, levels);
     HIPCHK(hipMemsetAsync(d.occ, 0, (h->K + 1) * sizeof(int32_t), s));

@@ -35,7 +35,7 @@ class plds_stats_t(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS[:-1]] + [("timed_ms", ctypes.c_double),
                                                                    ("reserved", ctypes.c_int64)]
 
-TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "ins_fin": 5, "ins_sweep": 6}
+TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "ins_sweep": 6}
 
 
 _lib = None
@@ -191,7 +191,7 @@ def plds_set_sweep_mode(h, mode):
 
 
 def plds_set_timing(h, kernel):
-    k = TIMED_KERNELS.get(kernel, kernel) if isinstance(kernel, str) else int(kernel)
+    k = int(TIMED_KERNELS.get(kernel, kernel)) if isinstance(kernel, str) else int(kernel)
     return _chk(lib().plds_set_timing(h, k), "plds_set_timing")
 
 

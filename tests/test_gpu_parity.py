@@ -42,9 +42,14 @@ STAT_KEYS = (("applied_ins", "applied_ins"), ("applied_del", "applied_del"), ("s
 class Pair:
     """A GPU handle and an oracle fed the same batches."""
 
-    def __init__(self, n, delta=0.4, lam=3.0, L=0, sweep_mode=0):
+    def __init__(self, n, delta=0.4, lam=3.0, L=0, sweep_mode=1):
+        """sweep_mode 0: one cooperative launch; 1: prebuilt graph of step
+        kernels; 2: step kernels launched one by one (what kernel timing of
+        the preparation kernel selects)."""
         self.g = lib().PLDS(n, delta, lam, L)
-        lib().plds_set_sweep_mode(self.g.h, sweep_mode)
+        lib().plds_set_sweep_mode(self.g.h, min(sweep_mode, 1))
+        if sweep_mode == 2:
+            lib().plds_set_timing(self.g.h, "ins_prep")
         self.o = O.Oracle(n, delta, lam, L)
         self.n = n
 
@@ -152,7 +157,7 @@ def test_random_small(seed):
     L = rng.choice([0, 0, 2, 3])
     delta, lam = rng.choice([(0.4, 3.0), (1.0, 3.0), (0.2, 6.0)])
     say("random small", seed, n, L, delta, lam)
-    p = Pair(n, delta, lam, L, sweep_mode=seed % 2)
+    p = Pair(n, delta, lam, L, sweep_mode=seed % 3)
     for it in range(6):
         ins = [(rng.randrange(n), rng.randrange(n)) for _ in range(rng.randrange(0, 4 * n))]
         cur = p.o.edges().tolist()
@@ -180,7 +185,7 @@ def test_rmat_tiny_config():
     p.step(ins=W.new_pairs(n, cur, 5000, 1003), dele=W.sample_edges(cur, 5000, 1004))
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_rmat_multi_batch(mode):
     """RMAT scale 14, edge factor 16, built in 4 insertion batches, then mixed
     and deletion batches, each compared with the oracle; both ways of running
