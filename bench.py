@@ -18,6 +18,15 @@ CPU oracle (one core) timed on a bounded sample of the same stream (one
 deletion and one mixed batch of 1e6 from the post-build state).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+With --scale 24 (or any scale other than 20) it runs the large streamed
+workload instead: an R-MAT graph of that scale with 16*2^scale unique edges
+(seed 1), streamed as insertion batches of --batch edges in a seeded random
+permutation (seed 3001), then two deletion batches of --batch sampled
+existing edges and one mixed batch; every batch is timed and the value is all
+applied updates over the wall time of the whole stream.
+
+    python bench.py --scale 24 [--batch 1000000]
 """
 import argparse
 import hashlib
@@ -142,6 +151,8 @@ def main():
         print(json.dumps({"copy_bytes": COPY_BYTES, "note": "one device-to-device copy kernel, read+write"}))
         return
     dev = torch.device("cuda", 0)
+    if args.scale != 20:
+        return run_stream(args, P, W, torch, np)
     scale, B = args.scale, args.batch
     m0 = 16 * 2 ** scale
     log("generating R-MAT", scale, m0)
@@ -258,6 +269,87 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def roofline(tot, kernel):
+    if tot["launches"] <= 0 or tot["timed_ms"] <= 0:
+        return None
+    avg_ms = tot["timed_ms"] / tot["launches"]
+    per_launch = tot["alg_bytes"] / tot["launches"]
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_" + kernel,
+            "avg_launch_us": round(avg_ms * 1e3, 3), "launches": tot["launches"],
+            "alg_bytes_per_launch": round(per_launch, 1)}
+
+
+def run_stream(args, P, W, torch, np):
+    """Large streamed workload: build by timed insertion batches, then
+    deletion and mixed batches, all timed."""
+    scale, B = args.scale, args.batch
+    n, m0 = 2 ** scale, 16 * 2 ** scale
+    t = time.perf_counter()
+    e = W.rmat(scale, m0, seed=1)
+    log(f"R-MAT {scale}: {m0} edges in {time.perf_counter() - t:.1f}s")
+    perm = W.permute_edges(e, 1000 * 3 + 1)
+    dels = W.sample_edges(e, 2 * B + B // 2, 1000 * 3 + 100)
+    mix_ins = W.new_pairs(n, e, B - B // 2, 1000 * 3 + 101)
+    del e
+    dev = torch.device("cuda", 0)
+    perm_d = torch.from_numpy(perm).to(dev)
+    del perm
+    dels_d = torch.from_numpy(dels).to(dev)
+    mix_ins_d = torch.from_numpy(mix_ins).to(dev)
+    plan = [("ins", perm_d[i:i + B], None) for i in range(0, m0, B)]
+    plan += [("del", None, dels_d[:B]), ("del", None, dels_d[B:2 * B]), ("mix", mix_ins_d, dels_d[2 * B:])]
+    g = P.PLDS(n, 0.4, 3.0, 0, 2 * m0)
+    log(f"batches ready: {len(plan)}")
+    P.plds_set_timing(g.h, args.kernel)
+    per_kind = {"ins": [0, 0.0], "del": [0, 0.0], "mix": [0, 0.0]}
+    tot = {"updates": 0, "alg_bytes": 0, "timed_ms": 0.0, "launches": 0}
+    sweeps, lat = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (kind, ins, dele) in enumerate(plan):
+        tb = time.perf_counter()
+        P.plds_update(g.h, ins, dele)
+        dt = time.perf_counter() - tb
+        s = g.stats()
+        u = s["applied_ins"] + s["applied_del"]
+        per_kind[kind][0] += u
+        per_kind[kind][1] += dt
+        lat.append(dt)
+        tot["updates"] += u
+        tot["alg_bytes"] += s["alg_bytes_up"]
+        tot["timed_ms"] += s["timed_ms"]
+        tot["launches"] += s["timed_launches"]
+        sweeps.append(s["sweeps_ins"] + s["sweeps_del"])
+        if i % 16 == 0 or kind != "ins":
+            log(f"batch {i} {kind}: {u} updates in {dt * 1e3:.2f} ms, sweeps {sweeps[-1]}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    P.plds_set_timing(g.h, 0)
+    value = tot["updates"] / wall
+    log(f"timed: {tot['updates']} updates in {wall:.3f}s -> {value:.3e}/s")
+    rc = g.check()
+    lat_ms = sorted(x * 1e3 for x in lat)
+    info = g.info()
+    out = {
+        "metric": METRIC, "value": value, "unit": "edge updates/s", "n_gpus": 1, "steps": len(plan), "warmup": 0,
+        "ms_per_step": wall / len(plan) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"rmat{scale}-ef16-streamed-ins{B}-then-2del-1mix", "n": n, "m0": m0, "delta": 0.4,
+                   "lambda": 3.0, "batch": B, "K": info["K"],
+                   "step": "one batch: the insertion stream of the whole graph, then deletions and a mixed batch"},
+        "rates": {k: (v[0] / v[1] if v[1] else None) for k, v in per_kind.items()},
+        "batch_latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1,
+                                                                              int(0.99 * len(lat_ms)))]},
+        "sweeps_per_insert_batch": {"mean": float(np.mean(sweeps[:-3])), "max": int(np.max(sweeps[:-3]))},
+        "roofline": roofline(tot, args.kernel),
+        "device_check": rc,
+        "slab_slots": info["slab_slots"],
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -20,9 +20,12 @@
  *   sample    uniform sample without replacement from an edge list.
  */
 #include <math.h>
+#include <pthread.h>
+#include <stdatomic.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 static inline uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -97,10 +100,25 @@ int wl_permutation(int64_t n, uint64_t seed, uint64_t stream, int32_t *perm) {
     return 0;
 }
 
-/* R-MAT with `m` unique undirected edges on 2^scale vertices.  out: [m][2].
- * Returns the number of candidates drawn, or -1. */
-int64_t wl_rmat(int32_t scale, int64_t m, double a, double b, double c, uint64_t seed, int32_t relabel,
-                int32_t *out) {
+/* Candidate i of an R-MAT stream: `scale` quadrant choices, one draw each. */
+static inline void rmat_cand(uint64_t key, int32_t scale, uint64_t i, double a, double ab, double abc,
+                             int32_t *uo, int32_t *vo) {
+    int32_t u = 0, v = 0;
+    for (int32_t j = 0; j < scale; j++) {
+        double r = unit53(draw(key, i * (uint64_t)scale + (uint64_t)j));
+        int32_t ub = r >= ab, vb = (r >= a && r < ab) || r >= abc;
+        u = (u << 1) | ub;
+        v = (v << 1) | vb;
+    }
+    *uo = u;
+    *vo = v;
+}
+
+static void relabel_edges(int64_t n, int64_t m, uint64_t seed, int32_t *out);
+
+/* Reference form: one candidate after the other, a set of the pairs seen. */
+int64_t wl_rmat_seq(int32_t scale, int64_t m, double a, double b, double c, uint64_t seed, int32_t relabel,
+                    int32_t *out) {
     int64_t n = (int64_t)1 << scale;
     if (scale < 1 || scale > 30 || m < 0 || m > n * (n - 1) / 2) return -1;
     hset_t h;
@@ -109,13 +127,8 @@ int64_t wl_rmat(int32_t scale, int64_t m, double a, double b, double c, uint64_t
     double ab = a + b, abc = a + b + c;
     int64_t got = 0, cand = 0;
     while (got < m) {
-        int32_t u = 0, v = 0;
-        for (int32_t j = 0; j < scale; j++) {
-            double r = unit53(draw(key, (uint64_t)cand * (uint64_t)scale + (uint64_t)j));
-            int32_t ub = r >= ab, vb = (r >= a && r < ab) || r >= abc;
-            u = (u << 1) | ub;
-            v = (v << 1) | vb;
-        }
+        int32_t u, v;
+        rmat_cand(key, scale, (uint64_t)cand, a, ab, abc, &u, &v);
         cand++;
         if (u == v) continue;
         if (!hset_add(&h, ekey(u, v))) continue;
@@ -124,14 +137,241 @@ int64_t wl_rmat(int32_t scale, int64_t m, double a, double b, double c, uint64_t
         got++;
     }
     free(h.slot);
-    if (relabel) {
-        int32_t *perm = (int32_t *)malloc((size_t)n * sizeof(int32_t));
-        if (!perm) return -1;
-        wl_permutation(n, seed, 2, perm);
-        for (int64_t i = 0; i < 2 * m; i++) out[i] = perm[out[i]];
-        free(perm);
-    }
+    if (relabel) relabel_edges(n, m, seed, out);
     return cand;
+}
+
+/* ---- the same stream, generated by threads.  The edges kept are the first
+ * m distinct pairs in candidate order, exactly as above: a shared table maps
+ * every pair seen to the least candidate index that drew it; once the
+ * candidates processed hold m distinct pairs, the m smallest such indices
+ * are the kept candidates, and they are written out in index order. */
+static int wl_threads(void) {
+    const char *e = getenv("WL_THREADS");
+    if (!e) e = getenv("OMP_NUM_THREADS");
+    long t = e ? strtol(e, NULL, 10) : sysconf(_SC_NPROCESSORS_ONLN);
+    if (t < 1) t = 1;
+    if (t > 64) t = 64;
+    return (int)t;
+}
+
+typedef struct {
+    _Atomic uint64_t *key;  /* HEMPTY or the pair */
+    _Atomic uint32_t *first; /* least candidate index of the pair */
+    uint64_t cap;
+    _Atomic int64_t distinct;
+    _Atomic int32_t full;
+} ftab_t;
+
+typedef struct {
+    ftab_t *t;
+    uint64_t ckey, lo, hi;
+    int32_t scale;
+    double a, ab, abc;
+    /* output pass */
+    _Atomic uint64_t *bits;
+    int64_t m, base;
+    int32_t *out;
+} rjob_t;
+
+static void *rmat_scan_worker(void *arg) {
+    rjob_t *j = (rjob_t *)arg;
+    ftab_t *t = j->t;
+    int64_t added = 0;
+    for (uint64_t i = j->lo; i < j->hi && !atomic_load_explicit(&t->full, memory_order_relaxed); i++) {
+        int32_t u, v;
+        rmat_cand(j->ckey, j->scale, i, j->a, j->ab, j->abc, &u, &v);
+        if (u == v) continue;
+        uint64_t k = ekey(u, v);
+        uint64_t s = (uint64_t)(((unsigned __int128)mix64(k) * t->cap) >> 64);
+        for (uint64_t probe = 0;; probe++) {
+            if (probe == t->cap) {
+                atomic_store(&t->full, 1);
+                break;
+            }
+            uint64_t cur = atomic_load_explicit(&t->key[s], memory_order_relaxed);
+            if (cur == HEMPTY) {
+                uint64_t expect = HEMPTY;
+                if (atomic_compare_exchange_strong(&t->key[s], &expect, k)) {
+                    added++;
+                    cur = k;
+                } else {
+                    cur = expect;
+                }
+            }
+            if (cur == k) {
+                uint32_t f = atomic_load_explicit(&t->first[s], memory_order_relaxed);
+                while ((uint32_t)i < f &&
+                       !atomic_compare_exchange_weak(&t->first[s], &f, (uint32_t)i)) {
+                }
+                break;
+            }
+            s = s + 1 == t->cap ? 0 : s + 1;
+        }
+    }
+    atomic_fetch_add(&t->distinct, added);
+    return NULL;
+}
+
+static void *rmat_mark_worker(void *arg) {
+    rjob_t *j = (rjob_t *)arg;
+    ftab_t *t = j->t;
+    for (uint64_t s = j->lo; s < j->hi; s++) {
+        if (atomic_load_explicit(&t->key[s], memory_order_relaxed) == HEMPTY) continue;
+        uint32_t f = atomic_load_explicit(&t->first[s], memory_order_relaxed);
+        atomic_fetch_or_explicit(&j->bits[f >> 6], 1ull << (f & 63), memory_order_relaxed);
+    }
+    return NULL;
+}
+
+static void *rmat_emit_worker(void *arg) {
+    rjob_t *j = (rjob_t *)arg;
+    int64_t pos = j->base;
+    for (uint64_t w = j->lo; w < j->hi && pos < j->m; w++) {
+        uint64_t word = atomic_load_explicit(&j->bits[w], memory_order_relaxed);
+        while (word && pos < j->m) {
+            uint64_t i = (w << 6) + (uint64_t)__builtin_ctzll(word);
+            word &= word - 1;
+            int32_t u, v;
+            rmat_cand(j->ckey, j->scale, i, j->a, j->ab, j->abc, &u, &v);
+            j->out[2 * pos] = u;
+            j->out[2 * pos + 1] = v;
+            pos++;
+        }
+    }
+    return NULL;
+}
+
+static void run_jobs(rjob_t *jobs, int nt, void *(*fn)(void *)) {
+    pthread_t th[64];
+    for (int i = 1; i < nt; i++)
+        if (pthread_create(&th[i], NULL, fn, &jobs[i])) {
+            fn(&jobs[i]);
+            th[i] = 0;
+        }
+    fn(&jobs[0]);
+    for (int i = 1; i < nt; i++)
+        if (th[i]) pthread_join(th[i], NULL);
+}
+
+/* R-MAT with `m` unique undirected edges on 2^scale vertices.  out: [m][2].
+ * Returns the number of candidates drawn, or -1.  Threads: WL_THREADS, else
+ * OMP_NUM_THREADS, else the online processors; the result does not depend on
+ * the thread count. */
+int64_t wl_rmat(int32_t scale, int64_t m, double a, double b, double c, uint64_t seed, int32_t relabel,
+                int32_t *out) {
+    int64_t n = (int64_t)1 << scale;
+    if (scale < 1 || scale > 30 || m < 0 || m > n * (n - 1) / 2) return -1;
+    int nt = wl_threads();
+    if (nt == 1 || m < (1 << 16)) return wl_rmat_seq(scale, m, a, b, c, seed, relabel, out);
+    ftab_t t;
+    t.cap = (uint64_t)(m * 5 / 2) + 1024;
+    t.key = (_Atomic uint64_t *)malloc(t.cap * sizeof(uint64_t));
+    t.first = (_Atomic uint32_t *)malloc(t.cap * sizeof(uint32_t));
+    if (!t.key || !t.first) {
+        free((void *)t.key);
+        free((void *)t.first);
+        return wl_rmat_seq(scale, m, a, b, c, seed, relabel, out);
+    }
+    memset((void *)t.key, 0xff, t.cap * sizeof(uint64_t));
+    memset((void *)t.first, 0xff, t.cap * sizeof(uint32_t));
+    atomic_init(&t.distinct, 0);
+    atomic_init(&t.full, 0);
+    rjob_t jobs[64];
+    rjob_t proto = {0};
+    proto.t = &t;
+    proto.ckey = stream_key(seed, 1);
+    proto.scale = scale;
+    proto.a = a;
+    proto.ab = a + b;
+    proto.abc = a + b + c;
+    proto.m = m;
+    proto.out = out;
+    uint64_t C = 0;
+    int ok = 1;
+    while (atomic_load(&t.distinct) < m) {
+        int64_t need = m - atomic_load(&t.distinct);
+        uint64_t step = (uint64_t)(need + need / 2) + 4096;
+        if (C + step >= (uint64_t)UINT32_MAX ||
+            (uint64_t)atomic_load(&t.distinct) + step > t.cap * 17 / 20) {
+            ok = 0;    /* index or table limit: take the reference path */
+            break;
+        }
+        for (int i = 0; i < nt; i++) {
+            jobs[i] = proto;
+            jobs[i].lo = C + step * (uint64_t)i / (uint64_t)nt;
+            jobs[i].hi = C + step * (uint64_t)(i + 1) / (uint64_t)nt;
+        }
+        run_jobs(jobs, nt, rmat_scan_worker);
+        if (atomic_load(&t.full)) {
+            ok = 0;
+            break;
+        }
+        C += step;
+    }
+    int64_t cand = -1;
+    if (ok) {
+        uint64_t nw = (C + 63) / 64;
+        _Atomic uint64_t *bits = (_Atomic uint64_t *)calloc(nw, sizeof(uint64_t));
+        int64_t *cnt = (int64_t *)calloc((size_t)nt + 1, sizeof(int64_t));
+        if (!bits || !cnt) {
+            ok = 0;
+        } else {
+            for (int i = 0; i < nt; i++) {
+                jobs[i] = proto;
+                jobs[i].bits = bits;
+                jobs[i].lo = t.cap * (uint64_t)i / (uint64_t)nt;
+                jobs[i].hi = t.cap * (uint64_t)(i + 1) / (uint64_t)nt;
+            }
+            run_jobs(jobs, nt, rmat_mark_worker);
+            /* word ranges per thread and their starting output positions */
+            for (int i = 0; i < nt; i++) {
+                uint64_t lo = nw * (uint64_t)i / (uint64_t)nt, hi = nw * (uint64_t)(i + 1) / (uint64_t)nt;
+                int64_t k = 0;
+                for (uint64_t w = lo; w < hi; w++) k += __builtin_popcountll(atomic_load(&bits[w]));
+                cnt[i + 1] = cnt[i] + k;
+                jobs[i] = proto;
+                jobs[i].bits = bits;
+                jobs[i].lo = lo;
+                jobs[i].hi = hi;
+            }
+            for (int i = 0; i < nt; i++) jobs[i].base = cnt[i];
+            run_jobs(jobs, nt, rmat_emit_worker);
+            /* candidates drawn by the reference form: index of the m-th kept one, plus one */
+            int64_t seen = 0;
+            for (uint64_t w = 0; w < nw && cand < 0; w++) {
+                uint64_t word = atomic_load(&bits[w]);
+                int64_t pc = __builtin_popcountll(word);
+                if (seen + pc < m) {
+                    seen += pc;
+                    continue;
+                }
+                while (word) {
+                    uint64_t i = (w << 6) + (uint64_t)__builtin_ctzll(word);
+                    word &= word - 1;
+                    if (++seen == m) {
+                        cand = (int64_t)i + 1;
+                        break;
+                    }
+                }
+            }
+        }
+        free((void *)bits);
+        free(cnt);
+    }
+    free((void *)t.key);
+    free((void *)t.first);
+    if (!ok) return wl_rmat_seq(scale, m, a, b, c, seed, relabel, out);
+    if (relabel) relabel_edges(n, m, seed, out);
+    return cand;
+}
+
+static void relabel_edges(int64_t n, int64_t m, uint64_t seed, int32_t *out) {
+    int32_t *perm = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!perm) return;
+    wl_permutation(n, seed, 2, perm);
+    for (int64_t i = 0; i < 2 * m; i++) out[i] = perm[out[i]];
+    free(perm);
 }
 
 /* G(n,p) by geometric skipping over the pairs (v,w), w < v.  Writes at most

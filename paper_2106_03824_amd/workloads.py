@@ -26,7 +26,7 @@ def build(force=True):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
-    subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", SRC, "-o", tmp, "-lm"], check=True)
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-Wall", "-fPIC", "-shared", "-pthread", SRC, "-o", tmp, "-lm"], check=True)
     os.replace(tmp, LIB)
     return LIB
 
@@ -38,6 +38,8 @@ def _lib():
         L.wl_rmat.restype = ctypes.c_int64
         L.wl_rmat.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_uint64, ctypes.c_int32, _I32P]
+        L.wl_rmat_seq.restype = ctypes.c_int64
+        L.wl_rmat_seq.argtypes = L.wl_rmat.argtypes
         L.wl_er.restype = ctypes.c_int64
         L.wl_er.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, _I32P, ctypes.c_int64]
         L.wl_permutation.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, _I32P]

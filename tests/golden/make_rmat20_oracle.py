@@ -7,7 +7,13 @@ batches, workload 2): the 16 insertion batches of the build, then rounds of
 the build (int16) and, for every batch, a checksum of the levels and the
 sweep/move counts, plus the oracle's single-core time per batch.
 
-    python tests/golden/make_rmat20_oracle.py [rounds]
+With the argument ``sizes`` it instead starts from the stored post-build
+state (the build's edges and the levels above) and applies the batch sizes
+10^4 and 10^5: insertions, then deletions, then mixed batches, with update
+seeds 1000*2 + 100 + j for j = 100, 101, ...; the result goes to
+rmat20_oracle_sizes.json.
+
+    python tests/golden/make_rmat20_oracle.py [rounds | sizes]
 """
 import hashlib
 import json
@@ -26,6 +32,9 @@ from paper_2106_03824_amd import workloads as W  # noqa: E402
 SCALE, BATCH = 20, 10 ** 6
 OUT_NPZ = os.path.join(HERE, "rmat20_oracle_levels.npz")
 OUT_JSON = os.path.join(HERE, "rmat20_oracle_trace.json")
+OUT_SIZES = os.path.join(HERE, "rmat20_oracle_sizes.json")
+SIZES = (10 ** 4, 10 ** 5)
+SIZES_J0 = 100
 
 
 def digest(levels):
@@ -71,5 +80,38 @@ def main(rounds=2):
     assert o.check() == 0
 
 
+def sizes():
+    st = W.RmatStream(SCALE, 16 * 2 ** SCALE, seed=1, build_batches=16, cfg=2)
+    st.j = SIZES_J0
+    o = O.Oracle(st.n, 0.4, 3.0)
+    lv0 = np.load(OUT_NPZ)["levels"].astype(np.int32)
+    assert o.load_state(np.concatenate(st.build), lv0) == 0
+    trace = {"workload": "RMAT scale 20 after the 16 build batches (stored oracle levels); then insertions of "
+                         "1e4 and 1e5, deletions of 1e4 and 1e5, mixed 1e4 and 1e5, update seeds from j=100",
+             "delta": 0.4, "lambda": 3.0, "batches": []}
+    plan = [("ins", c) for c in SIZES] + [("del", c) for c in SIZES] + [("mix", c) for c in SIZES]
+    for kind, c in plan:
+        if kind == "ins":
+            args = (st.insert_batch(c), None)
+        elif kind == "del":
+            args = (None, st.delete_batch(c))
+        else:
+            args = st.mixed_batch(c)
+        t = time.perf_counter()
+        rc = o.update(*args)
+        dt = time.perf_counter() - t
+        s = o.stats()
+        item = {"kind": f"{kind}{c}", "rc": rc, "seconds": round(dt, 3), "sha": digest(o.levels()),
+                **{k: s[k] for k in ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up",
+                                     "moves_down", "viol_ins0", "viol_del0")}}
+        trace["batches"].append(item)
+        print(json.dumps(item), flush=True)
+        json.dump(trace, open(OUT_SIZES, "w"), indent=1)
+    assert o.check() == 0
+
+
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2)
+    if len(sys.argv) > 1 and sys.argv[1] == "sizes":
+        sizes()
+    else:
+        main(int(sys.argv[1]) if len(sys.argv) > 1 else 2)

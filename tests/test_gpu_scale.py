@@ -81,3 +81,40 @@ def test_rmat20_stream_against_oracle_trace(mode):
     up, dn, pw = g.thresholds()
     exp = np.array([0.0 if d == 0 else pw[max((l + 1) // info["L"] - 1, 0)] for l, d in zip(lvs, deg)])
     assert np.array_equal(est, exp)
+
+
+SIZES = os.path.join(HERE, "golden", "rmat20_oracle_sizes.json")
+
+
+def test_rmat20_batch_sizes_against_oracle_trace():
+    """The smaller batch sizes of the same RMAT scale-20 workload: from the
+    post-build state, insertions of 10^4 and 10^5 new pairs, deletions of 10^4
+    and 10^5 existing edges, mixed batches of both sizes, each compared with
+    the oracle's trace (tests/golden/rmat20_oracle_sizes.json)."""
+    from paper_2106_03824_amd import plds as P
+    from paper_2106_03824_amd import workloads as W
+    ref = json.load(open(SIZES))["batches"]
+    st = W.RmatStream(20, 16 * 2 ** 20, seed=1, build_batches=16, cfg=2)
+    g = P.PLDS(st.n, 0.4, 3.0, 0, 2 * 16 * 2 ** 20)
+    for i, b in enumerate(st.build):
+        say("rmat20 sizes: build", i)
+        P.plds_batch_insert(g.h, torch.from_numpy(np.ascontiguousarray(b)).cuda())
+    assert np.array_equal(g.levels().cpu().numpy(), np.load(LEVELS)["levels"].astype(np.int32))
+    st.j = 100
+    for item in ref:
+        kind, size = item["kind"][:3], int(item["kind"][3:])
+        say("rmat20 sizes:", item["kind"])
+        if kind == "ins":
+            ins, dele = torch.from_numpy(st.insert_batch(size)).cuda(), None
+        elif kind == "del":
+            ins, dele = None, torch.from_numpy(st.delete_batch(size)).cuda()
+        else:
+            mi, md = st.mixed_batch(size)
+            ins, dele = torch.from_numpy(mi).cuda(), torch.from_numpy(md).cuda()
+        P.plds_update(g.h, ins, dele)
+        s = g.stats()
+        assert digest(g.levels().cpu().numpy()) == item["sha"], f"levels differ after {item['kind']}"
+        for k in ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up", "moves_down",
+                  "viol_ins0", "viol_del0"):
+            assert s[k] == item[k], (item["kind"], k, s[k], item[k])
+    assert g.check() == 0
