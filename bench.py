@@ -27,6 +27,18 @@ existing edges and one mixed batch; every batch is timed and the value is all
 applied updates over the wall time of the whole stream.
 
     python bench.py --scale 24 [--batch 1000000]
+
+With --batched it runs the batched form instead: 256 independent graphs of
+uneven size (128 Erdos-Renyi G(n, p) with n log-uniform in [2^10, 2^16] and
+mean degree uniform in [4, 32]; 128 R-MAT graphs with scale uniform in
+[10, 16] and edge factor 8), each built by one insertion batch, then one
+measured batch per graph (insertion or deletion with probability 1/2, size
+uniform in [10^3, 5*10^4], deletions clamped to m).  The measured batches
+of all graphs go through one multi-graph handle in one call (the value), and
+through one plain handle per graph in a loop; the levels of both must be
+identical.
+
+    python bench.py --batched
 """
 import argparse
 import hashlib
@@ -129,6 +141,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 2 GiB (reference for the HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="the batched form: 256 graphs in one handle")
+    ap.add_argument("--graphs", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -151,6 +165,8 @@ def main():
         print(json.dumps({"copy_bytes": COPY_BYTES, "note": "one device-to-device copy kernel, read+write"}))
         return
     dev = torch.device("cuda", 0)
+    if args.batched:
+        return run_batched(args, P, W, torch, np)
     if args.scale != 20:
         return run_stream(args, P, W, torch, np)
     scale, B = args.scale, args.batch
@@ -349,6 +365,83 @@ def run_stream(args, P, W, torch, np):
         "roofline": roofline(tot, args.kernel),
         "device_check": rc,
         "slab_slots": info["slab_slots"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batched_workload(k, W, np):
+    """The graphs and measured batches of the batched form (seed 4000 + i)."""
+    import random
+    rng = random.Random(4000)
+    graphs = []
+    for i in range(k):
+        if i % 2 == 0:
+            n = int(round(2 ** rng.uniform(10, 16)))
+            e = W.er(n, rng.uniform(4, 32) / (n - 1), seed=4000 + i)
+        else:
+            sc = rng.randint(10, 16)
+            n = 2 ** sc
+            e = W.rmat(sc, 8 * n, seed=4000 + i)
+        size = rng.randint(10 ** 3, 5 * 10 ** 4)
+        if rng.random() < 0.5:
+            b = ("ins", W.new_pairs(n, e, size, 4500 + i))
+        else:
+            b = ("del", W.sample_edges(e, min(size, len(e)), 4500 + i))
+        graphs.append((n, e, b))
+    return graphs
+
+
+def run_batched(args, P, W, torch, np):
+    k = args.graphs
+    t = time.perf_counter()
+    graphs = batched_workload(k, W, np)
+    ns = [n for n, _, _ in graphs]
+    log(f"{k} graphs, {sum(ns)} vertices, {sum(len(e) for _, e, _ in graphs)} edges, "
+        f"generated in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda", 0)
+    build = [torch.from_numpy(np.ascontiguousarray(e)).to(dev) for _, e, _ in graphs]
+    meas = [torch.from_numpy(np.ascontiguousarray(b)).to(dev) for _, _, (_, b) in graphs]
+    kinds = [kd for _, _, (kd, _) in graphs]
+    mg = P.MultiPLDS(ns)
+    singles = [P.PLDS(n) for n in ns]
+    mg.update_multi(ins=build)
+    for g in range(k):
+        P.plds_update(singles[g].h, build[g], None)
+    torch.cuda.synchronize()
+    log("built")
+    ins_l = [meas[g] if kinds[g] == "ins" else None for g in range(k)]
+    del_l = [meas[g] if kinds[g] == "del" else None for g in range(k)]
+    # the plain per-graph loop
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u_loop = 0
+    for g in range(k):
+        P.plds_update(singles[g].h, ins_l[g], del_l[g])
+        s = singles[g].stats()
+        u_loop += s["applied_ins"] + s["applied_del"]
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    # the batched form: one call for all graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.plds_update_multi(mg.h, ins_l, del_l)
+    torch.cuda.synchronize()
+    t_fused = time.perf_counter() - t0
+    s = mg.stats()
+    u_fused = s["applied_ins"] + s["applied_del"]
+    lv = mg.levels()
+    same = all(torch.equal(mg.graph_levels(g, lv), singles[g].levels()) for g in range(k))
+    log(f"loop {u_loop} updates in {t_loop * 1e3:.1f} ms, batched {u_fused} in {t_fused * 1e3:.1f} ms, "
+        f"identical levels: {same}")
+    out = {
+        "metric": METRIC, "value": u_fused / t_fused, "unit": "edge updates/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": t_fused * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"batched-{k}-graphs-er-rmat-n2^10..2^16", "graphs": k, "vertices": sum(ns),
+                   "delta": 0.4, "lambda": 3.0, "step": "one measured batch per graph, all graphs in one call"},
+        "per_graph_loop": {"value": u_loop / t_loop, "ms": t_loop * 1e3},
+        "speedup_vs_loop": t_loop / t_fused,
+        "identical_levels": same, "updates": u_fused, "sweeps": s["sweeps_ins"] + s["sweeps_del"],
     }
     print(json.dumps(out), flush=True)
 

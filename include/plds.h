@@ -51,6 +51,8 @@ typedef struct {
     double delta, lambda;
     int64_t slab_slots; /* adjacency slots allocated (pool capacity, int32 each)     */
     int64_t slab_used;  /* slots handed out (live slabs plus abandoned ones)          */
+    int32_t ngraphs;    /* graphs held by the handle (1 unless made by plds_create_multi) */
+    int32_t reserved32;
 } plds_info_t;
 
 typedef struct {
@@ -86,6 +88,39 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
                    plds_t **out);
 
 int plds_destroy(plds_t *h);
+
+/* Batched form: one handle holding `ngraphs` independent graphs, graph g
+ * with n[g] vertices (host array), all with the same delta and lambda.  Each
+ * graph keeps its own levels per group (4t_g from its own n[g], or
+ * levels_per_group when > 0) and its own thresholds, exactly as a handle
+ * made by plds_create_ex(n[g], ...) would, so every graph goes through the
+ * same states as it would alone: no edge joins two graphs, and whether a
+ * vertex moves at a level depends only on its own neighbours and its own
+ * graph's thresholds (Algorithms 2 and 3 move, level by level, exactly the
+ * violators of that level).  The
+ * graphs occupy consecutive vertex ranges of one vertex space of
+ * sum(n[g]) <= 2^31 - 1 vertices; plds_graph_info gives each range's first
+ * vertex.  Every level step of a batch serves all graphs at once.
+ * plds_levels, plds_degrees, plds_coreness and plds_dump_state/
+ * plds_load_state work on the whole vertex space (global ids);
+ * plds_thresholds returns graph 0's tables; plds_stats counts all graphs. */
+int plds_create_multi(int32_t ngraphs, const int64_t *n, double delta, double lambda, int32_t levels_per_group,
+                      int64_t edge_capacity_hint, plds_t **out);
+
+/* One batch for every graph of a multi-graph handle, applied as Update(B)
+ * of Algorithm 1 to each graph (insertions and their sweep for all graphs,
+ * then deletions and theirs).  ins[g] / del[g]: device int32 [count][2]
+ * edge lists of graph g in its own ids [0, n[g]); ins, n_ins, del, n_del are
+ * host arrays of ngraphs entries (an array may be NULL: no such lists).
+ * Batch semantics per graph as plds_update; an id outside its own graph's
+ * range rejects the whole call with PLDS_ERANGE before anything changes. */
+int plds_update_multi(plds_t *h, const int32_t *const *ins, const int64_t *n_ins, const int32_t *const *del,
+                      const int64_t *n_del, void *stream);
+
+/* Graph g of a handle: *vertex_base receives its first global vertex id,
+ * *out its n, t, L, G, K (m, delta, lambda and the slab figures are those
+ * of the whole handle).  Either pointer may be NULL. */
+int plds_graph_info(const plds_t *h, int32_t g, int64_t *vertex_base, plds_info_t *out);
 
 /* Update(B) of Algorithm 1 with B = (ins, del): all insertions are applied
  * and rebalanced (RebalanceInsertions, Algorithm 2), then all deletions

@@ -98,9 +98,17 @@ struct Ctl {
 
 // Everything a kernel needs, passed by value.
 struct Dev {
-    int32_t n, L, G, K;
-    int32_t *up_max, *dn_min;         // [G+1] (entry G = INT_MAX / unused)
-    double *pow_tab;                  // [G]
+    int32_t n, L, G, K;               // L, G, K: the largest over the graphs of the handle
+    int32_t *up_max, *dn_min;         // per graph g: [G_g+1] from gtab[g] (entry G_g = INT_MAX)
+    double *pow_tab;                  // per graph g: [G_g+1] from gtab[g]
+    // A handle holds ng independent graphs on disjoint vertex ranges (ng = 1
+    // for a plain handle).  Each graph has its own levels per group and
+    // thresholds; every level step serves all graphs at once.
+    int32_t ng;
+    int32_t *gid;                     // [n] graph of each vertex (ng > 1)
+    int32_t *gL, *gK, *gtab;          // [ng] levels per group, levels, table offset
+    int32_t *Ls;                      // [nLs] the distinct levels-per-group values
+    int32_t nLs;
     int32_t *level, *deg, *up, *ups, *cap, *fill;
     int64_t *off;
     int32_t *pool;
@@ -132,6 +140,21 @@ struct Dev {
     int32_t *p0, *p1;                 // [n]
     int32_t *rc;                      // [n]
 };
+
+// Levels per group and table offset of the graph that holds vertex v.
+struct GP {
+    int32_t L, tab;
+};
+__device__ __forceinline__ GP gp(const Dev &d, int32_t v) {
+    if (d.ng == 1) return GP{d.L, 0};
+    int32_t g = d.gid[v];
+    return GP{d.gL[g], d.gtab[g]};
+}
+// Invariant 1 cap and Invariant 2 floor of a vertex of graph p at level lvl
+__device__ __forceinline__ int32_t up_cap(const Dev &d, GP p, int32_t lvl) { return d.up_max[p.tab + lvl / p.L]; }
+__device__ __forceinline__ int32_t dn_floor(const Dev &d, GP p, int32_t lvl) {
+    return d.dn_min[p.tab + (lvl - 1) / p.L];
+}
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     // integer finaliser (low-bias 32-bit mixer)
@@ -574,7 +597,7 @@ __global__ void k_ins_seed(Dev d) {
             x = d.touch[i];
             d.addc[x] = 0;
             int32_t lx = d.level[x];
-            if (d.up[x] > d.up_max[lx / d.L]) key = lx;
+            if (d.up[x] > up_cap(d, gp(d, x), lx)) key = lx;
         }
         wpush(d.cand, &d.ctl->n_cand, d.n, key >= 0, x, d.ctl);
         wadd_key(d.lvl_cnt, key);
@@ -764,7 +787,7 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
     int32_t l = st.l, nxt = st.cur ^ 1, jump = st.jump;
     int32_t Mp = p ? kMover1 : kMover0, Mn = p ? kMover0 : kMover1;
     int32_t *casc = nxt ? d.casc1 : d.casc0;
-    int32_t ub1 = d.up_max[(l + 1) / d.L];
+    const int32_t ub1_all = d.ng == 1 ? d.up_max[(l + 1) / d.L] : 0;
     int lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
     int nw = nblk * wpb;
     const int32_t *ncls = d.ctl->n_cls2[p];
@@ -810,6 +833,8 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
             hi = min(lo + kChunk, d.cap[v]);
         }
         const int32_t *s = v >= 0 ? d.pool + d.off[v] : d.pool;
+        // the cap of level l+1 in v's graph (neighbours share v's graph)
+        const int32_t ub1 = d.ng == 1 ? ub1_all : (v >= 0 ? up_cap(d, gp(d, v), l + 1) : 0);
         int32_t stay = 0;
         int iters = cl == 4 ? kChunk / kWave : 1;
         for (int it = 0; it < iters; it++) {
@@ -905,10 +930,14 @@ __device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn
     int32_t movers = (z0 == l + 1 ? cn : 0) + ns;
     int32_t occz = d.occ[z0] + (z0 == l + 1 ? nmv : 0);
     bool all = occz == movers;
-    int32_t limit = min((z0 / d.L + 1) * d.L, d.K - 1);   // first level of the next group
     __syncthreads();
     if (threadIdx.x == 0) sh1[0] = INT32_MAX;
+    if (threadIdx.x == 1) sh1[1] = min((z0 / d.L + 1) * d.L, d.K - 1);   // first level of the next group
     __syncthreads();
+    if (d.ng > 1)   // several graphs: the first group boundary above z0 of any of them
+        for (int i = threadIdx.x; i < d.nLs; i += blockDim.x) atomicMin(&sh1[1], (z0 / d.Ls[i] + 1) * d.Ls[i]);
+    __syncthreads();
+    int32_t limit = sh1[1];
     if (all && z0 + 2 <= limit)
         for (int32_t z = z0 + 1 + threadIdx.x; z < limit; z += blockDim.x)
             if (d.occ[z] > 0) atomicMin(&sh1[0], z);
@@ -1165,6 +1194,7 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
 // the top bin holding every level >= lw-1), then a suffix scan.
 __device__ int32_t block_dl(Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_t *seg, int32_t *red) {
     int tid = threadIdx.x, nt = blockDim.x;
+    const GP pw = gp(d, w);
     int32_t nb = lw;
     for (int i = tid; i < nb; i += nt) hist[i] = 0;
     __syncthreads();
@@ -1192,7 +1222,7 @@ __device__ int32_t block_dl(Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_
     int32_t best = -1, cnt = seg[tid];
     for (int j = hi - 1; j >= lo; j--) {
         cnt += hist[j];                       // cnt(j)
-        if (j <= lw - 2 && cnt >= d.dn_min[j / d.L]) {
+        if (j <= lw - 2 && cnt >= dn_floor(d, pw, j + 1)) {
             best = j;
             break;
         }
@@ -1224,7 +1254,7 @@ __global__ void k_dl(Dev d, int mode) {
         int32_t w = list[i];
         if (mode == 0 && threadIdx.x == 0) d.addc[w] = 0;
         int32_t lw = d.level[w];
-        bool viol = lw > 0 && d.ups[w] < d.dn_min[(lw - 1) / d.L];
+        bool viol = lw > 0 && d.ups[w] < dn_floor(d, gp(d, w), lw);
         if (!viol) continue;                  // block-uniform
         int32_t dv = block_dl(d, w, lw, hist, seg, red);
         ncalc++;
@@ -1332,7 +1362,7 @@ __global__ void k_del_scan(Dev d) {
                     if (lw > l && lw <= pv) atomicSub(&d.up[w], 1);
                     if (lw > l + 1 && lw <= pv + 1) {
                         int32_t old = atomicSub(&d.ups[w], 1);
-                        if (old == d.dn_min[(lw - 1) / d.L]) again = true;
+                        if (old == dn_floor(d, gp(d, w), lw)) again = true;
                     }
                     fresh = again && atomicExch(&d.rcstamp[w], sid) != sid;
                 }
@@ -1381,8 +1411,9 @@ __global__ void k_coreness(Dev d, const int32_t *vs, int64_t cnt, double *out) {
             latch(d.ctl, kErrRange);
             continue;
         }
-        int32_t e = (d.level[v] + 1) / d.L - 1;
-        out[i] = d.deg[v] == 0 ? 0.0 : d.pow_tab[e > 0 ? e : 0];
+        const GP p = gp(d, v);
+        int32_t e = (d.level[v] + 1) / p.L - 1;
+        out[i] = d.deg[v] == 0 ? 0.0 : d.pow_tab[p.tab + (e > 0 ? e : 0)];
     }
 }
 
@@ -1408,12 +1439,13 @@ __global__ void k_check(Dev d, int32_t *bad) {
         cus = wave_sum(cus);
         live = wave_sum(live);
         if (lane == 0) {
-            if (lv < 0 || lv >= d.K) {
+            const GP p = gp(d, v);
+            if (lv < 0 || lv >= (d.ng == 1 ? d.K : d.gK[d.gid[v]])) {
                 atomicAdd(&bad[4], 1);
             } else {
                 if (cu != d.up[v] || cus != d.ups[v]) atomicAdd(&bad[0], 1);
-                if (cu > d.up_max[lv / d.L]) atomicAdd(&bad[1], 1);
-                if (lv > 0 && cus < d.dn_min[(lv - 1) / d.L]) atomicAdd(&bad[2], 1);
+                if (cu > up_cap(d, p, lv)) atomicAdd(&bad[1], 1);
+                if (lv > 0 && cus < dn_floor(d, p, lv)) atomicAdd(&bad[2], 1);
                 if (d.deg[v] == 0 && lv != 0) atomicAdd(&bad[3], 1);
                 if (live != d.deg[v]) atomicAdd(&bad[5], 1);
             }
@@ -1522,16 +1554,87 @@ __global__ void k_set_offsets(Dev d, const int64_t *newoff) {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) d.off[v] = newoff[v];
 }
 
+// One graph's edge list of a multi-graph batch: `cnt` pairs at `src` (ids
+// local to the graph), written from pair `dst` on with the graph's first
+// vertex `base` added.
+struct Seg {
+    const int32_t *src;
+    int64_t cnt, dst;
+    int32_t base, n;
+};
+
+// Gather the per-graph lists of a multi-graph batch into one list of global
+// ids; an id outside [0, n) of its own graph latches kErrRange.
+__global__ void k_stage(const Seg *segs, int32_t nseg, int64_t total, int32_t *out, Ctl *ctl) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += stride) {
+        int32_t lo = 0, hi = nseg - 1;   // last segment with dst <= i
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) / 2;
+            if (segs[mid].dst <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const Seg sg = segs[lo];
+        int64_t j = i - sg.dst;
+        int32_t a = sg.src[2 * j], b = sg.src[2 * j + 1];
+        if (a < 0 || a >= sg.n || b < 0 || b >= sg.n) latch(ctl, kErrRange);
+        out[2 * i] = a + sg.base;
+        out[2 * i + 1] = b + sg.base;
+    }
+}
+
 }  // namespace
 
 // ===================================================================== host
+// Levels, groups and thresholds of one graph (Section "Detailed PLDS
+// Algorithm"): t = least integer with (1+delta)^t >= n, L = 4t (or the
+// override, at least 1), G = t+1, K = G*L; up_max[g] = floor((2+3/lambda)
+// x_g) and dn_min[g] = ceil(x_g) as exact integer rewrites of Invariants
+// 1-2, where x_g = (1+delta)^g is formed by repeated IEEE double
+// multiplication.  Entry G of up_max/dn_min is INT32_MAX.
+struct Tables {
+    int32_t t = 0, L = 0, G = 0, K = 0;
+    std::vector<int32_t> up, dn;
+    std::vector<double> pw;
+};
+
+static Tables make_tables(int64_t n, double delta, double lambda, int32_t lpg) {
+    Tables T;
+    double p = 1.0;
+    while (p < (double)n) {
+        p *= 1.0 + delta;
+        T.t++;
+    }
+    T.L = lpg > 0 ? lpg : std::max(1, 4 * T.t);
+    T.G = T.t + 1;
+    T.K = T.G * T.L;
+    T.up.assign(T.G + 1, INT32_MAX);
+    T.dn.assign(T.G + 1, INT32_MAX);
+    T.pw.assign(T.G + 1, 0.0);
+    double coeff = 2.0 + 3.0 / lambda, x = 1.0;
+    for (int32_t g = 0; g < T.G; g++) {
+        if (g > 0) x *= 1.0 + delta;
+        T.pw[g] = x;
+        double ub = std::floor(coeff * x), lb = std::ceil(x);
+        T.up[g] = ub >= (double)INT32_MAX ? INT32_MAX : (int32_t)ub;
+        T.dn[g] = lb >= (double)INT32_MAX ? INT32_MAX : (int32_t)lb;
+    }
+    return T;
+}
 struct plds {
     int64_t n = 0, m = 0;
     double delta = 0, lambda = 0;
     int32_t t = 0, L = 0, G = 0, K = 0;
     int device = 0;
-    std::vector<int32_t> h_up_max, h_dn_min;
+    std::vector<int32_t> h_up_max, h_dn_min;   // concatenated per graph (stride G_g + 1)
     std::vector<double> h_pow;
+    // graphs of a multi-graph handle (one entry for a plain handle)
+    std::vector<Tables> gt;
+    std::vector<int64_t> gbase, gn;           // first vertex and vertex count of each graph
+    std::vector<int32_t> gtab;
+    int32_t *stage = nullptr;                 // gathered multi-graph batch
+    int64_t stage_cap = 0;                    // pairs
+    Seg *d_segs = nullptr, *h_segs = nullptr;
     Dev d{};
     int64_t batch_cap = 0;
     int64_t pool_top = 0;
@@ -1591,38 +1694,36 @@ int grid_for(int64_t work, int block = kBlock, int cap = 4096) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
-// Levels and groups (Section "Detailed PLDS Algorithm"): t = least integer with
-// (1+delta)^t >= n, L = 4t (or override, at least 1), G = t+1, K = G*L.
-// Thresholds as exact integer rewrites of Invariants 1-2:
-// up_max[g] = floor((2+3/lambda) x_g), dn_min[g] = ceil(x_g), where x_g is
-// (1+delta)^g formed by repeated IEEE double multiplication.
+// Tables of every graph of the handle, concatenated; the handle's t, L, G,
+// K are the largest over its graphs.
 void build_tables(plds *h, int32_t lpg) {
-    double p = 1.0;
-    int32_t t = 0;
-    while (p < (double)h->n) {
-        p *= 1.0 + h->delta;
-        t++;
-    }
-    h->t = t;
-    h->L = lpg > 0 ? lpg : std::max(1, 4 * t);
-    h->G = t + 1;
-    h->K = h->G * h->L;
-    h->h_up_max.assign(h->G + 1, INT32_MAX);
-    h->h_dn_min.assign(h->G + 1, INT32_MAX);
-    h->h_pow.assign(h->G, 1.0);
-    double coeff = 2.0 + 3.0 / h->lambda, x = 1.0;
-    for (int32_t g = 0; g < h->G; g++) {
-        if (g > 0) x *= 1.0 + h->delta;
-        h->h_pow[g] = x;
-        double ub = std::floor(coeff * x), lb = std::ceil(x);
-        h->h_up_max[g] = ub >= (double)INT32_MAX ? INT32_MAX : (int32_t)ub;
-        h->h_dn_min[g] = lb >= (double)INT32_MAX ? INT32_MAX : (int32_t)lb;
+    h->gt.clear();
+    h->gtab.clear();
+    h->h_up_max.clear();
+    h->h_dn_min.clear();
+    h->h_pow.clear();
+    h->t = h->L = h->G = h->K = 0;
+    for (size_t g = 0; g < h->gn.size(); g++) {
+        Tables T = make_tables(h->gn[g], h->delta, h->lambda, lpg);
+        h->gtab.push_back((int32_t)h->h_up_max.size());
+        h->h_up_max.insert(h->h_up_max.end(), T.up.begin(), T.up.end());
+        h->h_dn_min.insert(h->h_dn_min.end(), T.dn.begin(), T.dn.end());
+        h->h_pow.insert(h->h_pow.end(), T.pw.begin(), T.pw.end());
+        h->t = std::max(h->t, T.t);
+        h->L = std::max(h->L, T.L);
+        h->G = std::max(h->G, T.G);
+        h->K = std::max(h->K, T.K);
+        h->gt.push_back(std::move(T));
     }
 }
 
 void free_all(plds *h) {
     Dev &d = h->d;
     dfree(d.up_max), dfree(d.dn_min), dfree(d.pow_tab);
+    dfree(d.gid), dfree(d.gL), dfree(d.gK), dfree(d.gtab), dfree(d.Ls);
+    dfree(h->stage), dfree(h->d_segs);
+    if (h->h_segs) (void)hipHostFree(h->h_segs);
+    h->h_segs = nullptr;
     dfree(d.level), dfree(d.deg), dfree(d.up), dfree(d.ups), dfree(d.cap), dfree(d.fill), dfree(d.off);
     dfree(d.pool), dfree(d.stay), dfree(d.cnt2), dfree(d.addc), dfree(d.dl), dfree(d.rcstamp), dfree(d.ctl);
     dfree(d.hset), dfree(d.valid), dfree(d.touch), dfree(d.grow), dfree(d.newcap), dfree(d.oldoff),
@@ -2044,18 +2145,28 @@ const char *plds_strerror(int code) {
     }
 }
 
-int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int64_t edge_capacity_hint,
-                   plds_t **out) {
+int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double lambda, int32_t levels_per_group,
+                      int64_t edge_capacity_hint, plds_t **out) {
     if (!out) return PLDS_EINVAL;
     *out = nullptr;
-    if (n < 1 || n > INT32_MAX || !(delta > 0) || !(lambda > 0) || !std::isfinite(delta) ||
-        !std::isfinite(lambda) || levels_per_group < 0 || edge_capacity_hint < 0)
+    if (ngraphs < 1 || !ns || !(delta > 0) || !(lambda > 0) || !std::isfinite(delta) || !std::isfinite(lambda) ||
+        levels_per_group < 0 || edge_capacity_hint < 0)
         return PLDS_EINVAL;
+    int64_t n = 0;
+    for (int32_t g = 0; g < ngraphs; g++) {
+        if (ns[g] < 1 || ns[g] > INT32_MAX) return PLDS_EINVAL;
+        n += ns[g];
+        if (n > INT32_MAX) return PLDS_EINVAL;
+    }
     plds *h = new (std::nothrow) plds();
     if (!h) return PLDS_ENOMEM;
     h->n = n;
     h->delta = delta;
     h->lambda = lambda;
+    for (int32_t g = 0, b = 0; g < ngraphs; b += (int32_t)ns[g], g++) {
+        h->gbase.push_back(b);
+        h->gn.push_back(ns[g]);
+    }
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return PLDS_EHIP;
@@ -2070,8 +2181,19 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
     d.L = h->L;
     d.G = h->G;
     d.K = h->K;
+    d.ng = ngraphs;
+    int64_t ntab = (int64_t)h->h_up_max.size();
+    std::vector<int32_t> hL, hK, hLs;
+    for (auto &T : h->gt) {
+        hL.push_back(T.L);
+        hK.push_back(T.K);
+        if (std::find(hLs.begin(), hLs.end(), T.L) == hLs.end()) hLs.push_back(T.L);
+    }
+    d.nLs = (int32_t)hLs.size();
     int rc = 0;
-    rc |= dalloc(&d.up_max, h->G + 1) | dalloc(&d.dn_min, h->G + 1) | dalloc(&d.pow_tab, h->G);
+    rc |= dalloc(&d.up_max, ntab) | dalloc(&d.dn_min, ntab) | dalloc(&d.pow_tab, ntab);
+    rc |= dalloc(&d.gL, ngraphs) | dalloc(&d.gK, ngraphs) | dalloc(&d.gtab, ngraphs) | dalloc(&d.Ls, d.nLs);
+    if (ngraphs > 1) rc |= dalloc(&d.gid, n);
     rc |= dalloc(&d.level, n) | dalloc(&d.deg, n) | dalloc(&d.up, n) | dalloc(&d.ups, n);
     rc |= dalloc(&d.cap, n) | dalloc(&d.fill, n) | dalloc(&d.off, n);
     rc |= dalloc(&d.stay, n) | dalloc(&d.cnt2, n) | dalloc(&d.addc, n) | dalloc(&d.dl, n) | dalloc(&d.rcstamp, n);
@@ -2102,11 +2224,14 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
     h->h_ctl->nm = kInf;
     hipStream_t s = 0;
     int32_t n32 = (int32_t)n;
-    bool ok = hipMemcpy(d.up_max, h->h_up_max.data(), (h->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice) ==
+    bool ok = hipMemcpy(d.up_max, h->h_up_max.data(), ntab * sizeof(int32_t), hipMemcpyHostToDevice) ==
                   hipSuccess &&
-              hipMemcpy(d.dn_min, h->h_dn_min.data(), (h->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice) ==
-                  hipSuccess &&
-              hipMemcpy(d.pow_tab, h->h_pow.data(), h->G * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.dn_min, h->h_dn_min.data(), ntab * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.pow_tab, h->h_pow.data(), ntab * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.gL, hL.data(), ngraphs * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.gK, hK.data(), ngraphs * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.gtab, h->gtab.data(), ngraphs * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(d.Ls, hLs.data(), d.nLs * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemsetAsync(d.level, 0, n * sizeof(int32_t), s) == hipSuccess &&
               hipMemsetAsync(d.deg, 0, n * sizeof(int32_t), s) == hipSuccess &&
               hipMemsetAsync(d.up, 0, n * sizeof(int32_t), s) == hipSuccess &&
@@ -2124,6 +2249,9 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
               hipMemcpy(d.occ, &n32, sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(d.ctl, h->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) == hipSuccess &&
               hipStreamSynchronize(s) == hipSuccess;
+    for (int32_t g = 0; ok && ngraphs > 1 && g < ngraphs; g++)
+        ok = hipMemsetD32Async((hipDeviceptr_t)(d.gid + h->gbase[g]), g, (size_t)h->gn[g], s) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
         free_all(h);
         delete h;
@@ -2131,6 +2259,15 @@ int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_gr
     }
     *out = h;
     return PLDS_OK;
+}
+
+int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int64_t edge_capacity_hint,
+                   plds_t **out) {
+    if (n < 1 || n > INT32_MAX) {
+        if (out) *out = nullptr;
+        return PLDS_EINVAL;
+    }
+    return plds_create_multi(1, &n, delta, lambda, levels_per_group, edge_capacity_hint, out);
 }
 
 int plds_create(int64_t n, double delta, double lambda, plds_t **out) {
@@ -2146,23 +2283,25 @@ int plds_destroy(plds_t *h) {
     return PLDS_OK;
 }
 
-int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, void *stream) {
-    int rc = guard(h);
-    if (rc) return rc;
-    if (n_ins < 0 || n_del < 0 || (n_ins && !ins) || (n_del && !del)) return PLDS_EINVAL;
-    if ((uint64_t)n_ins > (uint64_t)INT32_MAX / 2 || (uint64_t)n_del > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
-    hipStream_t s = S(stream);
+}  // extern "C"
+
+namespace {
+
+// Start of a batch call: clear the statistics, the step log and the error
+// bits (host mirror and device).
+int begin_call(plds *h, hipStream_t s) {
     memset(&h->stats, 0, sizeof(h->stats));
-    if (n_ins + n_del == 0) return PLDS_OK;
-    // range check of both lists before anything changes
     h->h_ctl->err = 0;
     h->h_ctl->n_log = 0;
     HIPCHK(hipMemcpyAsync(&h->d.ctl->n_log, &h->h_ctl->n_log, sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(&h->d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    if (n_ins) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_ins)), dim3(kBlock), 0, s, ins, n_ins, h->d.n, h->d.ctl);
-    if (n_del) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_del)), dim3(kBlock), 0, s, del, n_del, h->d.n, h->d.ctl);
-    HIPCHK(hipGetLastError());
-    rc = sync_ctl(h, s);
+    return PLDS_OK;
+}
+
+// After the range checks of a call: PLDS_ERANGE (nothing applied) if any id
+// was out of range.
+int end_range_check(plds *h, hipStream_t s) {
+    int rc = sync_ctl(h, s);
     if (rc) return rc;
     if (h->h_ctl->err & kErrRange) {
         h->h_ctl->err = 0;
@@ -2170,6 +2309,13 @@ int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del
         HIPCHK(hipStreamSynchronize(s));
         return PLDS_ERANGE;
     }
+    return PLDS_OK;
+}
+
+// Algorithm 1 on range-checked lists of global ids: insertions and their
+// sweep, then deletions and theirs.
+int run_update(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, hipStream_t s) {
+    int rc;
     if (n_ins) {
         int64_t applied = 0;
         rc = apply_list(h, ins, n_ins, 1, s, &applied);
@@ -2193,6 +2339,94 @@ int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del
     rc = sync_ctl(h, s);
     if (rc) return rc;
     return check_err(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (n_ins < 0 || n_del < 0 || (n_ins && !ins) || (n_del && !del)) return PLDS_EINVAL;
+    if ((uint64_t)n_ins > (uint64_t)INT32_MAX / 2 || (uint64_t)n_del > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    memset(&h->stats, 0, sizeof(h->stats));
+    if (n_ins + n_del == 0) return PLDS_OK;
+    rc = begin_call(h, s);
+    if (rc) return rc;
+    // range check of both lists before anything changes
+    if (n_ins) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_ins)), dim3(kBlock), 0, s, ins, n_ins, h->d.n, h->d.ctl);
+    if (n_del) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_del)), dim3(kBlock), 0, s, del, n_del, h->d.n, h->d.ctl);
+    HIPCHK(hipGetLastError());
+    rc = end_range_check(h, s);
+    if (rc) return rc;
+    return run_update(h, ins, n_ins, del, n_del, s);
+}
+
+int plds_update_multi(plds_t *h, const int32_t *const *ins, const int64_t *n_ins, const int32_t *const *del,
+                      const int64_t *n_del, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    int32_t ng = h->d.ng;
+    int64_t ti = 0, td = 0;
+    for (int32_t g = 0; g < ng; g++) {
+        int64_t a = n_ins ? n_ins[g] : 0, b = n_del ? n_del[g] : 0;
+        if (a < 0 || b < 0 || (a && (!ins || !ins[g])) || (b && (!del || !del[g]))) return PLDS_EINVAL;
+        ti += a;
+        td += b;
+    }
+    if ((uint64_t)ti > (uint64_t)INT32_MAX / 2 || (uint64_t)td > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    memset(&h->stats, 0, sizeof(h->stats));
+    if (ti + td == 0) return PLDS_OK;
+    if (ti + td > h->stage_cap) {
+        dfree(h->stage);
+        h->stage_cap = 0;
+        if (dalloc(&h->stage, 2 * (ti + td))) return PLDS_ENOMEM;
+        h->stage_cap = ti + td;
+    }
+    if (!h->d_segs) {
+        if (dalloc(&h->d_segs, 2 * (int64_t)ng)) return PLDS_ENOMEM;
+        if (hipHostMalloc((void **)&h->h_segs, 2 * (size_t)ng * sizeof(Seg), hipHostMallocDefault) != hipSuccess) {
+            h->h_segs = nullptr;
+            return PLDS_ENOMEM;
+        }
+    }
+    // the insertion lists, then the deletion lists, each in graph order
+    int32_t nseg = 0;
+    int64_t at = 0;
+    for (int pass = 0; pass < 2; pass++)
+        for (int32_t g = 0; g < ng; g++) {
+            int64_t c = pass == 0 ? (n_ins ? n_ins[g] : 0) : (n_del ? n_del[g] : 0);
+            if (!c) continue;
+            h->h_segs[nseg++] = Seg{pass == 0 ? ins[g] : del[g], c, at, (int32_t)h->gbase[g], (int32_t)h->gn[g]};
+            at += c;
+        }
+    rc = begin_call(h, s);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(h->d_segs, h->h_segs, nseg * sizeof(Seg), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_stage, dim3(grid_for(ti + td)), dim3(kBlock), 0, s, h->d_segs, nseg, ti + td, h->stage,
+                       h->d.ctl);
+    HIPCHK(hipGetLastError());
+    rc = end_range_check(h, s);
+    if (rc) return rc;
+    return run_update(h, h->stage, ti, h->stage + 2 * ti, td, s);
+}
+
+int plds_graph_info(const plds_t *h, int32_t g, int64_t *vertex_base, plds_info_t *out) {
+    if (!h || g < 0 || g >= h->d.ng) return PLDS_EINVAL;
+    if (vertex_base) *vertex_base = h->gbase[g];
+    if (out) {
+        const Tables &T = h->gt[g];
+        plds_info(h, out);
+        out->n = h->gn[g];
+        out->t = T.t;
+        out->L = T.L;
+        out->G = T.G;
+        out->K = T.K;
+    }
+    return PLDS_OK;
 }
 
 int plds_batch_insert(plds_t *h, const int32_t *edges, int64_t count, void *stream) {
@@ -2242,12 +2476,14 @@ int plds_info(const plds_t *h, plds_info_t *out) {
     out->lambda = h->lambda;
     out->slab_slots = h->d.pool_cap;
     out->slab_used = h->pool_top;
+    out->ngraphs = h->d.ng;
+    out->reserved32 = 0;
     return PLDS_OK;
 }
 
 int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *pow_tab) {
     if (!h) return PLDS_EINVAL;
-    for (int32_t g = 0; g < h->G; g++) {
+    for (int32_t g = 0; g < h->gt[0].G; g++) {   // graph 0 (the only one of a plain handle)
         if (up_max) up_max[g] = h->h_up_max[g];
         if (dn_min) dn_min[g] = h->h_dn_min[g];
         if (pow_tab) pow_tab[g] = h->h_pow[g];

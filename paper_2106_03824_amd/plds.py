@@ -23,7 +23,8 @@ class PLDSError(RuntimeError):
 class plds_info_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("t", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("G", ctypes.c_int32), ("K", ctypes.c_int32), ("delta", ctypes.c_double),
-                ("lambda_", ctypes.c_double), ("slab_slots", ctypes.c_int64), ("slab_used", ctypes.c_int64)]
+                ("lambda_", ctypes.c_double), ("slab_slots", ctypes.c_int64), ("slab_used", ctypes.c_int64),
+                ("ngraphs", ctypes.c_int32), ("reserved32", ctypes.c_int32)]
 
 
 STAT_FIELDS = ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up", "moves_down", "dl_calcs",
@@ -53,6 +54,10 @@ def lib():
         L.plds_create_ex.argtypes = [_I64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _I64,
                                      ctypes.POINTER(_VP)]
         L.plds_destroy.argtypes = [_VP]
+        L.plds_create_multi.argtypes = [ctypes.c_int32, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _I64,
+                                        ctypes.POINTER(_VP)]
+        L.plds_update_multi.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
+        L.plds_graph_info.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(_I64), ctypes.POINTER(plds_info_t)]
         L.plds_update.argtypes = [_VP, _VP, _I64, _VP, _I64, _VP]
         L.plds_batch_insert.argtypes = [_VP, _VP, _I64, _VP]
         L.plds_batch_delete.argtypes = [_VP, _VP, _I64, _VP]
@@ -75,7 +80,8 @@ def lib():
     return _lib
 
 
-EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_update", "plds_batch_insert",
+EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi", "plds_update_multi",
+           "plds_graph_info", "plds_update", "plds_batch_insert",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
            "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror")
 
@@ -131,6 +137,44 @@ def plds_create_ex(n, delta, lam, levels_per_group=0, edge_capacity_hint=0):
 
 def plds_destroy(h):
     return _chk(lib().plds_destroy(h), "plds_destroy")
+
+
+def plds_create_multi(ns, delta, lam, levels_per_group=0, edge_capacity_hint=0):
+    k = len(ns)
+    arr = (ctypes.c_int64 * k)(*[int(x) for x in ns])
+    h = _VP()
+    _chk(lib().plds_create_multi(k, ctypes.addressof(arr), float(delta), float(lam), int(levels_per_group),
+                                 int(edge_capacity_hint), ctypes.byref(h)), "plds_create_multi")
+    return h
+
+
+def plds_update_multi(h, ins=None, dele=None, stream=None, check=True):
+    """ins, dele: sequences with one entry per graph (an int32 [count, 2]
+    device tensor in the graph's own ids, or None), or None."""
+    def arrays(lists):
+        if lists is None:
+            return None, None, None
+        k = len(lists)
+        ptrs = (ctypes.c_void_p * k)()
+        cnts = (ctypes.c_int64 * k)()
+        for i, e in enumerate(lists):
+            p, c = _edges_arg(e)
+            ptrs[i], cnts[i] = p, c
+        return ptrs, cnts, (ctypes.addressof(ptrs), ctypes.addressof(cnts))
+    pi, ci, ai = arrays(ins)
+    pd, cd, ad = arrays(dele)
+    rc = lib().plds_update_multi(h, ai[0] if ai else None, ai[1] if ai else None, ad[0] if ad else None,
+                                 ad[1] if ad else None, _stream(stream))
+    return _chk(rc, "plds_update_multi") if check else rc
+
+
+def plds_graph_info(h, g):
+    i = plds_info_t()
+    base = _I64()
+    _chk(lib().plds_graph_info(h, int(g), ctypes.byref(base), ctypes.byref(i)), "plds_graph_info")
+    d = {f: getattr(i, f) for f, _ in plds_info_t._fields_}
+    d["base"] = base.value
+    return d
 
 
 def plds_update(h, ins=None, dele=None, stream=None, check=True):
@@ -229,8 +273,9 @@ def plds_sync(h, stream=None):
 class PLDS:
     """Owning wrapper: one handle on the current device."""
 
-    def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, edge_capacity_hint=0):
-        self.h = plds_create_ex(n, delta, lam, levels_per_group, edge_capacity_hint)
+    def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, edge_capacity_hint=0, _handle=None):
+        self.h = _handle if _handle is not None else plds_create_ex(n, delta, lam, levels_per_group,
+                                                                    edge_capacity_hint)
         info = plds_info(self.h)
         self.n, self.L, self.G, self.K, self.t = info["n"], info["L"], info["G"], info["K"], info["t"]
 
@@ -304,3 +349,23 @@ class PLDS:
         import torch
         lv = torch.as_tensor(levels, dtype=torch.int32).to("cuda").contiguous()
         return plds_load_state(self.h, self._dev(edges), lv, check=check)
+
+
+class MultiPLDS(PLDS):
+    """Owning wrapper of a multi-graph handle: graph g has ns[g] vertices and
+    occupies global ids [base[g], base[g] + ns[g])."""
+
+    def __init__(self, ns, delta=0.4, lam=3.0, levels_per_group=0, edge_capacity_hint=0):
+        super().__init__(0, _handle=plds_create_multi(ns, delta, lam, levels_per_group, edge_capacity_hint))
+        self.graphs = [plds_graph_info(self.h, g) for g in range(len(ns))]
+        self.base = [gi["base"] for gi in self.graphs]
+        self.ns = [gi["n"] for gi in self.graphs]
+
+    def update_multi(self, ins=None, dele=None, check=True):
+        dev = lambda lists: None if lists is None else [self._dev(e) if e is not None and len(e) else None
+                                                        for e in lists]
+        return plds_update_multi(self.h, dev(ins), dev(dele), check=check)
+
+    def graph_levels(self, g, levels=None):
+        lv = self.levels() if levels is None else levels
+        return lv[self.base[g]:self.base[g] + self.ns[g]]
