@@ -39,6 +39,18 @@ through one plain handle per graph in a loop; the levels of both must be
 identical.
 
     python bench.py --batched
+
+With --serve it runs the serving form: 64 resident R-MAT graphs (scale
+uniform in [16, 22], edge factor 16) behind the request loop of
+paper_2106_03824_amd/serve.py with 8 worker streams.  Request streams (half
+update batches of log-uniform size in [10^2, 10^6], 70% insertions; half
+coreness queries of 10^3 vertices) are served first all at once (the
+saturation rate), then as Poisson streams at 10%, 50%, 90% and 120% of it;
+p50/p99 latency per rate.  Afterwards the same graphs and requests are
+served again by one worker, one request at a time, and every query result
+and final level must be identical.
+
+    python bench.py --serve [--serve-scales 16 22] [--serve-graphs 64]
 """
 import argparse
 import hashlib
@@ -143,6 +155,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", action="store_true", help="the batched form: 256 graphs in one handle")
     ap.add_argument("--graphs", type=int, default=256)
+    ap.add_argument("--serve", action="store_true", help="the serving form: resident graphs behind a request loop")
+    ap.add_argument("--serve-graphs", type=int, default=64)
+    ap.add_argument("--serve-scales", type=int, nargs=2, default=[16, 22])
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -167,6 +184,8 @@ def main():
     dev = torch.device("cuda", 0)
     if args.batched:
         return run_batched(args, P, W, torch, np)
+    if args.serve:
+        return run_serve(args, P, W, torch, np)
     if args.scale != 20:
         return run_stream(args, P, W, torch, np)
     scale, B = args.scale, args.batch
@@ -442,6 +461,77 @@ def run_batched(args, P, W, torch, np):
         "per_graph_loop": {"value": u_loop / t_loop, "ms": t_loop * 1e3},
         "speedup_vs_loop": t_loop / t_fused,
         "identical_levels": same, "updates": u_fused, "sweeps": s["sweeps_ins"] + s["sweeps_del"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args, P, W, torch, np):
+    import random
+    from paper_2106_03824_amd import serve as S
+
+    def fresh(reqs):   # unserved copies sharing the (read-only) payloads
+        return [S.Request(r.rid, r.graph, r.kind, r.arrival, r.payload) for r in reqs]
+
+    rng = random.Random(5000)
+    lo, hi = args.serve_scales
+    t = time.perf_counter()
+    graphs = {}
+    for g in range(args.serve_graphs):
+        sc = rng.randint(lo, hi)
+        graphs[g] = (2 ** sc, W.rmat(sc, 16 * 2 ** sc, seed=5000 + g))
+    m_total = sum(len(e) for _, e in graphs.values())
+    log(f"{len(graphs)} graphs, {m_total} edges, generated in {time.perf_counter() - t:.1f}s")
+    N = args.serve_requests
+    admits = [S.Request(g, g, "admit", 0.0, graphs[g]) for g in graphs]
+    retires = [S.Request(10 ** 9 + g, g, "retire", 0.0) for g in graphs]
+    srv = S.Server(1 << 60, args.workers)
+    t_build = srv.serve(fresh(admits), arrival=False)
+    log(f"admitted and built in {t_build:.1f}s")
+    applied = lambda tr: sum(r.result["applied_ins"] + r.result["applied_del"] for r in tr
+                             if r.kind == "update" and r.result)
+    served, alone, runs = [], [], []
+    sat_rps = None
+    for k, f in enumerate((None, 0.1, 0.5, 0.9, 1.2)):
+        tr = S.make_updates(graphs, N, None if f is None else f * sat_rps, 5100 + k, rid0=(k + 1) * 10 ** 6)
+        alone.append(fresh(tr))
+        served.append(tr)
+        wall = srv.serve(tr, arrival=f is not None)
+        if f is None:
+            sat_rps = N / wall
+        runs.append({"rate_factor": f, "offered_per_s": None if f is None else f * sat_rps,
+                     "requests_per_s": N / wall, "updates_per_s": applied(tr) / wall, **S.latency_stats(tr)})
+        log(f"rate {'saturation' if f is None else f}: {N / wall:.1f} requests/s, "
+            f"{applied(tr) / wall:.3e} updates/s, p50 {runs[-1]['p50_ms']:.2f} ms, p99 {runs[-1]['p99_ms']:.2f} ms")
+    mixed_ret = fresh(retires)
+    srv.serve(mixed_ret, arrival=False)
+    srv.close()
+    # the same graphs and requests, one request at a time
+    srv = S.Server(1 << 60, 1)
+    srv.serve(fresh(admits), arrival=False)
+    for tr in alone:
+        srv.serve(tr, arrival=False)
+    alone_ret = fresh(retires)
+    srv.serve(alone_ret, arrival=False)
+    srv.close()
+    same, errors = True, 0
+    for a, b in zip(served, alone):
+        for x, y in zip(a, b):
+            errors += (x.error is not None) + (y.error is not None)
+            if x.kind == "query":
+                same = same and np.array_equal(x.result.view(np.int64), y.result.view(np.int64))
+            elif x.kind == "update":
+                same = same and x.result == y.result
+    for x, y in zip(mixed_ret, alone_ret):
+        same = same and np.array_equal(x.result["levels"], y.result["levels"])
+    log(f"identical to one-at-a-time serving: {same}, errors {errors}")
+    out = {
+        "metric": METRIC, "value": runs[0]["updates_per_s"], "unit": "edge updates/s", "n_gpus": 1,
+        "steps": N, "warmup": 0, "ms_per_step": 1e3 / sat_rps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"serving-{len(graphs)}-rmat-scale{lo}..{hi}-ef16", "graphs": len(graphs),
+                   "edges": m_total, "workers": args.workers, "requests_per_run": N,
+                   "step": "one request: an update batch (1e2..1e6, 70% ins) or a 1e3-vertex coreness query"},
+        "latency": runs, "identical_to_alone": same, "errors": errors, "build_s": t_build,
     }
     print(json.dumps(out), flush=True)
 

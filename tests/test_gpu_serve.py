@@ -1,0 +1,126 @@
+"""Serving loop: requests of many graphs served by several workers at once,
+arriving as a Poisson stream, give exactly the results of serving each
+graph alone (one request at a time, in arrival order), and both equal the
+CPU oracle replaying each graph's requests in order (levels at retirement
+and every coreness query)."""
+import copy
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2106_03824_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def make_trace(ngraphs, nreq, seed, rate):
+    from paper_2106_03824_amd.serve import Request
+    rng = random.Random(seed)
+    reqs, t, rid = [], 0.0, 0
+    graphs = {}
+    for g in range(ngraphs):
+        sc = rng.randint(8, 12)
+        n = 2 ** sc
+        e = W.rmat(sc, 8 * n, seed=seed * 100 + g)
+        graphs[g] = (n, e)
+        reqs.append(Request(rid, g, "admit", t, (n, e)))
+        rid += 1
+    last = {g: 0.0 for g in graphs}
+    for i in range(nreq):
+        t += rng.expovariate(rate)
+        g = rng.randrange(ngraphs)
+        n, e = graphs[g]
+        if rng.random() < 0.5:
+            size = int(round(10 ** rng.uniform(1, 3.3)))
+            if rng.random() < 0.7:
+                r = np.random.default_rng(seed * 7919 + i)
+                ins = r.integers(0, n, size=(size, 2), dtype=np.int32)
+                reqs.append(Request(rid, g, "update", t, (ins, None)))
+            else:
+                reqs.append(Request(rid, g, "update", t, (None, W.sample_edges(e, min(size, len(e)), seed + i))))
+        else:
+            r = np.random.default_rng(seed * 104729 + i)
+            reqs.append(Request(rid, g, "query", t, r.integers(0, n, size=100, dtype=np.int32)))
+        rid += 1
+        last[g] = t
+    for g in graphs:
+        t += 1e-4
+        reqs.append(Request(rid, g, "retire", t))
+        rid += 1
+    return reqs
+
+
+def oracle_replay(reqs):
+    out = {}
+    oras = {}
+    for r in sorted(reqs, key=lambda r: r.rid):
+        if r.kind == "admit":
+            n, e = r.payload
+            oras[r.graph] = O.Oracle(n)
+            assert oras[r.graph].insert(e) == 0
+        elif r.kind == "update":
+            ins, dele = r.payload
+            assert oras[r.graph].update(ins, dele) == 0
+        elif r.kind == "query":
+            out[r.rid] = oras[r.graph].coreness()[r.payload]
+        else:
+            out[r.rid] = oras[r.graph].levels()
+    return out
+
+
+def results(reqs):
+    out = {}
+    for r in reqs:
+        assert r.error is None, (r.kind, r.error)
+        if r.kind == "query":
+            out[r.rid] = r.result
+        elif r.kind == "retire":
+            out[r.rid] = r.result["levels"]
+    return out
+
+
+def same(a, b):
+    assert a.keys() == b.keys()
+    for k in a:
+        x, y = np.asarray(a[k]), np.asarray(b[k])
+        assert x.dtype == y.dtype and np.array_equal(x.view(np.int64) if x.dtype == np.float64 else x,
+                                                     y.view(np.int64) if y.dtype == np.float64 else y), k
+
+
+def test_serving_mix_equals_alone_equals_oracle():
+    from paper_2106_03824_amd.serve import replay
+    reqs = make_trace(10, 120, 5, rate=4000.0)
+    alone = copy.deepcopy(reqs)
+    say("serve: mixed, 6 workers, Poisson arrivals")
+    replay(reqs, budget_bytes=64 << 30, workers=6, arrival=True)
+    say("serve: alone, 1 worker")
+    replay(alone, budget_bytes=64 << 30, workers=1, arrival=False)
+    say("serve: oracle replay")
+    ref = oracle_replay(reqs)
+    same(results(reqs), results(alone))
+    same(results(reqs), ref)
+    # the mixed run really overlapped requests of different graphs
+    spans = sorted((r.start, r.done, r.graph) for r in reqs)
+    assert any(b[0] < a[1] and b[2] != a[2] for a, b in zip(spans, spans[1:]))
+
+
+def test_serving_admission_waits_for_budget():
+    """With room for about two graphs at a time, admissions queue behind
+    retirements and results are unchanged."""
+    from paper_2106_03824_amd.serve import footprint_bytes, replay
+    reqs = make_trace(5, 30, 9, rate=4000.0)
+    alone = copy.deepcopy(reqs)
+    biggest = max(footprint_bytes(r.payload[0], len(r.payload[1])) for r in reqs if r.kind == "admit")
+    say("serve: small budget")
+    replay(reqs, budget_bytes=2 * biggest, workers=4, arrival=True)
+    replay(alone, budget_bytes=64 << 30, workers=1, arrival=False)
+    same(results(reqs), results(alone))
