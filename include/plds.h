@@ -162,8 +162,8 @@ int plds_stats(const plds_t *h, plds_stats_t *out);
 
 /* Per-step record of the last batch call, up to 2K rows of 4 int64 each,
  * copied to host memory `out` [cap][4]; *rows receives the number written by
- * the call.  Insertion step: (l, level the movers left, movers, cumulative
- * slots scanned), the movers landing at l+1.  Deletion step: (-1-l, -1,
+ * the call.  Insertion step: (l, level the movers left, movers, work items
+ * of its scan), the movers landing at l+1.  Deletion step: (-1-l, -1,
  * movers, cumulative slots scanned), the movers landing at l. */
 int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
 
@@ -175,8 +175,10 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode);
 /* Time one kernel of the level sweeps with HIP events recorded around each of
  * its launches (0 = off, 1 = insertion scan (which also finishes the
  * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
- * preparation, 5 = unused, 6 = the cooperative insertion sweep).  Results appear in plds_stats
- * (timed_launches, timed_ms). */
+ * preparation, 5 = unused, 6 = the cooperative insertion sweep).  Every
+ * launch counts, including those of steps after the sweep has finished
+ * (the prebuilt step sequences run to their end; such launches return at
+ * once).  Results appear in plds_stats (timed_launches, timed_ms). */
 int plds_set_timing(plds_t *h, int32_t kernel);
 
 /* Checkpoint.  plds_dump_state writes the edge list (u < v, unordered) to the

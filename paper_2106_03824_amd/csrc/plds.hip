@@ -38,6 +38,7 @@ constexpr int32_t kMinCap = 8;       // smallest slab, slots
 constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels
 constexpr int kDlGrid = 1024;        // blocks of the desire-level kernel
 constexpr int kListGrid = 256;       // blocks of the per-mover list kernels
+constexpr int kApplyGrid = 1024;     // most blocks of the batch-application kernels
 constexpr int32_t kInf = INT32_MAX;
 // During an insertion step its movers carry a bit in level[] that depends on
 // the step's parity (set by the step's preparation, cleared by the next
@@ -294,23 +295,26 @@ __device__ __forceinline__ void bpush(int32_t *list, int32_t *n, int32_t cap, bo
 // Block-staged append.  Lanes add entries to a queue in LDS (one LDS atomic
 // per wavefront); the block moves the queue to the global list with a single
 // atomic on the list's counter, when fewer than `room` free entries are left
-// or at the end (room = kStage).  Same-address atomics on a global counter
-// are serialised by the memory system, so a hot loop that appends from many
-// wavefronts pays one per block and flush instead of one per wavefront.
-constexpr int kStage = 4096;
-struct Stage {
+// or at the end (room = the queue's capacity).  Same-address atomics on a
+// global counter are serialised by the memory system, so a hot loop that
+// appends from many wavefronts pays one per block and flush instead of one
+// per wavefront.  Loops that flush are block-uniform.
+template <class T, int CAP>
+struct StageT {
     int32_t n, base;
-    int32_t buf[kStage];
+    T buf[CAP];
 };
 
-__device__ __forceinline__ void stage_init(Stage &q) {
+template <class T, int CAP>
+__device__ __forceinline__ void st_init(StageT<T, CAP> &q) {
     if (threadIdx.x == 0) q.n = 0;
     __syncthreads();
 }
 
 // every active lane calls it; lanes with `pred` stage x (the caller keeps
-// the number staged since the last flush under kStage)
-__device__ __forceinline__ void stage_push(Stage &q, bool pred, int32_t x) {
+// the number staged since the last flush within CAP)
+template <class T, int CAP>
+__device__ __forceinline__ void st_push(StageT<T, CAP> &q, bool pred, T x) {
     uint64_t mask = __ballot(pred);
     if (mask == 0) return;
     int lane = __lane_id();
@@ -321,22 +325,37 @@ __device__ __forceinline__ void stage_push(Stage &q, bool pred, int32_t x) {
     if (pred) q.buf[base + __popcll(mask & ((1ull << lane) - 1))] = x;
 }
 
-// every thread of the block calls it (block-uniform control flow)
-__device__ void stage_flush(Stage &q, int32_t room, int32_t *list, int32_t *n, int32_t cap, Ctl *c) {
+// every thread of the block calls it; wr(i, x) stores entry x at list
+// position i (positions at or beyond `cap` are dropped and latch an error)
+template <class T, int CAP, class Wr>
+__device__ void st_flush(StageT<T, CAP> &q, int32_t room, int32_t *counter, int32_t cap, Ctl *c, Wr wr) {
     __syncthreads();
     int32_t k = q.n;
     __syncthreads();
-    if (k == 0 || k + room <= kStage) return;
-    if (threadIdx.x == 0) q.base = atomicAdd(n, k);
+    if (k == 0 || k + room <= CAP) return;
+    if (threadIdx.x == 0) q.base = atomicAdd(counter, k);
     __syncthreads();
     int32_t b = q.base;
     if (b + k > cap && threadIdx.x == 0) latch(c, kErrLevel);
     for (int i = threadIdx.x; i < k; i += blockDim.x)
-        if (b + i < cap) list[b + i] = q.buf[i];
+        if (b + i < cap) wr(b + i, q.buf[i]);
     __syncthreads();
     if (threadIdx.x == 0) q.n = 0;
     __syncthreads();
 }
+
+constexpr int kStage = 4096;
+using Stage = StageT<int32_t, kStage>;
+
+__device__ __forceinline__ void stage_init(Stage &q) { st_init(q); }
+__device__ __forceinline__ void stage_push(Stage &q, bool pred, int32_t x) { st_push(q, pred, x); }
+__device__ __forceinline__ void stage_flush(Stage &q, int32_t room, int32_t *list, int32_t *n, int32_t cap, Ctl *c) {
+    st_flush(q, room, n, cap, c, [=](int32_t i, int32_t x) { list[i] = x; });
+}
+
+// Per-level histograms in LDS are used when the handle has at most this many
+// levels (the dynamic LDS of one block, beside a Stage).
+constexpr int kHistMax = 11264;
 
 // ----------------------------------------------------------------- slabs
 __device__ bool slab_has(const int32_t *s, int32_t cap, int32_t key) {
@@ -397,10 +416,13 @@ __global__ void k_range_check(const int32_t *e, int64_t cnt, int32_t n, Ctl *ctl
 // self-loop, first copy only (hash set), then keep it iff its presence in the
 // graph equals want_present (insertions: absent, deletions: present).
 __global__ void k_dedupe(Dev d, const int32_t *e, int64_t cnt, int want_present) {
+    __shared__ StageT<int64_t, 2048> q;
+    st_init(q);
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int lane = threadIdx.x % kWave;
-    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x - lane; i0 < cnt; i0 += stride) {
-        int64_t i = i0 + lane;
+    int64_t *valid = (int64_t *)d.valid;   // pair (u, v) as one little-endian int64
+    auto wr = [=](int32_t k, int64_t x) { valid[k] = x; };
+    for (int64_t ib = blockIdx.x * (int64_t)blockDim.x; ib < cnt; ib += stride) {
+        int64_t i = ib + threadIdx.x;
         bool keep = false;
         int32_t u = 0, v = 0;
         if (i < cnt) {
@@ -433,38 +455,42 @@ __global__ void k_dedupe(Dev d, const int32_t *e, int64_t cnt, int want_present)
                 }
             }
         }
-        uint64_t mask = __ballot(keep);
-        if (mask == 0) continue;
-        int leader = __ffsll((unsigned long long)mask) - 1;
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&d.ctl->n_valid, __popcll(mask));
-        base = __shfl(base, leader, kWave);
-        if (keep) {
-            int32_t k = base + __popcll(mask & ((1ull << lane) - 1));
-            d.valid[2 * k] = u;
-            d.valid[2 * k + 1] = v;
-        }
+        st_push(q, keep, (int64_t)(((uint64_t)(uint32_t)v << 32) | (uint32_t)u));
+        st_flush(q, (int32_t)blockDim.x, &d.ctl->n_valid, INT32_MAX, d.ctl, wr);
     }
+    st_flush(q, 2048, &d.ctl->n_valid, INT32_MAX, d.ctl, wr);
 }
 
 // count new slots per endpoint; first touch records the vertex
 __global__ void k_touch(Dev d) {
+    __shared__ Stage q;
+    stage_init(q);
     int32_t nv = d.ctl->n_valid;
-    int stride = gridDim.x * blockDim.x, lane = threadIdx.x % kWave;
-    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < 2 * nv; i0 += stride) {
-        int i = i0 + lane;
+    int stride = gridDim.x * blockDim.x;
+    for (int ib = blockIdx.x * blockDim.x; ib < 2 * nv; ib += stride) {
+        int i = ib + threadIdx.x;
         int32_t x = i < 2 * nv ? d.valid[i] : -1;
         bool first = x >= 0 && atomicAdd(&d.addc[x], 1) == 0;
-        wpush(d.touch, &d.ctl->n_touch, d.n, first, x, d.ctl);
+        stage_push(q, first, x);
+        stage_flush(q, blockDim.x, d.touch, &d.ctl->n_touch, d.n, d.ctl);
     }
+    stage_flush(q, kStage, d.touch, &d.ctl->n_touch, d.n, d.ctl);
 }
 
 // slabs that would exceed 80% occupancy are regrown to 60% of the new size
 __global__ void k_plan_growth(Dev d) {
+    __shared__ StageT<int64_t, 2048> q;
+    __shared__ int64_t red[kBlock / kWave];
+    st_init(q);
     int32_t nt = d.ctl->n_touch;
-    int stride = gridDim.x * blockDim.x, lane = threadIdx.x % kWave;
-    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < nt; i0 += stride) {
-        int i = i0 + lane;
+    int stride = gridDim.x * blockDim.x;
+    int64_t req = 0;
+    auto wr = [=](int32_t k, int64_t e) {
+        d.grow[k] = (int32_t)(e & 0xffffffff);
+        d.newcap[k] = (int32_t)(e >> 32);
+    };
+    for (int ib = blockIdx.x * blockDim.x; ib < nt; ib += stride) {
+        int i = ib + threadIdx.x;
         bool grow = false;
         int32_t x = -1, ncap = 0;
         if (i < nt) {
@@ -480,21 +506,20 @@ __global__ void k_plan_growth(Dev d) {
                 }
                 grow = true;
                 ncap = (int32_t)nc;
+                req += nc;
             }
         }
-        uint64_t mask = __ballot(grow);
-        if (mask == 0) continue;
-        int leader = __ffsll((unsigned long long)mask) - 1;
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&d.ctl->n_grow, __popcll(mask));
-        base = __shfl(base, leader, kWave);
-        int64_t tot = wave_sum64(ncap);
-        if (lane == leader) atomicAdd((unsigned long long *)&d.ctl->grow_req, (unsigned long long)tot);
-        if (grow) {
-            int32_t g = base + __popcll(mask & ((1ull << lane) - 1));
-            d.grow[g] = x;
-            d.newcap[g] = ncap;
-        }
+        st_push(q, grow, (int64_t)(((uint64_t)(uint32_t)ncap << 32) | (uint32_t)x));
+        st_flush(q, (int32_t)blockDim.x, &d.ctl->n_grow, d.n, d.ctl, wr);
+    }
+    st_flush(q, 2048, &d.ctl->n_grow, d.n, d.ctl, wr);
+    req = wave_sum64(req);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = req;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int i = 0; i < (int)blockDim.x / kWave; i++) t += red[i];
+        if (t) atomicAdd((unsigned long long *)&d.ctl->grow_req, (unsigned long long)t);
     }
 }
 
@@ -587,11 +612,18 @@ __global__ void k_apply_del(Dev d) {
 // Initial candidates of Algorithm 2: endpoints of inserted edges that
 // violate Invariant 1, bucketed by level.
 __global__ void k_ins_seed(Dev d) {
+    extern __shared__ int32_t hist[];   // [K] when K <= kHistMax
+    __shared__ Stage q;
+    const bool lds = d.K <= kHistMax;
+    stage_init(q);
+    if (lds) {
+        for (int i = threadIdx.x; i < d.K; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+    }
     int32_t nt = d.ctl->n_touch;
     int stride = gridDim.x * blockDim.x;
-    int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
-    for (int i0 = gid - lane; i0 < nt; i0 += stride) {
-        int i = i0 + lane;
+    for (int ib = blockIdx.x * blockDim.x; ib < nt; ib += stride) {
+        int i = ib + threadIdx.x;
         int32_t x = -1, key = -1;
         if (i < nt) {
             x = d.touch[i];
@@ -599,8 +631,18 @@ __global__ void k_ins_seed(Dev d) {
             int32_t lx = d.level[x];
             if (d.up[x] > up_cap(d, gp(d, x), lx)) key = lx;
         }
-        wpush(d.cand, &d.ctl->n_cand, d.n, key >= 0, x, d.ctl);
-        wadd_key(d.lvl_cnt, key);
+        stage_push(q, key >= 0, x);
+        stage_flush(q, blockDim.x, d.cand, &d.ctl->n_cand, d.n, d.ctl);
+        if (lds) {
+            if (key >= 0) atomicAdd(&hist[key], 1);
+        } else {
+            wadd_key(d.lvl_cnt, key);
+        }
+    }
+    stage_flush(q, kStage, d.cand, &d.ctl->n_cand, d.n, d.ctl);
+    if (lds) {   // the flush above ended with a barrier
+        for (int i = threadIdx.x; i < d.K; i += blockDim.x)
+            if (hist[i]) atomicAdd(&d.lvl_cnt[i], hist[i]);
     }
 }
 
@@ -664,15 +706,35 @@ __global__ void k_level_scan(Dev d) {
     }
 }
 
+// Candidates into their level buckets.  With a histogram in LDS: each block
+// counts its candidates per level, takes one range per level from the
+// global cursors, and places its candidates in it.
 __global__ void k_level_scatter(Dev d) {
+    extern __shared__ int32_t hist[];   // [K] when K <= kHistMax
     int32_t nc = d.ctl->n_cand;
     int stride = gridDim.x * blockDim.x;
-    int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
-    for (int i0 = gid - lane; i0 < nc; i0 += stride) {
-        int i = i0 + lane;
-        int32_t x = i < nc ? d.cand[i] : -1;
-        int32_t pos = wadd_key(d.lvl_fill, x >= 0 ? d.level[x] : -1);
-        if (x >= 0) d.sorted[pos] = x;
+    if (d.K > kHistMax) {
+        int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
+        for (int i0 = gid - lane; i0 < nc; i0 += stride) {
+            int i = i0 + lane;
+            int32_t x = i < nc ? d.cand[i] : -1;
+            int32_t pos = wadd_key(d.lvl_fill, x >= 0 ? d.level[x] : -1);
+            if (x >= 0) d.sorted[pos] = x;
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < d.K; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) atomicAdd(&hist[d.level[d.cand[i]]], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.K; b += blockDim.x) {
+        int32_t c = hist[b];
+        if (c) hist[b] = atomicAdd(&d.lvl_fill[b], c);
+    }
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        int32_t x = d.cand[i];
+        d.sorted[atomicAdd(&hist[d.level[x]], 1)] = x;
     }
 }
 
@@ -978,18 +1040,11 @@ __device__ void sum_parts(Dev &d, int nparts, int64_t out[3]) {
     __syncthreads();
 }
 
-// Bookkeeping of a finished step (one thread): statistics, step log, and the
-// reset of the cascade list the step consumed.  sums: the step's scan
-// statistics, or NULL when they are summed at the end of the sweep.
-__device__ void ins_account(Dev &d, const InsStep &st, int32_t nmv, const int64_t *sums) {
+// Bookkeeping of a finished step (one thread): counts, step log, and the
+// reset of the cascade list the step consumed.  items: the step's work items
+// (the scan statistics are summed per block and totalled after the sweep).
+__device__ void ins_account(Dev &d, const InsStep &st, int32_t nmv, int64_t items) {
     Ctl *c = d.ctl;
-    if (sums) {
-        c->scanned += sums[0];
-        c->alg_U += sums[1];
-        c->alg_up1 += sums[2];
-    } else {
-        c->scanned = -1;   // no per-step slot count in the step log
-    }
     int64_t steps = st.l + 1 - st.phys;
     c->sweeps += steps;
     c->moves += (int64_t)nmv * steps;
@@ -999,9 +1054,26 @@ __device__ void ins_account(Dev &d, const InsStep &st, int32_t nmv, const int64_
         row[0] = st.l;
         row[1] = st.phys;
         row[2] = nmv;
-        row[3] = c->scanned;
+        row[3] = items;
     }
     c->casc_n[st.cur] = 0;
+}
+
+// Work items of the last step of parity q (its slab-size lists and chunks).
+__device__ __forceinline__ int64_t ins_items(const Ctl *c, int q) {
+    const int32_t *k = c->n_cls2[q];
+    return (k[0] + 7) / 8 + (k[1] + 3) / 4 + (k[2] + 1) / 2 + k[3] + c->n_chunks2[q];
+}
+
+// Totals of the scans' per-block statistics, accumulated over a sweep (one block).
+__global__ void k_ins_totals(Dev d, int nparts) {
+    int64_t sums[3];
+    sum_parts(d, nparts, sums);
+    if (threadIdx.x == 0) {
+        d.ctl->scanned = sums[0];
+        d.ctl->alg_U = sums[1];
+        d.ctl->alg_up1 = sums[2];
+    }
 }
 
 __device__ __forceinline__ void ins_store(Ctl *c, const InsStep &nx) {
@@ -1041,15 +1113,11 @@ __global__ void k_ins_prep(Dev d, int p) {
     } else {
         int32_t nmv = c->nmvb[p ^ 1], cn = c->casc_n[prv.cur ^ 1];
         cur = ins_decide(d, prv, nmv, cn, sh1);
-        if (b0) {
-            int64_t sums[3];
-            sum_parts(d, kSweepGrid, sums);
-            if (writer) {
-                ins_account(d, prv, nmv, sums);
-                c->pend_phys = prv.phys;
-                c->pend_l1 = prv.l + 1;
-                c->pend_n = nmv;
-            }
+        if (writer) {
+            ins_account(d, prv, nmv, ins_items(c, p ^ 1));
+            c->pend_phys = prv.phys;
+            c->pend_l1 = prv.l + 1;
+            c->pend_n = nmv;
         }
     }
     if (writer) {
@@ -1070,7 +1138,7 @@ __global__ void k_ins_scan(Dev d, int p) {
     }
     InsStep st = c->st[p];
     if (st.done) return;
-    ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, false);
+    ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, true);
 }
 
 // ---- the whole level loop in one cooperative launch
@@ -1140,7 +1208,7 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
             int32_t cn = c->casc_n[prev.cur ^ 1];
             st = ins_decide(d, prev, prev_nmv, cn, sh1);
             if (writer) {
-                ins_account(d, prev, prev_nmv, nullptr);
+                ins_account(d, prev, prev_nmv, ins_items(c, p ^ 1));
                 ins_store(c, st);
                 c->n_chunks2[p ^ 1] = 0;
                 c->n_cls2[p ^ 1][0] = c->n_cls2[p ^ 1][1] = c->n_cls2[p ^ 1][2] = c->n_cls2[p ^ 1][3] = 0;
@@ -1169,16 +1237,7 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
         d.occ[prev.phys] -= prev_nmv;
         d.occ[prev.l + 1] += prev_nmv;
     }
-    // statistics accumulated per block over all steps
-    if (grid_sync(bar, nblk) && bid == 0) {
-        int64_t sums[3];
-        sum_parts(d, nblk, sums);
-        if (threadIdx.x == 0) {
-            c->scanned = sums[0];
-            c->alg_U = sums[1];
-            c->alg_up1 = sums[2];
-        }
-    }
+    (void)grid_sync(bar, nblk);   // the statistics are totalled by the caller
     if (writer && __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         latch(c, kErrHang);
         c->done = 1;
@@ -1901,9 +1960,11 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
     rc = ctl_reset_batch(h, s);
     if (rc) return rc;
     HIPCHK(hipMemsetAsync(d.hset, 0xff, (size_t)(d.hmask + 1) * sizeof(uint64_t), s));
-    hipLaunchKernelGGL(k_dedupe, dim3(grid_for(cnt)), dim3(kBlock), 0, s, d, e, cnt, insert ? 0 : 1);
-    hipLaunchKernelGGL(k_touch, dim3(grid_for(2 * cnt)), dim3(kBlock), 0, s, d);
-    if (insert) hipLaunchKernelGGL(k_plan_growth, dim3(grid_for(2 * cnt)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_dedupe, dim3(grid_for(cnt, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, e, cnt,
+                       insert ? 0 : 1);
+    hipLaunchKernelGGL(k_touch, dim3(grid_for(2 * cnt, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
+    if (insert)
+        hipLaunchKernelGGL(k_plan_growth, dim3(grid_for(2 * cnt, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
     HIPCHK(hipGetLastError());
     rc = sync_ctl(h, s);
     if (rc) return rc;
@@ -2006,16 +2067,17 @@ int insertion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
     int nt = h->h_ctl->n_touch;
     HIPCHK(hipMemsetAsync(d.lvl_cnt, 0, (size_t)(h->K + 1) * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_ins_seed, dim3(grid_for(nt)), dim3(kBlock), 0, s, d);
+    size_t hist = (size_t)(h->K <= kHistMax ? h->K : 0) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_ins_seed, dim3(grid_for(nt, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d);
     hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, d);
-    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(nt, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d);
     HIPCHK(hipGetLastError());
     int rc = sync_ctl(h, s);
     if (rc) return rc;
     h->stats.viol_ins0 = h->h_ctl->n_cand;
+    HIPCHK(hipMemsetAsync(d.part, 0, 3 * kSweepGrid * sizeof(int64_t), s));
     if (!h->h_ctl->done && h->sweep_mode == 0 && coop_blocks(h) > 0) {
         HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(Bar), s));
-        HIPCHK(hipMemsetAsync(d.part, 0, 3 * kSweepGrid * sizeof(int64_t), s));
         Bar *bar = h->bar;
         void *args[] = {(void *)&d, (void *)&bar};
         tstart(h, 6, s);
@@ -2039,7 +2101,6 @@ int insertion_sweep(plds *h, hipStream_t s) {
             h->broken = true;
             return PLDS_ESTATE;
         }
-        int32_t log0 = h->h_ctl->n_log;
         if (use_graph) {
             rc = ins_graph(h);
             if (rc) return rc;
@@ -2062,8 +2123,12 @@ int insertion_sweep(plds *h, hipStream_t s) {
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
-        take_timing(h, h->h_ctl->n_log - log0);   // steps that did work
+        take_timing(h, h->ev_used);
     }
+    hipLaunchKernelGGL(k_ins_totals, dim3(1), dim3(kBlock), 0, s, d, kSweepGrid);
+    HIPCHK(hipGetLastError());
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
     Ctl *c = h->h_ctl;
     h->stats.sweeps_ins += c->sweeps;
     h->stats.moves_up += c->moves;
@@ -2095,7 +2160,6 @@ int deletion_sweep(plds *h, hipStream_t s) {
             h->broken = true;
             return PLDS_ESTATE;
         }
-        int32_t log0 = h->h_ctl->n_log;
         steps += run;
         for (int i = 0; i < run; i++) {
             hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
@@ -2111,7 +2175,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
-        take_timing(h, h->h_ctl->n_log - log0);   // steps that did work
+        take_timing(h, h->ev_used);
         run = std::min(run * 2, 128);
     }
     Ctl *c = h->h_ctl;
