@@ -160,16 +160,24 @@ int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *p
 /* Statistics of the last batch call. */
 int plds_stats(const plds_t *h, plds_stats_t *out);
 
-/* Per-step record of the last batch call, up to 2K rows of 4 int64 each,
+/* Per-step record of the last batch call, up to 4K rows of 4 int64 each,
  * copied to host memory `out` [cap][4]; *rows receives the number written by
  * the call.  Insertion step: (l, level the movers left, movers, work items
- * of its scan), the movers landing at l+1.  Deletion step: (-1-l, -1,
- * movers, cumulative slots scanned), the movers landing at l. */
+ * of its scan + 2^48 * kind), the movers landing at l+1; kind 0 = movers
+ * scan their slabs, 1 = climbing step, 2 = exit step (no move; l+1 = the
+ * level left).  Deletion step: (-1-l, -1, movers, cumulative slots
+ * scanned), the movers landing at l. */
 int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
 
 /* How the insertion level loop runs: 0 = the whole loop in one cooperative
  * launch with grid barriers between its parts (when the device supports it,
- * else as 1); 1 (default) = one kernel per part.  Results are identical. */
+ * else as 2); 1 (default) = one kernel per part, with climbing steps (a large
+ * group of movers climbing level after level is kept flagged, and only the
+ * vertices it leaves behind and the residents of the next two levels scan
+ * their slabs); 2 = one kernel per part, every step scanning its movers'
+ * slabs; 3 = as 1, with climbing steps for groups of any size (not only
+ * large ones), which exercises them on small graphs.  Results are
+ * identical. */
 int plds_set_sweep_mode(plds_t *h, int32_t mode);
 
 /* Time one kernel of the level sweeps with HIP events recorded around each of

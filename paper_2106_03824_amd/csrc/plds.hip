@@ -45,7 +45,17 @@ constexpr int32_t kInf = INT32_MAX;
 // one), so one gather of a neighbour's level also tells whether it moves.
 constexpr int32_t kMover0 = 1 << 30;   // mover of an insertion step of parity 0
 constexpr int32_t kMover1 = 1 << 29;   // mover of an insertion step of parity 1
-constexpr int32_t kLevelMask = (1 << 29) - 1;
+// Member of a climbing group (see climb_decide): its level field is stale,
+// the group's level is the step's.
+constexpr int32_t kClimb = 1 << 28;
+// Member of a climbing group that stops at the end of the current step (set
+// by the scan that finds it; other scans of the step still see it climb).
+constexpr int32_t kStop = 1 << 27;
+constexpr int32_t kLevelMask = (1 << 27) - 1;
+constexpr int kCw = 64;                // slots per work item of a climbing step
+constexpr int32_t kClimbMin = 8192;    // smallest group that climbs
+// step modes
+constexpr int32_t kPull = 0, kClimbStep = 1, kExit = 2;
 
 // error bits latched on device
 constexpr int32_t kErrRange = 1;     // id out of range
@@ -62,7 +72,7 @@ constexpr int32_t kErrHang = 32;     // a grid barrier wait gave up
 // `fresh` marks the first step of a sweep (chosen by the seeding, not by a
 // decision).
 struct InsStep {
-    int32_t l, phys, jump, cur, done, fresh;
+    int32_t l, phys, jump, cur, done, fresh, mode;
 };
 
 struct Ctl {
@@ -77,7 +87,13 @@ struct Ctl {
     int32_t n_cls2[2][4]; // insertion: movers per slab-size class, by step parity
     int32_t n_chunks2[2]; // insertion: large-slab work items, by step parity
     int32_t n_log;        // rows written to the step log in the current call
-    int32_t nmvb[2];      // movers of the last insertion step of parity 0 / 1
+    int32_t nmvb[2];      // flagged movers of the last insertion step of parity 0 / 1 (mover lists)
+    int32_t nmove[2];     // vertices moved by the last step of parity 0 / 1 (climbers of a climbing step)
+    int32_t n_cl;         // entries of the climber list
+    int32_t n_sl[2];      // stoppers landed by the last step of parity 0 / 1
+    int32_t n_cw[2];      // work items of the climbing step of parity 0 / 1
+    int32_t step_dec[2];  // up-decrements of climbers by the climbing step of parity 0 / 1
+    int64_t sum_up;       // sum of up over the climbing group
     InsStep st[2];        // insertion step state by step parity
     int32_t pend_phys, pend_l1, pend_n;   // occupancy change of the last step, applied one kernel later
     int32_t n_rc;         // desire-level recomputations of the current step
@@ -134,12 +150,22 @@ struct Dev {
     int32_t *mv1;                     // [n] movers of insertion steps of parity 1
     int64_t *sp;                      // [n] packed (stay << 32 | work items left) of insertion movers
     int32_t *cls[4];                  // [n] movers with slabs of <= 8, 16, 32, 64 slots
-    int64_t *steplog;                 // [2K][4] per-step record of the last call
+    int64_t *steplog;                 // [4K][4] per-step record of the last call
     int64_t *part;                    // [kSweepGrid][3] per-block statistics of a scan
     int64_t *chunks;                  // [chunk_cap]
     int64_t chunk_cap;
     int32_t *p0, *p1;                 // [n]
     int32_t *rc;                      // [n]
+    // climbing steps
+    int32_t climb_ok;                 // climbing steps allowed (plain handle, per-part kernels)
+    int32_t climb_min;                // smallest group that enters a climbing step
+    int32_t *lvb_start;               // [K+2] vertices with edges, bucketed by level at the sweep start
+    int32_t *lvb_fill;                // [K+2]
+    int32_t *lvb;                     // [n]
+    int32_t *cl;                      // [n] climber list (members that stopped are skipped by flag)
+    int32_t *sl0, *sl1;               // [n] vertices that stopped, by step parity
+    int64_t *cw;                      // [cw_cap] climbing-step work items (vertex, role, 64-slot piece)
+    int64_t cw_cap;
 };
 
 // Levels per group and table offset of the graph that holds vertex v.
@@ -692,9 +718,15 @@ __global__ void k_level_scan(Dev d) {
         d.ctl->jump = 0;
         d.ctl->done = z >= K;
         d.ctl->cur = 0;
-        d.ctl->st[1] = InsStep{z, z, 0, 0, z >= K, 1};
+        d.ctl->st[1] = InsStep{z, z, 0, 0, z >= K, 1, kPull};
         d.ctl->pend_n = 0;
         d.ctl->nmvb[0] = d.ctl->nmvb[1] = 0;
+        d.ctl->nmove[0] = d.ctl->nmove[1] = 0;
+        d.ctl->n_sl[0] = d.ctl->n_sl[1] = 0;
+        d.ctl->n_cw[0] = d.ctl->n_cw[1] = 0;
+        d.ctl->step_dec[0] = d.ctl->step_dec[1] = 0;
+        d.ctl->n_cl = 0;
+        d.ctl->sum_up = 0;
         for (int q = 0; q < 2; q++) {
             d.ctl->n_chunks2[q] = 0;
             d.ctl->n_cls2[q][0] = d.ctl->n_cls2[q][1] = d.ctl->n_cls2[q][2] = d.ctl->n_cls2[q][3] = 0;
@@ -783,20 +815,30 @@ __device__ __forceinline__ void add_chunks_w(Dev &d, int32_t v) {
 // packed (stay, chunks left) counter, and sort the movers into work lists by
 // slab size.  All level[] writes are plain stores: a previous mover that
 // moves again was already given the parity-p bit by the scan that finished
-// it, so the clearing (which keeps that bit) and the flagging write the same
-// value to it.  When `st.done`, only clears.  Returns false (on every block
-// alike) if the step is out of range.
-__device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, int32_t *sh) {
-    int32_t Mp = p ? kMover1 : kMover0, Mq = p ? kMover0 : kMover1;
+// it, so the clearing and the flagging write the same value to it.  When
+// `st.done`, only clears.  Returns false (on every block alike) if the step
+// is out of range.
+__device__ void ins_clear_flags(Dev &d, int p, int bid, int nblk, int32_t F) {
+    // the previous step's movers: a mover that still violates carries this
+    // step's parity bit (it moves again), which becomes F, the flag this
+    // step gives its movers.  The gathering of this kernel writes the same
+    // value, before or after; a value it wrote first (with F) must come out
+    // unchanged, so F survives when it is kClimb.
+    int32_t Mp = p ? kMover1 : kMover0;
     int stride = nblk * blockDim.x;
-    {
-        const int32_t *prev = p ? d.mv : d.mv1;
-        int32_t np = d.ctl->nmvb[p ^ 1];
-        for (int i = bid * blockDim.x + threadIdx.x; i < np; i += stride) {
-            int32_t u = prev[i];
-            d.level[u] = d.level[u] & ~Mq;
-        }
+    const int32_t *prev = p ? d.mv : d.mv1;
+    int32_t np = d.ctl->nmvb[p ^ 1];
+    for (int i = bid * blockDim.x + threadIdx.x; i < np; i += stride) {
+        int32_t u = prev[i];
+        int32_t raw = d.level[u];
+        d.level[u] = (raw & (kLevelMask | kClimb)) | ((raw & Mp) ? F : 0);
     }
+}
+
+__device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, int32_t *sh) {
+    int32_t Mp = p ? kMover1 : kMover0;
+    int stride = nblk * blockDim.x;
+    ins_clear_flags(d, p, bid, nblk, Mp);
     if (st.done) return true;
     int32_t l = st.l, phys = st.phys, cur = st.cur;
     if (phys < 0 || phys > l || l + 1 >= d.K) {
@@ -827,7 +869,7 @@ __device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nb
         for (int k = 0; k < 4; k++) bpush(d.cls[k], &ncls[k], d.n, cl == k, v, d.ctl, sh);
         add_chunks_b(d, cl == 4 ? v : -1, &d.ctl->n_chunks2[p], sh);
     }
-    if (bid == 0 && threadIdx.x == 0) d.ctl->nmvb[p] = nA + nB;
+    if (bid == 0 && threadIdx.x == 0) d.ctl->nmvb[p] = d.ctl->nmove[p] = nA + nB;
     return true;
 }
 
@@ -854,13 +896,18 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
     int nw = nblk * wpb;
     const int32_t *ncls = d.ctl->n_cls2[p];
     int32_t n0 = ncls[0], n1c = ncls[1], n2 = ncls[2], n3 = ncls[3];
-    int32_t i0 = (n0 + 7) / 8, i1 = (n1c + 3) / 4, i2 = (n2 + 1) / 2, i3 = n3, i4 = d.ctl->n_chunks2[p];
+    int32_t i0 = (n0 + 7) / 8, i1 = (n1c + 3) / 4, i2 = (n2 + 1) / 2, i3 = n3;
+    int32_t i4 = (int32_t)min((int64_t)d.ctl->n_chunks2[p], d.chunk_cap);
     int32_t total = i0 + i1 + i2 + i3 + i4;
     int32_t scanned = 0, nU = 0, n1 = 0;
     // pushes of one round: per wavefront up to kChunk neighbours plus 8 movers
     const int32_t room = wpb * (kChunk + kWave / 8);
     __shared__ Stage q_casc;
+    __shared__ StageT<int32_t, 1024> q_stop;   // movers that stop at l+1 (residents of the next step)
+    int32_t *slist = p ? d.sl1 : d.sl0;
     stage_init(q_casc);
+    st_init(q_stop);
+    auto wr_stop = [=](int32_t k, int32_t x) { slist[k] = x; };
     // rounds are block-uniform (every wavefront of the block runs the same
     // number), so the staged pushes can be flushed between rounds
     for (int tb = bid * wpb; tb < total; tb += nw) {
@@ -921,7 +968,7 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
         }
         if (v >= 0) scanned += (q == 0) ? hi - lo : 0;
         for (int o = W / 2; o > 0; o >>= 1) stay += __shfl_xor(stay, o, kWave);
-        bool viol = false;
+        bool viol = false, stop = false;
         if (q == 0 && v >= 0) {
             bool last = true;
             int32_t total_stay = stay;
@@ -937,13 +984,17 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
                 u -= total_stay;
                 d.up[v] = u;
                 viol = u > ub1;
+                stop = !viol && d.climb_ok;
                 d.level[v] = (l + 1) | Mp | (viol ? Mn : 0);
             }
         }
         stage_push(q_casc, viol, v);
+        st_push(q_stop, stop, v);
         stage_flush(q_casc, room, casc, &d.ctl->casc_n[nxt], d.n, d.ctl);
+        st_flush(q_stop, wpb * (kWave / 8), &d.ctl->n_sl[p], d.n, d.ctl, wr_stop);
     }
     stage_flush(q_casc, kStage, casc, &d.ctl->casc_n[nxt], d.n, d.ctl);
+    st_flush(q_stop, 1024, &d.ctl->n_sl[p], d.n, d.ctl, wr_stop);
     __shared__ int32_t red[3][kBlock / kWave];
     nU = wave_sum(nU);
     n1 = wave_sum(n1);
@@ -963,6 +1014,315 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
     __syncthreads();
 }
 
+
+// ---- climbing groups.  In long insertion sweeps a large set of vertices
+// often climbs level after level through levels that hold few other
+// vertices; every step would rescan all their slabs.  A climbing step
+// instead keeps the group flagged (kClimb; their level fields go stale) and
+// lets the other vertices do the work, which gives the same counters:
+//   * a vertex that stays at the step's level l (a resident of l, or a
+//     member that stopped there) takes one from up(v) of every climbing
+//     neighbour v (v moves to l+1 and leaves it behind); the decrement that
+//     takes up(v) to the cap of level l+1 marks v as stopping there;
+//   * a resident w of level l+1 gains one up-neighbour per climbing
+//     neighbour and joins the group if that lifts it over its cap;
+//   * a resident of level l+2 gains one up*-neighbour per climbing neighbour.
+// Climbers never gain up-neighbours (everything they count stays at or
+// above them) and keep violating the same cap inside a group, so the group
+// is exactly Algorithm 2's mover set of every level it passes.  A member
+// that stops has up(v) right and counts up*(v) afresh from its slab in the
+// next step.  Residents come from buckets of every vertex with edges by its
+// level at the start of the sweep: the sweep has not reached those levels.
+// With no resident at or just above the group's level, nothing can change
+// until the next occupied level, and the group skips there in one step.
+// Before the group would cross a group boundary (the cap changes), or when
+// it gets small against the levels' residents, an exit step puts the
+// members back on their level as ordinary movers of the next step.
+
+// Work item of a climbing step: (vertex, role, kCw-slot piece)
+__device__ __forceinline__ int64_t cw_item(int32_t v, int32_t role, int32_t piece) {
+    return ((int64_t)v << 32) | ((int64_t)role << 30) | (int64_t)piece;
+}
+constexpr int32_t kRoleStay = 0, kRoleStopped = 1, kRoleUp1 = 2, kRoleUp2 = 3;
+
+// Append the kCw-slot pieces of vertex v (v < 0: none) with `role`, one
+// atomic per block.  Every thread of the block calls it.
+__device__ __forceinline__ void add_cw_b(Dev &d, int32_t v, int32_t role, int32_t *counter, int32_t *sh) {
+    int32_t cap = v >= 0 ? d.cap[v] : 0;
+    int32_t np = (cap + kCw - 1) / kCw;
+    int32_t total = 0;
+    int32_t off = block_excl(np, &total, sh);
+    if (total == 0) return;
+    if (threadIdx.x == 0) sh[kBlock / kWave + 1] = atomicAdd(counter, total);
+    __syncthreads();
+    int32_t base = sh[kBlock / kWave + 1];
+    __syncthreads();
+    if (base + total > d.cw_cap) {
+        if (threadIdx.x == 0) latch(d.ctl, kErrPool);
+        return;
+    }
+    for (int32_t k = 0; k < np; k++) d.cw[base + off + k] = cw_item(v, role, k);
+}
+
+// Block-wide sum of an int64 (every thread calls it; valid in every thread).
+__device__ __forceinline__ int64_t block_sum64(int64_t x, int64_t *red) {
+    x = wave_sum64(x);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = x;
+    __syncthreads();
+    int64_t t = 0;
+    for (int i = 0; i < (int)blockDim.x / kWave; i++) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// After climbing step `prv`: the group's size, and whether it climbs on
+// (possibly skipping empty levels) or exits.  Every thread of a block calls it.
+__device__ InsStep climb_decide(Dev &d, const InsStep &prv, int p, int32_t *sh1, int32_t *nc_out) {
+    Ctl *c = d.ctl;
+    InsStep nx;
+    nx.jump = 0;
+    nx.done = 0;
+    nx.fresh = 0;
+    int32_t x1 = prv.l + 1;   // the group's level after the step
+    int32_t ns = d.lvl_start[x1 + 1] - d.lvl_start[x1];
+    int32_t nC = c->nmove[p ^ 1] - c->n_sl[p ^ 1] + c->casc_n[prv.cur ^ 1] + ns;
+    bool boundary = (x1 + 1) % d.L == 0 || x1 + 2 > d.K;   // the next landing level starts a group
+    bool go = nC > 0 && !boundary;
+    int32_t stay = 0, r1 = 0, r2 = 0;
+    if (go) {
+        // occupancy after the step (its own move is applied one kernel later)
+        stay = d.occ[x1] + c->nmove[p ^ 1] - nC;
+        r1 = d.occ[x1 + 1];
+        r2 = d.occ[x1 + 2];
+        go = (int64_t)(stay + r1 + r2) * 2 <= nC;
+    }
+    __syncthreads();
+    if (!go) {
+        *nc_out = 0;
+        nx.mode = kExit;
+        nx.l = x1 - 1;
+        nx.phys = x1;
+        nx.cur = prv.cur;   // it consumes nothing and adds the members to the joiners' list
+        return nx;
+    }
+    *nc_out = nC;
+    nx.mode = kClimbStep;
+    nx.cur = prv.cur ^ 1;
+    nx.phys = nx.l = x1;
+    if (stay == 0 && r1 == 0) {
+        int32_t b = min((x1 / d.L + 1) * d.L, d.K);   // first level of the next group
+        if (threadIdx.x == 0) sh1[0] = b;
+        __syncthreads();
+        for (int32_t z = x1 + 2 + threadIdx.x; z < b; z += blockDim.x)
+            if (d.occ[z] > 0) atomicMin(&sh1[0], z);
+        __syncthreads();
+        int32_t xl = sh1[0] - 2;   // the first occupied level is xl+2 (or the group ends at xl+2)
+        __syncthreads();
+        if (xl > x1) {
+            nx.l = xl;
+            nx.jump = 1;
+        }
+    }
+    return nx;
+}
+
+// Part 1 of a climbing step (parity p) at level st.l, the group at st.phys:
+// stopped members of the previous climbing step back to a plain level
+// (up* to be recounted), joiners (the cascade list and the level's sorted
+// candidates) into the group, then the step's work items: the vertices that
+// stay at l (when the group moves from its own level), the residents of l+1
+// and l+2.
+__device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, int p, int bid, int nblk,
+                                 int32_t *sh) {
+    __shared__ int64_t red[kBlock / kWave];
+    Ctl *c = d.ctl;
+    ins_clear_flags(d, p, bid, nblk, kClimb);
+    const int stride = nblk * blockDim.x;
+    const int32_t x = st.phys, l = st.l;
+    const bool after_climb = prv.mode == kClimbStep;
+    const bool landed_here = !prv.fresh && prv.l + 1 == x;   // the previous step's stoppers sit at x
+    const int32_t *slp = p ? d.sl0 : d.sl1;
+    const int32_t nsl = landed_here ? c->n_sl[p ^ 1] : 0;
+    const int32_t *casc = st.cur ? d.casc1 : d.casc0;
+    const int32_t nj = c->casc_n[st.cur];
+    const int32_t a0 = d.lvl_start[x], ns = d.lvl_start[x + 1] - a0;
+    int64_t dsum = 0;
+    // fix-ups: stopped members, joiners
+    for (int i0 = bid * blockDim.x; i0 < nsl + nj + ns; i0 += stride) {
+        int i = i0 + threadIdx.x;
+        int32_t v = -1;
+        if (i < nsl) {
+            if (after_climb) {
+                int32_t u = slp[i];
+                dsum -= d.up[u];
+                d.level[u] = x;
+                d.ups[u] = 0;
+            }
+        } else if (i < nsl + nj + ns) {
+            v = i < nsl + nj ? casc[i - nsl] : d.sorted[a0 + i - nsl - nj];
+            d.level[v] = x | kClimb;
+            dsum += d.up[v];
+        }
+        bpush(d.cl, &c->n_cl, d.n, v >= 0, v, c, sh);
+    }
+    dsum = block_sum64(dsum, red);
+    if (threadIdx.x == 0 && dsum) atomicAdd((unsigned long long *)&c->sum_up, (unsigned long long)dsum);
+    // work items
+    const int32_t cap_x = up_cap(d, gp(d, 0), x);
+    const int32_t *bk = d.lvb;
+    int32_t s0 = 0, s1 = 0, r1a = 0, r1b = 0, r2a = 0, r2b = 0;
+    if (l == x) {
+        s0 = d.lvb_start[x];
+        s1 = d.lvb_start[x + 1];
+    }
+    r1a = d.lvb_start[min(l + 1, d.K)];
+    r1b = d.lvb_start[min(l + 2, d.K)];
+    r2a = r1b;
+    r2b = d.lvb_start[min(l + 3, d.K)];
+    const int32_t nst = s1 - s0, nss = l == x ? nsl : 0, n1 = r1b - r1a, n2 = r2b - r2a;
+    const int32_t tot = nst + nss + n1 + n2;
+    for (int i0 = bid * blockDim.x; i0 < tot; i0 += stride) {
+        int i = i0 + threadIdx.x;
+        int32_t v = -1, role = 0;
+        if (i < nst) {
+            int32_t u = bk[s0 + i];
+            int32_t raw = d.level[u];
+            // a resident of x that stays (not climbing, within the cap); joiners
+            // being flagged right now are over the cap
+            if (!(raw & kClimb) && (raw & kLevelMask) == x && d.up[u] <= cap_x) v = u;
+            role = kRoleStay;
+        } else if (i < nst + nss) {
+            v = slp[i - nst];
+            role = after_climb ? kRoleStopped : kRoleStay;
+        } else if (i < nst + nss + n1) {
+            v = bk[r1a + i - nst - nss];
+            role = kRoleUp1;
+        } else if (i < tot) {
+            v = bk[r2a + i - nst - nss - n1];
+            role = kRoleUp2;
+        }
+        add_cw_b(d, v, role, &c->n_cw[p], sh);
+    }
+}
+
+// Part 1 of an exit step (the group at st.phys): stopped members of the last
+// climbing step back to a plain level (up* recounted by the step's scan), and
+// every member still climbing back on its level, appended to the joiners'
+// list so that the next step moves them as ordinary movers.
+__device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, int p, int bid, int nblk,
+                                int32_t *sh) {
+    __shared__ int64_t red[kBlock / kWave];
+    Ctl *c = d.ctl;
+    const int stride = nblk * blockDim.x;
+    const int32_t x = st.phys;
+    const int32_t *slp = p ? d.sl0 : d.sl1;
+    const int32_t nsl = c->n_sl[p ^ 1];
+    int32_t *join = (st.cur ^ 1) ? d.casc1 : d.casc0;
+    const int32_t ncl = c->n_cl;
+    for (int i0 = bid * blockDim.x; i0 < nsl + ncl; i0 += stride) {
+        int i = i0 + threadIdx.x;
+        int32_t v = -1, w = -1;
+        if (i < nsl) {
+            v = slp[i];
+            d.level[v] = x;
+            d.ups[v] = 0;
+        } else if (i < nsl + ncl) {
+            int32_t u = d.cl[i - nsl];
+            int32_t raw = d.level[u];
+            // still climbing (members that stopped carry kStop until their
+            // fix-up in this same kernel writes their plain level)
+            if ((raw & kClimb) && !(raw & kStop)) {
+                d.level[u] = x;
+                w = u;
+            }
+        }
+        bpush(join, &c->casc_n[st.cur ^ 1], d.n, w >= 0, w, c, sh);
+        add_cw_b(d, v, kRoleStopped, &c->n_cw[p], sh);
+    }
+    (void)red;
+    (void)prv;
+}
+
+// Part 2 of a climbing or exit step: the work items of part 1, a wavefront
+// each (kCw slots).  Exit steps only recount up* of stopped members.
+__device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nblk) {
+    __shared__ Stage q_join;
+    __shared__ StageT<int32_t, 1024> q_stop;
+    __shared__ int64_t red[kBlock / kWave];
+    Ctl *c = d.ctl;
+    const bool climb = st.mode == kClimbStep;
+    const int32_t l = st.l, slvl = st.phys;   // stopped members sit at st.phys
+    int32_t *join = (st.cur ^ 1) ? d.casc1 : d.casc0;
+    int32_t *slist = p ? d.sl1 : d.sl0;
+    auto wr_stop = [=](int32_t k, int32_t x) { slist[k] = x; };
+    const int32_t cap1 = up_cap(d, gp(d, 0), l + 1);   // the cap of level l+1 (one graph)
+    stage_init(q_join);
+    st_init(q_stop);
+    const int lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
+    const int nw = nblk * wpb;
+    const int32_t total = (int32_t)min((int64_t)c->n_cw[p], d.cw_cap);
+    int64_t scanned = 0, m1 = 0, dec = 0;
+    for (int tb = bid * wpb; tb < total; tb += nw) {
+        int32_t t = tb + threadIdx.x / kWave;
+        int32_t v = -1, role = 0, lo = 0, hi = 0;
+        if (t < total) {
+            int64_t desc = d.cw[t];
+            v = (int32_t)(desc >> 32);
+            role = (int32_t)((desc >> 30) & 3);
+            lo = (int32_t)(desc & ((1 << 30) - 1)) * kCw;
+            hi = min(lo + kCw, d.cap[v]);
+        }
+        int32_t e = lo + lane;
+        int32_t w = v >= 0 && e < hi ? d.pool[d.off[v] + e] : -1;
+        int32_t raw = w >= 0 ? d.level[w] : 0;
+        bool clim = w >= 0 && (raw & kClimb);
+        bool stop = false;
+        if (climb && role <= kRoleStopped && clim) {
+            int32_t old = atomicSub(&d.up[w], 1);
+            stop = old == cap1 + 1;
+            if (stop) d.level[w] = raw | kStop;   // the only write to w's level in this step
+            dec++;
+        }
+        st_push(q_stop, stop, w);
+        int32_t cnt = 0;
+        if (role == kRoleStopped) cnt = w >= 0 && (clim || (raw & kLevelMask) >= slvl - 1);
+        else if (role >= kRoleUp1) cnt = clim;
+        cnt = wave_sum(cnt);
+        bool jn = false;
+        if (lane == 0 && v >= 0) {
+            scanned += hi - lo;
+            if (role == kRoleStopped) {
+                if (cnt) atomicAdd(&d.ups[v], cnt);
+            } else if (role == kRoleUp1) {
+                if (cnt) {
+                    int32_t old = atomicAdd(&d.up[v], cnt);
+                    jn = old <= cap1 && old + cnt > cap1;
+                    m1 += cnt;
+                }
+            } else if (role == kRoleUp2) {
+                if (cnt) atomicAdd(&d.ups[v], cnt);
+            }
+        }
+        stage_push(q_join, jn, v);
+        stage_flush(q_join, wpb, join, &c->casc_n[st.cur ^ 1], d.n, c);
+        st_flush(q_stop, wpb * kWave, &c->n_sl[p], d.n, c, wr_stop);
+    }
+    stage_flush(q_join, kStage, join, &c->casc_n[st.cur ^ 1], d.n, c);
+    st_flush(q_stop, 1024, &c->n_sl[p], d.n, c, wr_stop);
+    // statistics: slots read, the group's up-neighbours (the U[v] reads of
+    // its moves), neighbours of level l+1 gained; decrements of the group's up
+    dec = block_sum64(dec, red);
+    if (threadIdx.x == 0 && dec) atomicAdd(&c->step_dec[p], (int32_t)dec);
+    scanned = block_sum64(scanned, red);
+    m1 = block_sum64(m1, red);
+    if (threadIdx.x == 0) {
+        int64_t u = (bid == 0 && climb) ? c->sum_up * (int64_t)(st.l + 1 - st.phys) : 0;
+        d.part[3 * bid] += scanned;
+        d.part[3 * bid + 1] += u;
+        d.part[3 * bid + 2] += m1;
+    }
+}
+
 // Part 4: the next step after step `st` (every thread of a block calls it and
 // gets the same answer).  The next movers sit at level z0: the marked
 // vertices at l+1, else the next level with sorted candidates.  If they are
@@ -974,12 +1334,15 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
 // go, its level set to y-1; the skipped sweeps and moves are counted by the
 // caller.  occ[] is read without this step's own update (applied later by
 // the caller): occ[z0] after the step is occ[z0] + (z0 == l+1 ? movers : 0).
-__device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn, int32_t *sh1) {
+__device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn, int32_t *sh1,
+                              int32_t *movers_out, int32_t *occz_out) {
     InsStep nx;
     nx.cur = st.cur ^ 1;
     nx.jump = 0;
     nx.done = 0;
     nx.fresh = 0;
+    nx.mode = kPull;
+    *movers_out = *occz_out = 0;
     int32_t l = st.l;
     int32_t z0 = cn > 0 ? l + 1 : (l + 1 < d.K ? d.next_nz[l + 1] : d.K);
     if (z0 >= d.K - 1) {       // nothing left (no vertex of the top group can violate Invariant 1)
@@ -991,6 +1354,8 @@ __device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn
     int32_t ns = d.lvl_start[z0 + 1] - d.lvl_start[z0];
     int32_t movers = (z0 == l + 1 ? cn : 0) + ns;
     int32_t occz = d.occ[z0] + (z0 == l + 1 ? nmv : 0);
+    *movers_out = movers;
+    *occz_out = occz;
     bool all = occz == movers;
     __syncthreads();
     if (threadIdx.x == 0) sh1[0] = INT32_MAX;
@@ -1049,12 +1414,12 @@ __device__ void ins_account(Dev &d, const InsStep &st, int32_t nmv, int64_t item
     c->sweeps += steps;
     c->moves += (int64_t)nmv * steps;
     c->top = max(c->top, (int64_t)(st.l + 1));
-    if (c->n_log < 2 * d.K) {
+    if (c->n_log < 4 * d.K) {
         int64_t *row = d.steplog + 4 * c->n_log++;
         row[0] = st.l;
         row[1] = st.phys;
         row[2] = nmv;
-        row[3] = items;
+        row[3] = items | ((int64_t)st.mode << 48);
     }
     c->casc_n[st.cur] = 0;
 }
@@ -1085,7 +1450,7 @@ __device__ __forceinline__ void ins_store(Ctl *c, const InsStep &nx) {
 }
 
 __device__ __forceinline__ InsStep ins_load(const Ctl *c) {
-    return InsStep{c->l, c->phys, c->jump, c->cur, c->done, 0};
+    return InsStep{c->l, c->phys, c->jump, c->cur, c->done, 0, kPull};
 }
 
 // ---- one kernel per part.  A step of parity p is two kernels: decide+prep
@@ -1107,26 +1472,56 @@ __global__ void k_ins_prep(Dev d, int p) {
         return;
     }
     InsStep cur;
+    int32_t nmove = 0, movers = 0, occz = 0;
     if (prv.fresh) {
         cur = prv;
         cur.fresh = 0;
+        if (!cur.done) {
+            movers = d.lvl_start[cur.phys + 1] - d.lvl_start[cur.phys];
+            occz = d.occ[cur.phys];
+        }
+    } else if (prv.mode == kClimbStep) {
+        cur = climb_decide(d, prv, p, sh1, &nmove);
     } else {
-        int32_t nmv = c->nmvb[p ^ 1], cn = c->casc_n[prv.cur ^ 1];
-        cur = ins_decide(d, prv, nmv, cn, sh1);
-        if (writer) {
-            ins_account(d, prv, nmv, ins_items(c, p ^ 1));
-            c->pend_phys = prv.phys;
-            c->pend_l1 = prv.l + 1;
-            c->pend_n = nmv;
+        cur = ins_decide(d, prv, c->nmove[p ^ 1], c->casc_n[prv.cur ^ 1], sh1, &movers, &occz);
+    }
+    // (not right after an exit step: the members that stopped in its last
+    // climbing step are residents of its level that no list holds)
+    if (prv.mode == kPull && d.climb_ok && !cur.done && !cur.jump && cur.l == cur.phys &&
+        (cur.l + 1) % d.L != 0 && cur.l + 2 <= d.K && movers >= d.climb_min) {
+        // enter a climbing step if the level's other vertices and the two
+        // levels above hold few vertices next to the movers
+        int32_t work = occz - movers + d.occ[cur.l + 1] + d.occ[cur.l + 2];
+        if ((int64_t)work * 2 <= movers) {
+            cur.mode = kClimbStep;
+            nmove = movers;
         }
     }
     if (writer) {
+        if (!prv.fresh) {
+            int32_t nm = c->nmove[p ^ 1];
+            ins_account(d, prv, nm, prv.mode == kPull ? ins_items(c, p ^ 1) : c->n_cw[p ^ 1]);
+            c->pend_phys = prv.phys;
+            c->pend_l1 = prv.l + 1;
+            c->pend_n = nm;
+            if (prv.mode == kClimbStep)
+                atomicAdd((unsigned long long *)&c->sum_up, (unsigned long long)(-(int64_t)c->step_dec[p ^ 1]));
+        }
         c->st[p] = cur;
         ins_store(c, cur);
         c->n_chunks2[p ^ 1] = 0;
         c->n_cls2[p ^ 1][0] = c->n_cls2[p ^ 1][1] = c->n_cls2[p ^ 1][2] = c->n_cls2[p ^ 1][3] = 0;
+        c->n_cw[p ^ 1] = 0;
+        c->n_sl[p] = 0;
+        c->step_dec[p] = 0;
+        if (cur.mode != kPull) {
+            c->nmvb[p] = 0;
+            c->nmove[p] = nmove;
+        }
     }
-    ins_prep_phase(d, cur, p, blockIdx.x, gridDim.x, sh);
+    if (cur.mode == kClimbStep) climb_prep_phase(d, prv, cur, p, blockIdx.x, gridDim.x, sh);
+    else if (cur.mode == kExit) exit_prep_phase(d, prv, cur, p, blockIdx.x, gridDim.x, sh);
+    else ins_prep_phase(d, cur, p, blockIdx.x, gridDim.x, sh);
 }
 
 __global__ void k_ins_scan(Dev d, int p) {
@@ -1138,7 +1533,72 @@ __global__ void k_ins_scan(Dev d, int p) {
     }
     InsStep st = c->st[p];
     if (st.done) return;
-    ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, true);
+    if (st.mode == kPull) {
+        ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, true);
+    } else {
+        if (st.mode == kExit && blockIdx.x == 0 && threadIdx.x == 0) {   // the group is gone
+            c->n_cl = 0;
+            c->sum_up = 0;
+        }
+        climb_scan_phase(d, st, p, blockIdx.x, gridDim.x);
+    }
+}
+
+// Vertices with edges, bucketed by level at the start of an insertion sweep
+// (counting sort with a histogram in LDS per block; K <= kHistMax).
+__global__ void k_bucket_count(Dev d) {
+    extern __shared__ int32_t hist[];
+    for (int i = threadIdx.x; i < d.K; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride)
+        if (d.deg[v] > 0) atomicAdd(&hist[d.level[v]], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.K; i += blockDim.x)
+        if (hist[i]) atomicAdd(&d.lvb_fill[i], hist[i]);
+}
+
+// One block of 1024: the counts in lvb_fill to bucket starts (lvb_start,
+// K+2 entries) and scatter cursors (lvb_fill).
+__global__ void k_bucket_scan(Dev d) {
+    __shared__ int32_t part[1024];
+    int K = d.K, tid = threadIdx.x, nt = blockDim.x;
+    int per = (K + nt - 1) / nt, lo = min(K, tid * per), hi = min(K, lo + per);
+    int32_t sum = 0;
+    for (int i = lo; i < hi; i++) sum += d.lvb_fill[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        int32_t a = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += a;
+        __syncthreads();
+    }
+    int32_t acc = part[tid] - sum;
+    for (int i = lo; i < hi; i++) {
+        int32_t cnt = d.lvb_fill[i];
+        d.lvb_start[i] = acc;
+        d.lvb_fill[i] = acc;
+        acc += cnt;
+    }
+    if (tid == nt - 1) d.lvb_start[K] = d.lvb_start[K + 1] = part[nt - 1];
+}
+
+__global__ void k_bucket_scatter(Dev d) {
+    extern __shared__ int32_t hist[];
+    for (int i = threadIdx.x; i < d.K; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride)
+        if (d.deg[v] > 0) atomicAdd(&hist[d.level[v]], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.K; b += blockDim.x) {
+        int32_t cnt = hist[b];
+        if (cnt) hist[b] = atomicAdd(&d.lvb_fill[b], cnt);
+    }
+    __syncthreads();
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride)
+        if (d.deg[v] > 0) d.lvb[atomicAdd(&hist[d.level[v]], 1)] = v;
 }
 
 // ---- the whole level loop in one cooperative launch
@@ -1205,8 +1665,8 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
     bool have_prev = false, occ_pending = false;
     while (true) {
         if (have_prev) {
-            int32_t cn = c->casc_n[prev.cur ^ 1];
-            st = ins_decide(d, prev, prev_nmv, cn, sh1);
+            int32_t cn = c->casc_n[prev.cur ^ 1], mv_unused, oc_unused;
+            st = ins_decide(d, prev, prev_nmv, cn, sh1, &mv_unused, &oc_unused);
             if (writer) {
                 ins_account(d, prev, prev_nmv, ins_items(c, p ^ 1));
                 ins_store(c, st);
@@ -1334,7 +1794,7 @@ __global__ void k_del_next(Dev d, int mode) {
     if (mode == 1 && c->done) return;
     if (mode == 1) {
         int32_t cur = c->cur;
-        if (c->n_log < 2 * d.K) {
+        if (c->n_log < 4 * d.K) {
             int64_t *row = d.steplog + 4 * c->n_log++;
             row[0] = -1 - c->l;
             row[1] = -1;
@@ -1790,6 +2250,7 @@ void free_all(plds *h) {
     dfree(d.cand), dfree(d.sorted), dfree(d.lvl_cnt), dfree(d.lvl_start), dfree(d.next_nz), dfree(d.occ), dfree(d.lvl_fill), dfree(d.steplog), dfree(d.part);
     for (int k = 0; k < 4; k++) dfree(d.cls[k]);
     dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.mv1), dfree(d.sp), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
+    dfree(d.lvb_start), dfree(d.lvb_fill), dfree(d.lvb), dfree(d.cl), dfree(d.sl0), dfree(d.sl1), dfree(d.cw);
     dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
     if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
@@ -1857,13 +2318,22 @@ int ensure_batch(plds *h, int64_t count) {
 }
 
 int ensure_chunks(plds *h) {
-    // one descriptor per kChunk slots of any slab plus one per vertex
+    // one descriptor per kChunk (kCw) slots of any slab plus one per vertex
     int64_t need = h->n + h->d.pool_cap / kChunk + 1;
-    if (need <= h->d.chunk_cap) return PLDS_OK;
-    dfree(h->d.chunks);
-    int rc = dalloc(&h->d.chunks, need);
-    h->d.chunk_cap = rc ? 0 : need;
-    return rc;
+    if (need > h->d.chunk_cap) {
+        dfree(h->d.chunks);
+        int rc = dalloc(&h->d.chunks, need);
+        h->d.chunk_cap = rc ? 0 : need;
+        if (rc) return rc;
+    }
+    need = h->n + h->d.pool_cap / kCw + 1;
+    if (need > h->d.cw_cap) {
+        dfree(h->d.cw);
+        int rc = dalloc(&h->d.cw, need);
+        h->d.cw_cap = rc ? 0 : need;
+        if (rc) return rc;
+    }
+    return PLDS_OK;
 }
 
 // exclusive scan of d.cap into newoff (int64), returns the total
@@ -1927,6 +2397,12 @@ int ctl_reset_batch(plds *h, hipStream_t s) {
     }
     c->nm = kInf;
     c->blocks_done = 0;
+    c->nmove[0] = c->nmove[1] = 0;
+    c->n_cl = 0;
+    c->n_sl[0] = c->n_sl[1] = 0;
+    c->n_cw[0] = c->n_cw[1] = 0;
+    c->step_dec[0] = c->step_dec[1] = 0;
+    c->sum_up = 0;
     c->sweeps = c->moves = c->scanned = c->dl_calcs = 0;
     c->alg_U = c->alg_up1 = 0;
     c->top = 0;
@@ -2066,6 +2542,9 @@ int coop_blocks(plds *h) {
 int insertion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
     int nt = h->h_ctl->n_touch;
+    // climbing steps: plain handles, per-part kernels, level histograms in LDS
+    d.climb_ok = (h->sweep_mode == 1 || h->sweep_mode == 3) && d.ng == 1 && h->K <= kHistMax ? 1 : 0;
+    d.climb_min = h->sweep_mode == 3 ? 1 : kClimbMin;
     HIPCHK(hipMemsetAsync(d.lvl_cnt, 0, (size_t)(h->K + 1) * sizeof(int32_t), s));
     size_t hist = (size_t)(h->K <= kHistMax ? h->K : 0) * sizeof(int32_t);
     hipLaunchKernelGGL(k_ins_seed, dim3(grid_for(nt, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d);
@@ -2076,6 +2555,14 @@ int insertion_sweep(plds *h, hipStream_t s) {
     if (rc) return rc;
     h->stats.viol_ins0 = h->h_ctl->n_cand;
     HIPCHK(hipMemsetAsync(d.part, 0, 3 * kSweepGrid * sizeof(int64_t), s));
+    if (d.climb_ok && !h->h_ctl->done) {
+        HIPCHK(hipMemsetAsync(d.lvb_fill, 0, (size_t)(h->K + 2) * sizeof(int32_t), s));
+        size_t lds = (size_t)h->K * sizeof(int32_t);
+        hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), lds, s, d);
+        hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, d);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), lds, s, d);
+        HIPCHK(hipGetLastError());
+    }
     if (!h->h_ctl->done && h->sweep_mode == 0 && coop_blocks(h) > 0) {
         HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(Bar), s));
         Bar *bar = h->bar;
@@ -2097,7 +2584,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
     bool use_graph = h->timed_kind != 4;
     int run = use_graph ? kGraphSteps : 8;
     while (!h->h_ctl->done && !h->h_ctl->err) {
-        if (steps > (int64_t)h->K + 1) {    // each step raises the level: at most K steps
+        if (steps > 2 * (int64_t)h->K + 2) {   // a level gets at most an exit step and a moving step
             h->broken = true;
             return PLDS_ESTATE;
         }
@@ -2267,10 +2754,12 @@ int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double l
     rc |= dalloc(&d.cand, n) | dalloc(&d.sorted, n);
     rc |= dalloc(&d.lvl_cnt, h->K + 1) | dalloc(&d.lvl_start, h->K + 1) | dalloc(&d.next_nz, h->K + 1);
     rc |= dalloc(&d.occ, h->K + 1) | dalloc(&d.lvl_fill, h->K + 1);
-    rc |= dalloc(&d.steplog, 8 * (int64_t)h->K) | dalloc(&d.part, 3 * kSweepGrid);
+    rc |= dalloc(&d.steplog, 16 * (int64_t)h->K) | dalloc(&d.part, 3 * kSweepGrid);
     rc |= dalloc(&d.casc0, n) | dalloc(&d.casc1, n) | dalloc(&d.mv, n) | dalloc(&d.mv1, n) | dalloc(&d.sp, n);
     for (int k = 0; k < 4; k++) rc |= dalloc(&d.cls[k], n);
     rc |= dalloc(&d.p0, n) | dalloc(&d.p1, n) | dalloc(&d.rc, n);
+    rc |= dalloc(&d.lvb_start, h->K + 2) | dalloc(&d.lvb_fill, h->K + 2) | dalloc(&d.lvb, n) | dalloc(&d.cl, n) |
+          dalloc(&d.sl0, n) | dalloc(&d.sl1, n);
     rc |= dalloc(&h->newoff, n) | dalloc(&h->bad, 8);
     int64_t pool = std::max<int64_t>(1 << 20, 12 * n + (edge_capacity_hint * 2 * 5) / 3);
     rc |= dalloc(&d.pool, pool);
@@ -2556,7 +3045,7 @@ int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *p
 }
 
 int plds_set_sweep_mode(plds_t *h, int32_t mode) {
-    if (!h || mode < 0 || mode > 1) return PLDS_EINVAL;
+    if (!h || mode < 0 || mode > 3) return PLDS_EINVAL;
     h->sweep_mode = mode;
     return PLDS_OK;
 }

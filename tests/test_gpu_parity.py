@@ -42,13 +42,15 @@ STAT_KEYS = (("applied_ins", "applied_ins"), ("applied_del", "applied_del"), ("s
 class Pair:
     """A GPU handle and an oracle fed the same batches."""
 
-    def __init__(self, n, delta=0.4, lam=3.0, L=0, sweep_mode=1):
-        """sweep_mode 0: one cooperative launch; 1: prebuilt graph of step
-        kernels; 2: step kernels launched one by one (what kernel timing of
-        the preparation kernel selects)."""
+    def __init__(self, n, delta=0.4, lam=3.0, L=0, sweep_mode=1, direct=False):
+        """sweep_mode 0: one cooperative launch; 1: step kernels (prebuilt
+        graph) with climbing steps for large groups; 2: without climbing
+        steps; 3: climbing steps for groups of any size.  direct: step
+        kernels launched one by one (what kernel timing of the preparation
+        kernel selects)."""
         self.g = lib().PLDS(n, delta, lam, L)
-        lib().plds_set_sweep_mode(self.g.h, min(sweep_mode, 1))
-        if sweep_mode == 2:
+        lib().plds_set_sweep_mode(self.g.h, sweep_mode)
+        if direct:
             lib().plds_set_timing(self.g.h, "ins_prep")
         self.o = O.Oracle(n, delta, lam, L)
         self.n = n
@@ -157,7 +159,7 @@ def test_random_small(seed):
     L = rng.choice([0, 0, 2, 3])
     delta, lam = rng.choice([(0.4, 3.0), (1.0, 3.0), (0.2, 6.0)])
     say("random small", seed, n, L, delta, lam)
-    p = Pair(n, delta, lam, L, sweep_mode=seed % 3)
+    p = Pair(n, delta, lam, L, sweep_mode=seed % 4, direct=seed % 5 == 1)
     for it in range(6):
         ins = [(rng.randrange(n), rng.randrange(n)) for _ in range(rng.randrange(0, 4 * n))]
         cur = p.o.edges().tolist()
@@ -185,14 +187,15 @@ def test_rmat_tiny_config():
     p.step(ins=W.new_pairs(n, cur, 5000, 1003), dele=W.sample_edges(cur, 5000, 1004))
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
-def test_rmat_multi_batch(mode):
+@pytest.mark.parametrize("mode,direct", [(0, False), (1, False), (1, True), (2, False), (3, False), (3, True)])
+def test_rmat_multi_batch(mode, direct):
     """RMAT scale 14, edge factor 16, built in 4 insertion batches, then mixed
-    and deletion batches, each compared with the oracle; both ways of running
-    the insertion level loop (one cooperative launch / one kernel per part)."""
+    and deletion batches, each compared with the oracle; every way of running
+    the insertion level loop (one cooperative launch; kernels per part with
+    or without climbing steps, replayed from a graph or launched one by one)."""
     n = 2 ** 14
     e = W.permute_edges(W.rmat(14, 16 * n, seed=3), 2001)
-    p = Pair(n, sweep_mode=mode)
+    p = Pair(n, sweep_mode=mode, direct=direct)
     for i, c in enumerate(np.array_split(e, 4)):
         say("rmat14 build", i)
         p.step(ins=c)

@@ -30,7 +30,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("mode", [1])
+@pytest.mark.parametrize("mode", [1, 2])
 def test_rmat20_stream_against_oracle_trace(mode):
     from paper_2106_03824_amd import plds as P
     from paper_2106_03824_amd import workloads as W
