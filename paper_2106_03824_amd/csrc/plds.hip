@@ -90,6 +90,7 @@ struct Ctl {
     int32_t nmvb[2];      // flagged movers of the last insertion step of parity 0 / 1 (mover lists)
     int32_t nmove[2];     // vertices moved by the last step of parity 0 / 1 (climbers of a climbing step)
     int32_t n_cl;         // entries of the climber list
+    int32_t n_cl_snap;    // entries of the climber list before the current preparation
     int32_t n_sl[2];      // stoppers landed by the last step of parity 0 / 1
     int32_t n_cw[2];      // work items of the climbing step of parity 0 / 1
     int32_t step_dec[2];  // up-decrements of climbers by the climbing step of parity 0 / 1
@@ -899,6 +900,7 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
     int32_t i0 = (n0 + 7) / 8, i1 = (n1c + 3) / 4, i2 = (n2 + 1) / 2, i3 = n3;
     int32_t i4 = (int32_t)min((int64_t)d.ctl->n_chunks2[p], d.chunk_cap);
     int32_t total = i0 + i1 + i2 + i3 + i4;
+    if (bid * (int)(blockDim.x / kWave) >= total) return;   // no work item for this block (block-uniform)
     int32_t scanned = 0, nU = 0, n1 = 0;
     // pushes of one round: per wavefront up to kChunk neighbours plus 8 movers
     const int32_t room = wpb * (kChunk + kWave / 8);
@@ -1086,8 +1088,8 @@ __device__ InsStep climb_decide(Dev &d, const InsStep &prv, int p, int32_t *sh1,
     int32_t x1 = prv.l + 1;   // the group's level after the step
     int32_t ns = d.lvl_start[x1 + 1] - d.lvl_start[x1];
     int32_t nC = c->nmove[p ^ 1] - c->n_sl[p ^ 1] + c->casc_n[prv.cur ^ 1] + ns;
-    bool boundary = (x1 + 1) % d.L == 0 || x1 + 2 > d.K;   // the next landing level starts a group
-    bool go = nC > 0 && !boundary;
+    bool top = x1 + 2 > d.K;
+    bool go = nC > 0 && !top;
     int32_t stay = 0, r1 = 0, r2 = 0;
     if (go) {
         // occupancy after the step (its own move is applied one kernel later)
@@ -1146,11 +1148,17 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
     const int32_t *casc = st.cur ? d.casc1 : d.casc0;
     const int32_t nj = c->casc_n[st.cur];
     const int32_t a0 = d.lvl_start[x], ns = d.lvl_start[x + 1] - a0;
+    // Landing on the first level of a group raises the cap: the members
+    // whose up is within the new cap stop there without any decrement.
+    const bool boundary = l == x && (x + 1) % d.L == 0;
+    const int32_t cap_new = boundary ? up_cap(d, gp(d, 0), x + 1) : 0;
+    int32_t *sln = p ? d.sl1 : d.sl0;
+    const int32_t ncl0 = boundary ? c->n_cl_snap : 0;   // members of earlier steps
     int64_t dsum = 0;
-    // fix-ups: stopped members, joiners
-    for (int i0 = bid * blockDim.x; i0 < nsl + nj + ns; i0 += stride) {
+    // fix-ups: stopped members, joiners; at a boundary, members that stop
+    for (int i0 = bid * blockDim.x; i0 < nsl + nj + ns + ncl0; i0 += stride) {
         int i = i0 + threadIdx.x;
-        int32_t v = -1;
+        int32_t v = -1, stopn = -1;
         if (i < nsl) {
             if (after_climb) {
                 int32_t u = slp[i];
@@ -1160,10 +1168,23 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
             }
         } else if (i < nsl + nj + ns) {
             v = i < nsl + nj ? casc[i - nsl] : d.sorted[a0 + i - nsl - nj];
-            d.level[v] = x | kClimb;
-            dsum += d.up[v];
+            int32_t uv = d.up[v];
+            bool st_now = boundary && uv <= cap_new;
+            d.level[v] = x | kClimb | (st_now ? kStop : 0);
+            dsum += uv;
+            if (st_now) stopn = v;
+        } else if (i < nsl + nj + ns + ncl0) {
+            int32_t u = d.cl[i - nsl - nj - ns];
+            int32_t raw = d.level[u];
+            // stopped members of the previous step are being fixed right
+            // now: they read as kStop or as a plain level, both skipped
+            if ((raw & kClimb) && !(raw & kStop) && d.up[u] <= cap_new) {
+                d.level[u] = raw | kStop;
+                stopn = u;
+            }
         }
         bpush(d.cl, &c->n_cl, d.n, v >= 0, v, c, sh);
+        bpush(sln, &c->n_sl[p], d.n, stopn >= 0, stopn, c, sh);
     }
     dsum = block_sum64(dsum, red);
     if (threadIdx.x == 0 && dsum) atomicAdd((unsigned long long *)&c->sum_up, (unsigned long long)dsum);
@@ -1256,11 +1277,12 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
     int32_t *slist = p ? d.sl1 : d.sl0;
     auto wr_stop = [=](int32_t k, int32_t x) { slist[k] = x; };
     const int32_t cap1 = up_cap(d, gp(d, 0), l + 1);   // the cap of level l+1 (one graph)
-    stage_init(q_join);
-    st_init(q_stop);
     const int lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
     const int nw = nblk * wpb;
     const int32_t total = (int32_t)min((int64_t)c->n_cw[p], d.cw_cap);
+    if (bid * wpb >= total && !(bid == 0 && climb)) return;   // no item for this block (block-uniform)
+    stage_init(q_join);
+    st_init(q_stop);
     int64_t scanned = 0, m1 = 0, dec = 0;
     for (int tb = bid * wpb; tb < total; tb += nw) {
         int32_t t = tb + threadIdx.x / kWave;
@@ -1512,7 +1534,6 @@ __global__ void k_ins_prep(Dev d, int p) {
         c->n_chunks2[p ^ 1] = 0;
         c->n_cls2[p ^ 1][0] = c->n_cls2[p ^ 1][1] = c->n_cls2[p ^ 1][2] = c->n_cls2[p ^ 1][3] = 0;
         c->n_cw[p ^ 1] = 0;
-        c->n_sl[p] = 0;
         c->step_dec[p] = 0;
         if (cur.mode != kPull) {
             c->nmvb[p] = 0;
@@ -1533,15 +1554,18 @@ __global__ void k_ins_scan(Dev d, int p) {
     }
     InsStep st = c->st[p];
     if (st.done) return;
-    if (st.mode == kPull) {
-        ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, true);
-    } else {
-        if (st.mode == kExit && blockIdx.x == 0 && threadIdx.x == 0) {   // the group is gone
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the next step's stoppers list (the preparation of this step read
+        // the previous one's); the climber list is not appended to here
+        c->n_sl[p ^ 1] = 0;
+        if (st.mode == kExit) {   // the group is gone
             c->n_cl = 0;
             c->sum_up = 0;
         }
-        climb_scan_phase(d, st, p, blockIdx.x, gridDim.x);
+        c->n_cl_snap = c->n_cl;
     }
+    if (st.mode == kPull) ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, true);
+    else climb_scan_phase(d, st, p, blockIdx.x, gridDim.x);
 }
 
 // Vertices with edges, bucketed by level at the start of an insertion sweep
