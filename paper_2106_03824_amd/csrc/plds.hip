@@ -1032,8 +1032,9 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
 // Climbers never gain up-neighbours (everything they count stays at or
 // above them) and keep violating the same cap inside a group, so the group
 // is exactly Algorithm 2's mover set of every level it passes.  A member
-// that stops has up(v) right and counts up*(v) afresh from its slab in the
-// next step.  Residents come from buckets of every vertex with edges by its
+// that stops has up(v) right; its up*(v) no longer changes in the sweep (the
+// levels below the sweep's frontier stay as they are) and is counted afresh
+// from its slab after the sweep (k_ups_recount).  Residents come from buckets of every vertex with edges by its
 // level at the start of the sweep: the sweep has not reached those levels.
 // With no resident at or just above the group's level, nothing can change
 // until the next occupied level, and the group skips there in one step.
@@ -1045,7 +1046,7 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
 __device__ __forceinline__ int64_t cw_item(int32_t v, int32_t role, int32_t piece) {
     return ((int64_t)v << 32) | ((int64_t)role << 30) | (int64_t)piece;
 }
-constexpr int32_t kRoleStay = 0, kRoleStopped = 1, kRoleUp1 = 2, kRoleUp2 = 3;
+constexpr int32_t kRoleStay = 0, kRoleUp1 = 2, kRoleUp2 = 3;
 
 // Append the kCw-slot pieces of vertex v (v < 0: none) with `role`, one
 // atomic per block.  Every thread of the block calls it.
@@ -1130,7 +1131,7 @@ __device__ InsStep climb_decide(Dev &d, const InsStep &prv, int p, int32_t *sh1,
 
 // Part 1 of a climbing step (parity p) at level st.l, the group at st.phys:
 // stopped members of the previous climbing step back to a plain level
-// (up* to be recounted), joiners (the cascade list and the level's sorted
+// (listed for the recount of up* after the sweep), joiners (the cascade list and the level's sorted
 // candidates) into the group, then the step's work items: the vertices that
 // stay at l (when the group moves from its own level), the residents of l+1
 // and l+2.
@@ -1159,12 +1160,13 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
     for (int i0 = bid * blockDim.x; i0 < nsl + nj + ns + ncl0; i0 += stride) {
         int i = i0 + threadIdx.x;
         int32_t v = -1, stopn = -1;
+        int32_t rcv = -1;
         if (i < nsl) {
             if (after_climb) {
                 int32_t u = slp[i];
                 dsum -= d.up[u];
                 d.level[u] = x;
-                d.ups[u] = 0;
+                rcv = u;
             }
         } else if (i < nsl + nj + ns) {
             v = i < nsl + nj ? casc[i - nsl] : d.sorted[a0 + i - nsl - nj];
@@ -1185,6 +1187,7 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
         }
         bpush(d.cl, &c->n_cl, d.n, v >= 0, v, c, sh);
         bpush(sln, &c->n_sl[p], d.n, stopn >= 0, stopn, c, sh);
+        bpush(d.rc, &c->n_rc, d.n, rcv >= 0, rcv, c, sh);
     }
     dsum = block_sum64(dsum, red);
     if (threadIdx.x == 0 && dsum) atomicAdd((unsigned long long *)&c->sum_up, (unsigned long long)dsum);
@@ -1214,7 +1217,7 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
             role = kRoleStay;
         } else if (i < nst + nss) {
             v = slp[i - nst];
-            role = after_climb ? kRoleStopped : kRoleStay;
+            role = kRoleStay;
         } else if (i < nst + nss + n1) {
             v = bk[r1a + i - nst - nss];
             role = kRoleUp1;
@@ -1227,7 +1230,7 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
 }
 
 // Part 1 of an exit step (the group at st.phys): stopped members of the last
-// climbing step back to a plain level (up* recounted by the step's scan), and
+// climbing step back to a plain level (up* recounted after the sweep), and
 // every member still climbing back on its level, appended to the joiners'
 // list so that the next step moves them as ordinary movers.
 __device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, int p, int bid, int nblk,
@@ -1246,7 +1249,6 @@ __device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, i
         if (i < nsl) {
             v = slp[i];
             d.level[v] = x;
-            d.ups[v] = 0;
         } else if (i < nsl + ncl) {
             int32_t u = d.cl[i - nsl];
             int32_t raw = d.level[u];
@@ -1258,21 +1260,21 @@ __device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, i
             }
         }
         bpush(join, &c->casc_n[st.cur ^ 1], d.n, w >= 0, w, c, sh);
-        add_cw_b(d, v, kRoleStopped, &c->n_cw[p], sh);
+        bpush(d.rc, &c->n_rc, d.n, v >= 0, v, c, sh);
     }
     (void)red;
     (void)prv;
 }
 
-// Part 2 of a climbing or exit step: the work items of part 1, a wavefront
-// each (kCw slots).  Exit steps only recount up* of stopped members.
+// Part 2 of a climbing step: the work items of part 1, a wavefront each
+// (kCw slots).  Exit steps have none.
 __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nblk) {
     __shared__ Stage q_join;
     __shared__ StageT<int32_t, 1024> q_stop;
     __shared__ int64_t red[kBlock / kWave];
     Ctl *c = d.ctl;
     const bool climb = st.mode == kClimbStep;
-    const int32_t l = st.l, slvl = st.phys;   // stopped members sit at st.phys
+    const int32_t l = st.l;
     int32_t *join = (st.cur ^ 1) ? d.casc1 : d.casc0;
     int32_t *slist = p ? d.sl1 : d.sl0;
     auto wr_stop = [=](int32_t k, int32_t x) { slist[k] = x; };
@@ -1299,23 +1301,19 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
         int32_t raw = w >= 0 ? d.level[w] : 0;
         bool clim = w >= 0 && (raw & kClimb);
         bool stop = false;
-        if (climb && role <= kRoleStopped && clim) {
+        if (climb && role == kRoleStay && clim) {
             int32_t old = atomicSub(&d.up[w], 1);
             stop = old == cap1 + 1;
             if (stop) d.level[w] = raw | kStop;   // the only write to w's level in this step
             dec++;
         }
         st_push(q_stop, stop, w);
-        int32_t cnt = 0;
-        if (role == kRoleStopped) cnt = w >= 0 && (clim || (raw & kLevelMask) >= slvl - 1);
-        else if (role >= kRoleUp1) cnt = clim;
+        int32_t cnt = role >= kRoleUp1 ? clim : 0;
         cnt = wave_sum(cnt);
         bool jn = false;
         if (lane == 0 && v >= 0) {
             scanned += hi - lo;
-            if (role == kRoleStopped) {
-                if (cnt) atomicAdd(&d.ups[v], cnt);
-            } else if (role == kRoleUp1) {
+            if (role == kRoleUp1) {
                 if (cnt) {
                     int32_t old = atomicAdd(&d.up[v], cnt);
                     jn = old <= cap1 && old + cnt > cap1;
@@ -1450,6 +1448,27 @@ __device__ void ins_account(Dev &d, const InsStep &st, int32_t nmv, int64_t item
 __device__ __forceinline__ int64_t ins_items(const Ctl *c, int q) {
     const int32_t *k = c->n_cls2[q];
     return (k[0] + 7) / 8 + (k[1] + 3) / 4 + (k[2] + 1) / 2 + k[3] + c->n_chunks2[q];
+}
+
+// up* of the members that stopped in climbing steps: #neighbours at level
+// >= level(v) - 1, counted from the slab after the sweep (a wavefront per
+// vertex).
+__global__ void k_ups_recount(Dev d) {
+    int32_t cnt = d.ctl->n_rc;
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    int nw = gridDim.x * blockDim.x / kWave;
+    for (int i = wid; i < cnt; i += nw) {
+        int32_t v = d.rc[i];
+        int32_t lv = d.level[v], cap = d.cap[v];
+        const int32_t *s = d.pool + d.off[v];
+        int32_t k = 0;
+        for (int32_t e = lane; e < cap; e += kWave) {
+            int32_t w = s[e];
+            k += w >= 0 && d.level[w] >= lv - 1;
+        }
+        k = wave_sum(k);
+        if (lane == 0) d.ups[v] = k;
+    }
 }
 
 // Totals of the scans' per-block statistics, accumulated over a sweep (one block).
@@ -2637,6 +2656,9 @@ int insertion_sweep(plds *h, hipStream_t s) {
         take_timing(h, h->ev_used);
     }
     hipLaunchKernelGGL(k_ins_totals, dim3(1), dim3(kBlock), 0, s, d, kSweepGrid);
+    if (h->h_ctl->n_rc > 0)
+        hipLaunchKernelGGL(k_ups_recount, dim3(grid_for((int64_t)h->h_ctl->n_rc * kWave, kBlock, 2048)),
+                           dim3(kBlock), 0, s, d);
     HIPCHK(hipGetLastError());
     rc = sync_ctl(h, s);
     if (rc) return rc;
