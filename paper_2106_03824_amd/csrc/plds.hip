@@ -580,26 +580,43 @@ __global__ void k_grow_alloc(Dev d) {
     }
 }
 
-// move the live entries of each regrown slab into its new slab
+// Move the live entries of each regrown slab into its new slab.  A
+// wavefront takes 8 regrown slabs: a slab of at most 64 old slots is
+// served by a group of 8 lanes, larger ones by the whole wavefront in turn.
 __global__ void k_grow_move(Dev d) {
     int32_t ng = d.ctl->n_grow;
     int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     int nw = gridDim.x * blockDim.x / kWave;
-    for (int g = wid; g < ng; g += nw) {
-        int32_t x = d.grow[g];
-        if (d.newcap[g] == 0) continue;
-        const int32_t *os = d.pool + d.oldoff[g];
-        int32_t oc = d.oldcap[g];
-        for (int32_t s = lane; s < oc; s += kWave) {
-            int32_t w = os[s];
-            if (w >= 0 && !slab_put(d.pool + d.off[x], d.cap[x], w, &d.fill[x])) latch(d.ctl, kErrFull);
+    int grp = lane / 8, q = lane % 8;
+    for (int base = wid * 8; base < ng; base += nw * 8) {
+        int g = base + grp;
+        bool has = g < ng && d.newcap[g] != 0;
+        int32_t x = has ? d.grow[g] : -1, oc = has ? d.oldcap[g] : 0;
+        bool small = has && oc <= 64;
+        if (small) {
+            const int32_t *os = d.pool + d.oldoff[g];
+            for (int32_t t = q; t < oc; t += 8) {
+                int32_t w = os[t];
+                if (w >= 0 && !slab_put(d.pool + d.off[x], d.cap[x], w, &d.fill[x])) latch(d.ctl, kErrFull);
+            }
+        }
+        uint64_t big = __ballot(has && !small && q == 0);
+        while (big) {
+            int leader = __ffsll((unsigned long long)big) - 1;
+            big &= big - 1;
+            int gb = base + leader / 8;
+            int32_t xb = d.grow[gb], ob = d.oldcap[gb];
+            const int32_t *os = d.pool + d.oldoff[gb];
+            for (int32_t t = lane; t < ob; t += kWave) {
+                int32_t w = os[t];
+                if (w >= 0 && !slab_put(d.pool + d.off[xb], d.cap[xb], w, &d.fill[xb])) latch(d.ctl, kErrFull);
+            }
         }
     }
 }
 
-// Insert both directed copies; degrees and up/up* counters follow the
-// current levels: up(a) counts b iff level(b) >= level(a), up*(a) iff
-// level(b) >= level(a)-1.
+// Insert both directed copies; up/up* counters follow the current levels:
+// up(a) counts b iff level(b) >= level(a), up*(a) iff level(b) >= level(a)-1.
 __global__ void k_apply_ins(Dev d) {
     int32_t nv = d.ctl->n_valid;
     int stride = gridDim.x * blockDim.x;
@@ -608,8 +625,7 @@ __global__ void k_apply_ins(Dev d) {
         if (!slab_put(d.pool + d.off[a], d.cap[a], b, &d.fill[a])) latch(d.ctl, kErrFull);
         if (!slab_put(d.pool + d.off[b], d.cap[b], a, &d.fill[b])) latch(d.ctl, kErrFull);
         int32_t la = d.level[a], lb = d.level[b];
-        atomicAdd(&d.deg[a], 1);
-        atomicAdd(&d.deg[b], 1);
+        // deg grows by the endpoint counts in k_ins_seed
         if (lb >= la) atomicAdd(&d.up[a], 1);
         if (lb >= la - 1) atomicAdd(&d.ups[a], 1);
         if (la >= lb) atomicAdd(&d.up[b], 1);
@@ -654,6 +670,7 @@ __global__ void k_ins_seed(Dev d) {
         int32_t x = -1, key = -1;
         if (i < nt) {
             x = d.touch[i];
+            d.deg[x] += d.addc[x];   // the endpoint's new edges (counted by k_touch)
             d.addc[x] = 0;
             int32_t lx = d.level[x];
             if (d.up[x] > up_cap(d, gp(d, x), lx)) key = lx;
@@ -2049,10 +2066,15 @@ __global__ void k_compare(const int32_t *a, const int32_t *b, int32_t cnt, int32
         if (a[i] != b[i]) atomicAdd(bad, 1);
 }
 
+// after a load: the endpoints' new edges into deg, counts cleared
 __global__ void k_clear_touch(Dev d) {
     int32_t nt = d.ctl->n_touch;
     int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) d.addc[d.touch[i]] = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
+        int32_t x = d.touch[i];
+        d.deg[x] += d.addc[x];
+        d.addc[x] = 0;
+    }
 }
 
 __global__ void k_set_levels(Dev d, const int32_t *lv) {
@@ -2495,8 +2517,8 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
             if (rc) return rc;
             HIPCHK(hipMemsetAsync(d.pool + h->pool_top, 0xff, (size_t)req * sizeof(int32_t), s));
             hipLaunchKernelGGL(k_grow_alloc, dim3(grid_for(h->h_ctl->n_grow)), dim3(kBlock), 0, s, d);
-            hipLaunchKernelGGL(k_grow_move, dim3(grid_for((int64_t)h->h_ctl->n_grow * kWave)), dim3(kBlock), 0,
-                               s, d);
+            hipLaunchKernelGGL(k_grow_move, dim3(grid_for((int64_t)h->h_ctl->n_grow * 8)), dim3(kBlock), 0, s,
+                               d);
             h->pool_top += req;
         }
         hipLaunchKernelGGL(k_apply_ins, dim3(grid_for(*applied)), dim3(kBlock), 0, s, d);
