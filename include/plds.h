@@ -180,13 +180,17 @@ int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
  * identical. */
 int plds_set_sweep_mode(plds_t *h, int32_t mode);
 
-/* Time one kernel of the level sweeps with HIP events recorded around each of
- * its launches (0 = off, 1 = insertion scan (which also finishes the
- * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
- * preparation, 5 = unused, 6 = the cooperative insertion sweep).  Every
- * launch counts, including those of steps after the sweep has finished
- * (the prebuilt step sequences run to their end; such launches return at
- * once).  Results appear in plds_stats (timed_launches, timed_ms). */
+/* Time one kernel of the level sweeps (0 = off, 1 = insertion scan (which
+ * also finishes the movers), 2 = deletion scan, 3 = desire-level, 4 =
+ * insertion step preparation, 5 = unused, 6 = the cooperative insertion
+ * sweep).  Each launch of that kernel carries a HIP event pair that the
+ * runtime stamps at the dispatch's own start and end (hipExtLaunchKernel);
+ * the cooperative sweep has events recorded around it on the stream.
+ * While kind 1 or 4 is timed, insertion steps are launched one by one
+ * instead of from the prebuilt step graph.  Every launch counts, including
+ * those of steps after the sweep has finished (steps are issued in runs;
+ * such launches return at once).  Results appear in plds_stats
+ * (timed_launches, timed_ms). */
 int plds_set_timing(plds_t *h, int32_t kernel);
 
 /* Checkpoint.  plds_dump_state writes the edge list (u < v, unordered) to the

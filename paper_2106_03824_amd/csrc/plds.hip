@@ -12,6 +12,7 @@
 // stream; the host enqueues a run of steps and reads a small control block
 // back between runs.  Each step reads its level from the control block, so
 // the host never needs the level to enqueue it.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,6 +92,7 @@ struct Ctl {
     int32_t nmove[2];     // vertices moved by the last step of parity 0 / 1 (climbers of a climbing step)
     int32_t n_cl;         // entries of the climber list
     int32_t n_cl_snap;    // entries of the climber list before the current preparation
+    int32_t n_exit;       // members an exit step appends after the joiners (folded into casc_n by its scan)
     int32_t n_sl[2];      // stoppers landed by the last step of parity 0 / 1
     int32_t n_cw[2];      // work items of the climbing step of parity 0 / 1
     int32_t step_dec[2];  // up-decrements of climbers by the climbing step of parity 0 / 1
@@ -744,6 +746,7 @@ __global__ void k_level_scan(Dev d) {
         d.ctl->n_cw[0] = d.ctl->n_cw[1] = 0;
         d.ctl->step_dec[0] = d.ctl->step_dec[1] = 0;
         d.ctl->n_cl = 0;
+        d.ctl->n_exit = 0;
         d.ctl->sum_up = 0;
         for (int q = 0; q < 2; q++) {
             d.ctl->n_chunks2[q] = 0;
@@ -1249,16 +1252,20 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
 // Part 1 of an exit step (the group at st.phys): stopped members of the last
 // climbing step back to a plain level (up* recounted after the sweep), and
 // every member still climbing back on its level, appended to the joiners'
-// list so that the next step moves them as ordinary movers.
+// list so that the next step moves them as ordinary movers.  The appends go
+// behind the list's current end through their own counter (n_exit): the
+// list's size is an input of every block's step decision in this kernel and
+// must not change while blocks still read it.  The step's scan adds n_exit
+// to the size.
 __device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, int p, int bid, int nblk,
                                 int32_t *sh) {
-    __shared__ int64_t red[kBlock / kWave];
     Ctl *c = d.ctl;
     const int stride = nblk * blockDim.x;
     const int32_t x = st.phys;
     const int32_t *slp = p ? d.sl0 : d.sl1;
     const int32_t nsl = c->n_sl[p ^ 1];
-    int32_t *join = (st.cur ^ 1) ? d.casc1 : d.casc0;
+    const int32_t base = c->casc_n[st.cur ^ 1];
+    int32_t *join = ((st.cur ^ 1) ? d.casc1 : d.casc0) + base;
     const int32_t ncl = c->n_cl;
     for (int i0 = bid * blockDim.x; i0 < nsl + ncl; i0 += stride) {
         int i = i0 + threadIdx.x;
@@ -1276,10 +1283,9 @@ __device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, i
                 w = u;
             }
         }
-        bpush(join, &c->casc_n[st.cur ^ 1], d.n, w >= 0, w, c, sh);
+        bpush(join, &c->n_exit, d.n - base, w >= 0, w, c, sh);
         bpush(d.rc, &c->n_rc, d.n, v >= 0, v, c, sh);
     }
-    (void)red;
     (void)prv;
 }
 
@@ -1594,7 +1600,9 @@ __global__ void k_ins_scan(Dev d, int p) {
         // the next step's stoppers list (the preparation of this step read
         // the previous one's); the climber list is not appended to here
         c->n_sl[p ^ 1] = 0;
-        if (st.mode == kExit) {   // the group is gone
+        if (st.mode == kExit) {   // the group is gone; its members are joiners now
+            c->casc_n[st.cur ^ 1] += c->n_exit;
+            c->n_exit = 0;
             c->n_cl = 0;
             c->sum_up = 0;
         }
@@ -2239,7 +2247,6 @@ struct plds {
     hipGraphExec_t ins_exec = nullptr;
     Dev ins_graph_dev{};
     int par[2] = {0, 1};
-    int ins_graph_timed = -1;
     // optional event timing of one sweep kernel
     int32_t timed_kind = 0;
     std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -2332,7 +2339,8 @@ hipStream_t S(void *s) { return (hipStream_t)s; }
 
 constexpr int kEvPairs = 512;
 
-// record the start event of a timed launch of `kind` (no-op otherwise)
+// record the start event of a timed launch of `kind` (no-op otherwise);
+// for launches that hipExtLaunchKernel cannot make (cooperative ones)
 inline void tstart(plds *h, int kind, hipStream_t s) {
     if (h->timed_kind != kind || h->ev_used >= kEvPairs) return;
     (void)hipEventRecord(h->ev[2 * h->ev_used], s);
@@ -2341,6 +2349,19 @@ inline void tstop(plds *h, int kind, hipStream_t s) {
     if (h->timed_kind != kind || h->ev_used >= kEvPairs) return;
     (void)hipEventRecord(h->ev[2 * h->ev_used + 1], s);
     h->ev_used++;
+}
+
+// Launch a kernel; when it is the timed kind, with an event pair that the
+// runtime stamps at the dispatch's own start and end (no queue gap inside).
+template <class F, class... A>
+inline void tlaunch(plds *h, int kind, F f, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... a) {
+    if (h->timed_kind == kind && h->ev_used < kEvPairs) {
+        hipExtLaunchKernelGGL(f, grid, block, (uint32_t)lds, s, h->ev[2 * h->ev_used], h->ev[2 * h->ev_used + 1], 0,
+                              a...);
+        h->ev_used++;
+    } else {
+        hipLaunchKernelGGL(f, grid, block, lds, s, a...);
+    }
 }
 
 // Add the durations of the first `count` recorded launches (the ones that
@@ -2532,18 +2553,15 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
 
 constexpr int kGraphSteps = 16;
 
-// The insertion step sequence (prep, scan, fin, next) x kGraphSteps as one
-// graph of kernel nodes, rebuilt when the device buffers move.  With timing
-// of the scan (kind 1), event record nodes bracket every scan node.
+// The insertion step sequence (prep, scan) x kGraphSteps as one graph of
+// kernel nodes, rebuilt when the device buffers move.
 int ins_graph(plds *h) {
-    int timed = h->timed_kind == 1 ? 1 : 0;
-    if (h->ins_exec && timed == h->ins_graph_timed && !memcmp(&h->ins_graph_dev, &h->d, sizeof(Dev))) return 0;
+    if (h->ins_exec && !memcmp(&h->ins_graph_dev, &h->d, sizeof(Dev))) return 0;
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
     if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
     h->ins_exec = nullptr;
     h->ins_graph = nullptr;
     h->ins_graph_dev = h->d;
-    h->ins_graph_timed = timed;
     if (hipGraphCreate(&h->ins_graph, 0) != hipSuccess) return PLDS_EHIP;
     Dev *dv = &h->ins_graph_dev;
     void *a0[] = {(void *)dv, (void *)&h->par[0]};
@@ -2556,12 +2574,6 @@ int ins_graph(plds *h) {
     for (int i = 0; i < kGraphSteps; i++) {
         for (int k = 0; k < 2; k++) {
             hipGraphNode_t node;
-            if (timed && k == 1) {
-                if (hipGraphAddEventRecordNode(&node, h->ins_graph, prev ? &prev : nullptr, prev ? 1 : 0,
-                                               h->ev[2 * i]) != hipSuccess)
-                    return PLDS_EHIP;
-                prev = node;
-            }
             hipKernelNodeParams p{};
             p.func = const_cast<void *>(ks[k].f);
             p.gridDim = dim3(ks[k].grid);
@@ -2572,11 +2584,6 @@ int ins_graph(plds *h) {
             if (hipGraphAddKernelNode(&node, h->ins_graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
                 return PLDS_EHIP;
             prev = node;
-            if (timed && k == 1) {
-                if (hipGraphAddEventRecordNode(&node, h->ins_graph, &prev, 1, h->ev[2 * i + 1]) != hipSuccess)
-                    return PLDS_EHIP;
-                prev = node;
-            }
         }
     }
     if (hipGraphInstantiate(&h->ins_exec, h->ins_graph, nullptr, nullptr, 0) != hipSuccess) return PLDS_EHIP;
@@ -2646,7 +2653,8 @@ int insertion_sweep(plds *h, hipStream_t s) {
         }
     }
     int64_t steps = 0;
-    bool use_graph = h->timed_kind != 4;
+    // a timed step kernel is launched directly, so that its events bracket the dispatch alone
+    bool use_graph = h->timed_kind != 1 && h->timed_kind != 4;
     int run = use_graph ? kGraphSteps : 8;
     while (!h->h_ctl->done && !h->h_ctl->err) {
         if (steps > 2 * (int64_t)h->K + 2) {   // a level gets at most an exit step and a moving step
@@ -2656,19 +2664,14 @@ int insertion_sweep(plds *h, hipStream_t s) {
         if (use_graph) {
             rc = ins_graph(h);
             if (rc) return rc;
-            if (h->timed_kind == 1) h->ev_used = kGraphSteps;
             HIPCHK(hipGraphLaunch(h->ins_exec, s));
             steps += kGraphSteps;
         } else {
             steps += run;
             for (int i = 0; i < run; i++) {      // run is even: every run starts at parity 0
                 int par = i & 1;
-                tstart(h, 4, s);
-                hipLaunchKernelGGL(k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d, par);
-                tstop(h, 4, s);
-                tstart(h, 1, s);
-                hipLaunchKernelGGL(k_ins_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d, par);
-                tstop(h, 1, s);
+                tlaunch(h, 4, k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d, par);
+                tlaunch(h, 1, k_ins_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d, par);
             }
             run = std::min(run * 2, 256);
         }
@@ -2699,9 +2702,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void *)k_dl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return PLDS_EINVAL;
-    tstart(h, 3, s);
-    hipLaunchKernelGGL(k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 0);
-    tstop(h, 3, s);
+    tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 0);
     hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 0);
     HIPCHK(hipGetLastError());
     int rc = sync_ctl(h, s);
@@ -2718,13 +2719,9 @@ int deletion_sweep(plds *h, hipStream_t s) {
         steps += run;
         for (int i = 0; i < run; i++) {
             hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-            tstart(h, 2, s);
-            hipLaunchKernelGGL(k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
-            tstop(h, 2, s);
+            tlaunch(h, 2, k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
             hipLaunchKernelGGL(k_del_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-            tstart(h, 3, s);
-            hipLaunchKernelGGL(k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 1);
-            tstop(h, 3, s);
+            tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 1);
             hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 1);
         }
         HIPCHK(hipGetLastError());
