@@ -304,22 +304,50 @@ __device__ __forceinline__ int32_t block_excl(int32_t x, int32_t *total, int32_t
     return r;
 }
 
-// Block-wide append with one atomic per block (every thread calls it).
-__device__ __forceinline__ void bpush(int32_t *list, int32_t *n, int32_t cap, bool pred, int32_t x, Ctl *c,
-                                      int32_t *sh) {
-    int32_t total = 0;
-    int32_t r = block_excl(pred ? 1 : 0, &total, sh);
-    if (total == 0) return;
-    if (threadIdx.x == 0) sh[kBlock / kWave + 1] = atomicAdd(n, total);
-    __syncthreads();
-    int32_t base = sh[kBlock / kWave + 1];
-    if (pred) {
-        if (base + r < cap) list[base + r] = x;
-        else latch(c, kErrLevel);
+// Block-wide append to N lists at once (every thread calls it): the thread
+// adds cnt[k] entries to list k and pos[k] receives the list position of its
+// first one.  The N counters are bumped by N lanes of the first wavefront in
+// one instruction, so a block pays one atomic round trip for all lists
+// instead of one per list.  sh: LDS of at least N*(kBlock/kWave+2) ints.
+template <int N>
+__device__ __forceinline__ void block_append(const int32_t (&cnt)[N], int32_t *const (&ctr)[N], int32_t (&pos)[N],
+                                             int32_t *sh) {
+    constexpr int S = kBlock / kWave + 2;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nwv = blockDim.x / kWave;
+    int32_t off[N];
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        int32_t t = 0;
+        off[k] = wave_excl(cnt[k], &t);
+        if (lane == 0) sh[k * S + wv] = t;
     }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        const int k = threadIdx.x;
+        int32_t *mine = nullptr;
+#pragma unroll
+        for (int j = 0; j < N; j++)
+            if (k == j) mine = ctr[j];
+        int32_t acc = 0;
+        for (int i = 0; i < nwv; i++) {
+            int32_t t = sh[k * S + i];
+            sh[k * S + i] = acc;
+            acc += t;
+        }
+        sh[k * S + nwv] = acc > 0 ? atomicAdd(mine, acc) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; k++) pos[k] = sh[k * S + nwv] + sh[k * S + wv] + off[k];
     __syncthreads();
 }
 
+// Store x at list position at (pred only); positions at or beyond cap latch an error.
+__device__ __forceinline__ void put(int32_t *list, int32_t at, int32_t cap, bool pred, int32_t x, Ctl *c) {
+    if (!pred) return;
+    if (at < cap) list[at] = x;
+    else latch(c, kErrLevel);
+}
 
 // Block-staged append.  Lanes add entries to a queue in LDS (one LDS atomic
 // per wavefront); the block moves the queue to the global list with a single
@@ -380,6 +408,34 @@ __device__ __forceinline__ void stage_init(Stage &q) { st_init(q); }
 __device__ __forceinline__ void stage_push(Stage &q, bool pred, int32_t x) { st_push(q, pred, x); }
 __device__ __forceinline__ void stage_flush(Stage &q, int32_t room, int32_t *list, int32_t *n, int32_t cap, Ctl *c) {
     st_flush(q, room, n, cap, c, [=](int32_t i, int32_t x) { list[i] = x; });
+}
+
+// Final flush of two staged queues (every thread of the block calls it):
+// both counters are bumped by two lanes of one instruction, so the two
+// round trips overlap.
+template <class QA, class QB, class WA, class WB>
+__device__ void st_flush_both(QA &qa, int32_t *ca, int32_t capa, WA wa, QB &qb, int32_t *cb, int32_t capb, WB wb,
+                              Ctl *c) {
+    __syncthreads();
+    const int32_t ka = qa.n, kb = qb.n;
+    if (ka == 0 && kb == 0) return;   // block-uniform
+    if (threadIdx.x < 2) {
+        const bool b = threadIdx.x == 1;
+        const int32_t k = b ? kb : ka;
+        const int32_t base = k ? atomicAdd(b ? cb : ca, k) : 0;
+        if (b) qb.base = base;
+        else qa.base = base;
+    }
+    __syncthreads();
+    const int32_t ba = qa.base, bb = qb.base;
+    if (threadIdx.x == 0 && ((ka && ba + ka > capa) || (kb && bb + kb > capb))) latch(c, kErrLevel);
+    for (int i = threadIdx.x; i < ka; i += blockDim.x)
+        if (ba + i < capa) wa(ba + i, qa.buf[i]);
+    for (int i = threadIdx.x; i < kb; i += blockDim.x)
+        if (bb + i < capb) wb(bb + i, qb.buf[i]);
+    __syncthreads();
+    if (threadIdx.x == 0) qa.n = qb.n = 0;
+    __syncthreads();
 }
 
 // Per-level histograms in LDS are used when the handle has at most this many
@@ -792,25 +848,6 @@ __global__ void k_level_scatter(Dev d) {
 }
 
 // Work items of a step: kChunk-slot pieces of the movers' slabs, appended
-// with one atomic per block.  Every thread of the block calls it; threads
-// with v < 0 add nothing.
-__device__ __forceinline__ void add_chunks_b(Dev &d, int32_t v, int32_t *counter, int32_t *sh) {
-    int32_t nch = v >= 0 ? (d.cap[v] + kChunk - 1) / kChunk : 0;
-    int32_t total = 0;
-    int32_t off = block_excl(nch, &total, sh);
-    if (total == 0) return;
-    if (threadIdx.x == 0) sh[kBlock / kWave + 1] = atomicAdd(counter, total);
-    __syncthreads();
-    int32_t base = sh[kBlock / kWave + 1];
-    __syncthreads();
-    if (base + total > d.chunk_cap) {
-        if (threadIdx.x == 0) latch(d.ctl, kErrPool);
-        return;
-    }
-    for (int32_t k = 0; k < nch; k++) d.chunks[base + off + k] = ((int64_t)v << 32) | (uint32_t)k;
-}
-
-// Work items of a step: kChunk-slot pieces of the movers' slabs, appended
 // with one atomic per wavefront.  All lanes of the wave call it; lanes with
 // v < 0 add nothing.
 __device__ __forceinline__ void add_chunks_w(Dev &d, int32_t v) {
@@ -875,20 +912,31 @@ __device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nb
     }
     int32_t *mv = p ? d.mv1 : d.mv;
     int32_t *ncls = d.ctl->n_cls2[p];
+    int32_t *const ctr[5] = {&ncls[0], &ncls[1], &ncls[2], &ncls[3], &d.ctl->n_chunks2[p]};
     for (int i0 = bid * blockDim.x; i0 < nA + nB; i0 += stride) {
         int i = i0 + threadIdx.x;
-        int32_t v = -1, cl = -1;
+        int32_t v = -1, cl = -1, nch = 0;
         if (i < nA + nB) {
             v = i < nA ? d.sorted[a0 + i] : casc[i - nA];
             mv[i] = v;
             d.level[v] = phys | Mp;
             int32_t cap = d.cap[v];
             cl = cap <= 8 ? 0 : cap <= 16 ? 1 : cap <= 32 ? 2 : cap <= 64 ? 3 : 4;
-            if (cl == 4) d.sp[v] = (cap + kChunk - 1) / kChunk;
+            if (cl == 4) {
+                nch = (cap + kChunk - 1) / kChunk;
+                d.sp[v] = nch;
+            }
         }
+        const int32_t cnt[5] = {cl == 0, cl == 1, cl == 2, cl == 3, nch};
+        int32_t pos[5];
+        block_append(cnt, ctr, pos, sh);
 #pragma unroll
-        for (int k = 0; k < 4; k++) bpush(d.cls[k], &ncls[k], d.n, cl == k, v, d.ctl, sh);
-        add_chunks_b(d, cl == 4 ? v : -1, &d.ctl->n_chunks2[p], sh);
+        for (int k = 0; k < 4; k++) put(d.cls[k], pos[k], d.n, cl == k, v, d.ctl);
+        if (cl == 4) {
+            if (pos[4] + nch > d.chunk_cap) latch(d.ctl, kErrPool);
+            else
+                for (int32_t k = 0; k < nch; k++) d.chunks[pos[4] + k] = ((int64_t)v << 32) | (uint32_t)k;
+        }
     }
     if (bid == 0 && threadIdx.x == 0) d.ctl->nmvb[p] = d.ctl->nmove[p] = nA + nB;
     return true;
@@ -947,7 +995,9 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
         if (t >= total) cl = 0;
         int W = cl == 4 ? kWave : (8 << cl);
         int grp = lane / W, q = lane % W;
-        int32_t v = -1, lo = 0, hi = 0;
+        // up(v) is read with the slab's size: no other scan of the step
+        // touches a mover's counters (they see its flag)
+        int32_t v = -1, lo = 0, hi = 0, upv = 0;
         if (t >= total) {
             // no work item for this wavefront in the last round
         } else if (cl < 4) {
@@ -956,12 +1006,14 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
             if (j < ncl) {
                 v = d.cls[cl][j];
                 hi = d.cap[v];
+                if (q == 0) upv = d.up[v];
             }
         } else {
             int64_t desc = d.chunks[tl];
             v = (int32_t)(desc >> 32);
             lo = (int32_t)(desc & 0xffffffff) * kChunk;
             hi = min(lo + kChunk, d.cap[v]);
+            if (q == 0) upv = d.up[v];
         }
         const int32_t *s = v >= 0 ? d.pool + d.off[v] : d.pool;
         // the cap of level l+1 in v's graph (neighbours share v's graph)
@@ -1001,7 +1053,7 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
                 total_stay += (int32_t)(old >> 32);
             }
             if (last) {
-                int32_t u = d.up[v];
+                int32_t u = upv;
                 d.ups[v] = u;
                 u -= total_stay;
                 d.up[v] = u;
@@ -1015,8 +1067,8 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
         stage_flush(q_casc, room, casc, &d.ctl->casc_n[nxt], d.n, d.ctl);
         st_flush(q_stop, wpb * (kWave / 8), &d.ctl->n_sl[p], d.n, d.ctl, wr_stop);
     }
-    stage_flush(q_casc, kStage, casc, &d.ctl->casc_n[nxt], d.n, d.ctl);
-    st_flush(q_stop, 1024, &d.ctl->n_sl[p], d.n, d.ctl, wr_stop);
+    st_flush_both(q_casc, &d.ctl->casc_n[nxt], d.n, [=](int32_t k, int32_t x) { casc[k] = x; }, q_stop,
+                  &d.ctl->n_sl[p], d.n, wr_stop, d.ctl);
     __shared__ int32_t red[3][kBlock / kWave];
     nU = wave_sum(nU);
     n1 = wave_sum(n1);
@@ -1205,9 +1257,13 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
                 stopn = u;
             }
         }
-        bpush(d.cl, &c->n_cl, d.n, v >= 0, v, c, sh);
-        bpush(sln, &c->n_sl[p], d.n, stopn >= 0, stopn, c, sh);
-        bpush(d.rc, &c->n_rc, d.n, rcv >= 0, rcv, c, sh);
+        const int32_t cnt[3] = {v >= 0, stopn >= 0, rcv >= 0};
+        int32_t *const ctr[3] = {&c->n_cl, &c->n_sl[p], &c->n_rc};
+        int32_t pos[3];
+        block_append(cnt, ctr, pos, sh);
+        put(d.cl, pos[0], d.n, v >= 0, v, c);
+        put(sln, pos[1], d.n, stopn >= 0, stopn, c);
+        put(d.rc, pos[2], d.n, rcv >= 0, rcv, c);
     }
     dsum = block_sum64(dsum, red);
     if (threadIdx.x == 0 && dsum) atomicAdd((unsigned long long *)&c->sum_up, (unsigned long long)dsum);
@@ -1283,8 +1339,12 @@ __device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, i
                 w = u;
             }
         }
-        bpush(join, &c->n_exit, d.n - base, w >= 0, w, c, sh);
-        bpush(d.rc, &c->n_rc, d.n, v >= 0, v, c, sh);
+        const int32_t cnt[2] = {w >= 0, v >= 0};
+        int32_t *const ctr[2] = {&c->n_exit, &c->n_rc};
+        int32_t pos[2];
+        block_append(cnt, ctr, pos, sh);
+        put(join, pos[0], d.n - base, w >= 0, w, c);
+        put(d.rc, pos[1], d.n, v >= 0, v, c);
     }
     (void)prv;
 }
@@ -1350,8 +1410,8 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
         stage_flush(q_join, wpb, join, &c->casc_n[st.cur ^ 1], d.n, c);
         st_flush(q_stop, wpb * kWave, &c->n_sl[p], d.n, c, wr_stop);
     }
-    stage_flush(q_join, kStage, join, &c->casc_n[st.cur ^ 1], d.n, c);
-    st_flush(q_stop, 1024, &c->n_sl[p], d.n, c, wr_stop);
+    st_flush_both(q_join, &c->casc_n[st.cur ^ 1], d.n, [=](int32_t k, int32_t x) { join[k] = x; }, q_stop,
+                  &c->n_sl[p], d.n, wr_stop, c);
     // statistics: slots read, the group's up-neighbours (the U[v] reads of
     // its moves), neighbours of level l+1 gained; decrements of the group's up
     dec = block_sum64(dec, red);
@@ -1526,7 +1586,7 @@ __device__ __forceinline__ InsStep ins_load(const Ctl *c) {
 // occupancy change is applied by the next kernel (the scan), when no block
 // reads occ any more.
 __global__ void k_ins_prep(Dev d, int p) {
-    __shared__ int32_t sh[kBlock / kWave + 2];
+    __shared__ int32_t sh[5 * (kBlock / kWave + 2)];
     __shared__ int32_t sh1[2];
     Ctl *c = d.ctl;
     const bool b0 = blockIdx.x == 0, writer = b0 && threadIdx.x == 0;
@@ -1721,7 +1781,7 @@ __device__ bool grid_sync(Bar *b, unsigned nblk) {
 // bookkeeping, applies each step's occupancy change one phase later (when no
 // block reads occ) and resets the work-list counters of the other parity.
 __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
-    __shared__ int32_t sh[kBlock / kWave + 2];
+    __shared__ int32_t sh[5 * (kBlock / kWave + 2)];
     __shared__ int32_t sh1[2];
     const int bid = blockIdx.x, nblk = gridDim.x;
     const bool writer = bid == 0 && threadIdx.x == 0;
