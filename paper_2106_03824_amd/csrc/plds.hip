@@ -641,6 +641,9 @@ __global__ void k_grow_alloc(Dev d) {
 // Move the live entries of each regrown slab into its new slab.  A
 // wavefront takes 8 regrown slabs: a slab of at most 64 old slots is
 // served by a group of 8 lanes, larger ones by the whole wavefront in turn.
+// The new slab starts empty and only its mover writes it, so every entry
+// lands on an empty slot: its fill is the number of entries moved, stored
+// once (no per-entry counter atomics on one address).
 __global__ void k_grow_move(Dev d) {
     int32_t ng = d.ctl->n_grow;
     int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
@@ -651,13 +654,23 @@ __global__ void k_grow_move(Dev d) {
         bool has = g < ng && d.newcap[g] != 0;
         int32_t x = has ? d.grow[g] : -1, oc = has ? d.oldcap[g] : 0;
         bool small = has && oc <= 64;
+        int32_t moved = 0;
         if (small) {
             const int32_t *os = d.pool + d.oldoff[g];
+            int32_t *ns = d.pool + d.off[x];
+            const int32_t nc = d.cap[x];
             for (int32_t t = q; t < oc; t += 8) {
                 int32_t w = os[t];
-                if (w >= 0 && !slab_put(d.pool + d.off[x], d.cap[x], w, &d.fill[x])) latch(d.ctl, kErrFull);
+                if (w >= 0) {
+                    if (slab_put(ns, nc, w, nullptr)) moved++;
+                    else latch(d.ctl, kErrFull);
+                }
             }
         }
+        moved += __shfl_xor(moved, 1, kWave);
+        moved += __shfl_xor(moved, 2, kWave);
+        moved += __shfl_xor(moved, 4, kWave);
+        if (small && q == 0) d.fill[x] = moved;
         uint64_t big = __ballot(has && !small && q == 0);
         while (big) {
             int leader = __ffsll((unsigned long long)big) - 1;
@@ -665,10 +678,18 @@ __global__ void k_grow_move(Dev d) {
             int gb = base + leader / 8;
             int32_t xb = d.grow[gb], ob = d.oldcap[gb];
             const int32_t *os = d.pool + d.oldoff[gb];
+            int32_t *ns = d.pool + d.off[xb];
+            const int32_t nc = d.cap[xb];
+            int32_t mb = 0;
             for (int32_t t = lane; t < ob; t += kWave) {
                 int32_t w = os[t];
-                if (w >= 0 && !slab_put(d.pool + d.off[xb], d.cap[xb], w, &d.fill[xb])) latch(d.ctl, kErrFull);
+                if (w >= 0) {
+                    if (slab_put(ns, nc, w, nullptr)) mb++;
+                    else latch(d.ctl, kErrFull);
+                }
             }
+            mb = wave_sum(mb);
+            if (lane == 0) d.fill[xb] = mb;
         }
     }
 }
@@ -876,35 +897,63 @@ __device__ __forceinline__ void add_chunks_w(Dev &d, int32_t v) {
 // it, so the clearing and the flagging write the same value to it.  When
 // `st.done`, only clears.  Returns false (on every block alike) if the step
 // is out of range.
-__device__ void ins_clear_flags(Dev &d, int p, int bid, int nblk, int32_t F) {
+// The previous step's movers: the thread's first share, read before the
+// step is decided (the reads do not depend on the decision) so that they
+// overlap the decision's reads; written by ins_clear_flags.
+struct PrevFlags {
+    int32_t np, u, raw;
+};
+__device__ __forceinline__ PrevFlags prev_flags_load(const Dev &d, int p, int bid) {
+    PrevFlags f;
+    f.np = d.ctl->nmvb[p ^ 1];
+    const int32_t *prev = p ? d.mv : d.mv1;
+    const int i = bid * blockDim.x + threadIdx.x;
+    f.u = i < f.np ? prev[i] : -1;
+    f.raw = f.u >= 0 ? d.level[f.u] : 0;
+    return f;
+}
+
+__device__ void ins_clear_flags(Dev &d, int p, int bid, int nblk, int32_t F, const PrevFlags &f) {
     // the previous step's movers: a mover that still violates carries this
     // step's parity bit (it moves again), which becomes F, the flag this
     // step gives its movers.  The gathering of this kernel writes the same
     // value, before or after; a value it wrote first (with F) must come out
-    // unchanged, so F survives when it is kClimb.
+    // unchanged, so F survives when it is kClimb.  The value written depends
+    // only on what the previous scan left, so reading it early is the same.
     int32_t Mp = p ? kMover1 : kMover0;
+    if (f.u >= 0) d.level[f.u] = (f.raw & (kLevelMask | kClimb)) | ((f.raw & Mp) ? F : 0);
     int stride = nblk * blockDim.x;
     const int32_t *prev = p ? d.mv : d.mv1;
-    int32_t np = d.ctl->nmvb[p ^ 1];
-    for (int i = bid * blockDim.x + threadIdx.x; i < np; i += stride) {
+    for (int i = bid * blockDim.x + threadIdx.x + stride; i < f.np; i += stride) {
         int32_t u = prev[i];
         int32_t raw = d.level[u];
         d.level[u] = (raw & (kLevelMask | kClimb)) | ((raw & Mp) ? F : 0);
     }
 }
 
-__device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, int32_t *sh) {
+// mv: {first sorted position, sorted movers, cascaded movers} of the step
+// when the caller has them, else nullptr.
+__device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, int32_t *sh, const PrevFlags &pf,
+                               const int32_t *mvk) {
     int32_t Mp = p ? kMover1 : kMover0;
     int stride = nblk * blockDim.x;
-    ins_clear_flags(d, p, bid, nblk, Mp);
+    ins_clear_flags(d, p, bid, nblk, Mp, pf);
     if (st.done) return true;
     int32_t l = st.l, phys = st.phys, cur = st.cur;
     if (phys < 0 || phys > l || l + 1 >= d.K) {
         if (bid == 0 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
         return false;
     }
-    int32_t a0 = d.lvl_start[phys], a1 = d.lvl_start[phys + 1];
-    int32_t nA = a1 - a0, nB = d.ctl->casc_n[cur];
+    int32_t a0, nA, nB;
+    if (mvk) {
+        a0 = mvk[0];
+        nA = mvk[1];
+        nB = mvk[2];
+    } else {
+        a0 = d.lvl_start[phys];
+        nA = d.lvl_start[phys + 1] - a0;
+        nB = d.ctl->casc_n[cur];
+    }
     const int32_t *casc = cur ? d.casc1 : d.casc0;
     if (nA + nB > d.n) {
         if (bid == 0 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
@@ -1160,15 +1209,18 @@ __device__ InsStep climb_decide(Dev &d, const InsStep &prv, int p, int32_t *sh1,
     nx.fresh = 0;
     int32_t x1 = prv.l + 1;   // the group's level after the step
     int32_t ns = d.lvl_start[x1 + 1] - d.lvl_start[x1];
+    // occupancies are read with the counts (clamped indices; used only when
+    // the group can go on), so the reads overlap
+    const int32_t o0 = d.occ[min(x1, d.K)], o1 = d.occ[min(x1 + 1, d.K)], o2 = d.occ[min(x1 + 2, d.K)];
     int32_t nC = c->nmove[p ^ 1] - c->n_sl[p ^ 1] + c->casc_n[prv.cur ^ 1] + ns;
     bool top = x1 + 2 > d.K;
     bool go = nC > 0 && !top;
     int32_t stay = 0, r1 = 0, r2 = 0;
     if (go) {
         // occupancy after the step (its own move is applied one kernel later)
-        stay = d.occ[x1] + c->nmove[p ^ 1] - nC;
-        r1 = d.occ[x1 + 1];
-        r2 = d.occ[x1 + 2];
+        stay = o0 + c->nmove[p ^ 1] - nC;
+        r1 = o1;
+        r2 = o2;
         go = (int64_t)(stay + r1 + r2) * 2 <= nC;
     }
     __syncthreads();
@@ -1208,10 +1260,10 @@ __device__ InsStep climb_decide(Dev &d, const InsStep &prv, int p, int32_t *sh1,
 // stay at l (when the group moves from its own level), the residents of l+1
 // and l+2.
 __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, int p, int bid, int nblk,
-                                 int32_t *sh) {
+                                 int32_t *sh, const PrevFlags &pf) {
     __shared__ int64_t red[kBlock / kWave];
     Ctl *c = d.ctl;
-    ins_clear_flags(d, p, bid, nblk, kClimb);
+    ins_clear_flags(d, p, bid, nblk, kClimb, pf);
     const int stride = nblk * blockDim.x;
     const int32_t x = st.phys, l = st.l;
     const bool after_climb = prv.mode == kClimbStep;
@@ -1438,7 +1490,7 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
 // caller.  occ[] is read without this step's own update (applied later by
 // the caller): occ[z0] after the step is occ[z0] + (z0 == l+1 ? movers : 0).
 __device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn, int32_t *sh1,
-                              int32_t *movers_out, int32_t *occz_out) {
+                              int32_t *movers_out, int32_t *occz_out, int32_t *a0_out = nullptr) {
     InsStep nx;
     nx.cur = st.cur ^ 1;
     nx.jump = 0;
@@ -1447,18 +1499,25 @@ __device__ InsStep ins_decide(Dev &d, const InsStep &st, int32_t nmv, int32_t cn
     nx.mode = kPull;
     *movers_out = *occz_out = 0;
     int32_t l = st.l;
-    int32_t z0 = cn > 0 ? l + 1 : (l + 1 < d.K ? d.next_nz[l + 1] : d.K);
+    // level l+1's entries are read whatever z0 turns out to be (it usually
+    // is l+1), together with next_nz, so the reads overlap
+    const int32_t l1 = min(l + 1, d.K), l2 = min(l + 2, d.K);
+    const int32_t nz = d.next_nz[l1], s1 = d.lvl_start[l1], s2 = d.lvl_start[l2], o1 = d.occ[l1];
+    int32_t z0 = cn > 0 ? l + 1 : (l + 1 < d.K ? nz : d.K);
     if (z0 >= d.K - 1) {       // nothing left (no vertex of the top group can violate Invariant 1)
         if (z0 == d.K - 1 && threadIdx.x == 0) latch(d.ctl, kErrLevel);
         nx.done = 1;
         nx.l = nx.phys = d.K;
         return nx;
     }
-    int32_t ns = d.lvl_start[z0 + 1] - d.lvl_start[z0];
-    int32_t movers = (z0 == l + 1 ? cn : 0) + ns;
-    int32_t occz = d.occ[z0] + (z0 == l + 1 ? nmv : 0);
+    const bool near = z0 == l + 1;
+    const int32_t a0 = near ? s1 : d.lvl_start[z0];
+    int32_t ns = (near ? s2 : d.lvl_start[z0 + 1]) - a0;
+    int32_t movers = (near ? cn : 0) + ns;
+    int32_t occz = (near ? o1 : d.occ[z0]) + (near ? nmv : 0);
     *movers_out = movers;
     *occz_out = occz;
+    if (a0_out) *a0_out = a0;
     bool all = occz == movers;
     __syncthreads();
     if (threadIdx.x == 0) sh1[0] = INT32_MAX;
@@ -1580,16 +1639,20 @@ __device__ __forceinline__ InsStep ins_load(const Ctl *c) {
 // ---- one kernel per part.  A step of parity p is two kernels: decide+prep
 // and scan.  Kernels of parity p read the step state st[p]; decide+prep
 // computes it from st[p^1] (the previous step, or the seeding's first step)
-// in every block alike and block 0 stores it, so no block reads a slot that
-// is written during the same kernel.  Block 0 also does the previous step's
-// bookkeeping and resets the work-list counters of parity p^1; the step's
-// occupancy change is applied by the next kernel (the scan), when no block
-// reads occ any more.
+// in every block alike and block 1 stores it, so no block reads a slot
+// that is written during the same kernel.  That block also does the
+// previous step's bookkeeping and resets the work-list counters of parity
+// p^1; the step's occupancy change is applied by the next kernel (the
+// scan), when no block reads occ any more.
 __global__ void k_ins_prep(Dev d, int p) {
     __shared__ int32_t sh[5 * (kBlock / kWave + 2)];
     __shared__ int32_t sh1[2];
     Ctl *c = d.ctl;
-    const bool b0 = blockIdx.x == 0, writer = b0 && threadIdx.x == 0;
+    // the bookkeeping is done by block 1, which starts as early as block 0
+    // but has movers to gather only in large steps, so that its reads do not
+    // delay the gathering of small steps
+    const bool writer = blockIdx.x == min(1, (int)gridDim.x - 1) && threadIdx.x == 0;
+    const PrevFlags pf = prev_flags_load(d, p, blockIdx.x);
     InsStep prv = c->st[p ^ 1];
     if (prv.done) {
         if (writer) c->st[p] = prv;
@@ -1597,6 +1660,8 @@ __global__ void k_ins_prep(Dev d, int p) {
     }
     InsStep cur;
     int32_t nmove = 0, movers = 0, occz = 0;
+    int32_t mvk[3] = {0, 0, 0};   // the pull step's first sorted position, sorted and cascaded movers
+    bool have_mvk = false;
     if (prv.fresh) {
         cur = prv;
         cur.fresh = 0;
@@ -1607,7 +1672,11 @@ __global__ void k_ins_prep(Dev d, int p) {
     } else if (prv.mode == kClimbStep) {
         cur = climb_decide(d, prv, p, sh1, &nmove);
     } else {
-        cur = ins_decide(d, prv, c->nmove[p ^ 1], c->casc_n[prv.cur ^ 1], sh1, &movers, &occz);
+        const int32_t cn = c->casc_n[prv.cur ^ 1];
+        cur = ins_decide(d, prv, c->nmove[p ^ 1], cn, sh1, &movers, &occz, &mvk[0]);
+        mvk[1] = movers - cn;
+        mvk[2] = cn;
+        have_mvk = true;
     }
     // (not right after an exit step: the members that stopped in its last
     // climbing step are residents of its level that no list holds)
@@ -1642,26 +1711,32 @@ __global__ void k_ins_prep(Dev d, int p) {
             c->nmove[p] = nmove;
         }
     }
-    if (cur.mode == kClimbStep) climb_prep_phase(d, prv, cur, p, blockIdx.x, gridDim.x, sh);
+    if (cur.mode == kClimbStep) climb_prep_phase(d, prv, cur, p, blockIdx.x, gridDim.x, sh, pf);
     else if (cur.mode == kExit) exit_prep_phase(d, prv, cur, p, blockIdx.x, gridDim.x, sh);
-    else ins_prep_phase(d, cur, p, blockIdx.x, gridDim.x, sh);
+    else ins_prep_phase(d, cur, p, blockIdx.x, gridDim.x, sh, pf, have_mvk ? mvk : nullptr);
 }
 
 __global__ void k_ins_scan(Dev d, int p) {
     Ctl *c = d.ctl;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && c->pend_n) {
-        d.occ[c->pend_phys] -= c->pend_n;
-        d.occ[c->pend_l1] += c->pend_n;
-        c->pend_n = 0;
+    // bookkeeping: atomics whose result is not waited for, so block 0 goes
+    // on with its work items at once
+    const bool keeper = blockIdx.x == 0 && threadIdx.x == 0;
+    if (keeper) {
+        const int32_t pn = c->pend_n;
+        if (pn) {
+            atomicSub(&d.occ[c->pend_phys], pn);
+            atomicAdd(&d.occ[c->pend_l1], pn);
+            c->pend_n = 0;
+        }
     }
     InsStep st = c->st[p];
     if (st.done) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (keeper) {
         // the next step's stoppers list (the preparation of this step read
         // the previous one's); the climber list is not appended to here
         c->n_sl[p ^ 1] = 0;
         if (st.mode == kExit) {   // the group is gone; its members are joiners now
-            c->casc_n[st.cur ^ 1] += c->n_exit;
+            atomicAdd(&c->casc_n[st.cur ^ 1], c->n_exit);
             c->n_exit = 0;
             c->n_cl = 0;
             c->sum_up = 0;
@@ -1803,7 +1878,7 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
             }
             occ_pending = true;
         }
-        if (!ins_prep_phase(d, st, p, bid, nblk, sh)) {
+        if (!ins_prep_phase(d, st, p, bid, nblk, sh, prev_flags_load(d, p, bid), nullptr)) {
             if (writer) c->done = 1;
             break;
         }
