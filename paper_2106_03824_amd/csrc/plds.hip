@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -88,6 +89,7 @@ struct Ctl {
     int32_t n_cls2[2][4]; // insertion: movers per slab-size class, by step parity
     int32_t n_chunks2[2]; // insertion: large-slab work items, by step parity
     int32_t n_log;        // rows written to the step log in the current call
+    int32_t n_steps;      // insertion steps of the current sweep
     int32_t nmvb[2];      // flagged movers of the last insertion step of parity 0 / 1 (mover lists)
     int32_t nmove[2];     // vertices moved by the last step of parity 0 / 1 (climbers of a climbing step)
     int32_t n_cl;         // entries of the climber list
@@ -514,7 +516,9 @@ __global__ void k_dedupe(Dev d, const int32_t *e, int64_t cnt, int want_present)
             int32_t a = e[2 * i], b = e[2 * i + 1];
             u = min(a, b);
             v = max(a, b);
-            if (a != b) {
+            // ids out of range are left out (the call is then rejected
+            // before anything is applied)
+            if (a != b && u >= 0 && v < d.n) {
                 uint64_t key = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
                 uint64_t j = mix64(key) & d.hmask;
                 bool fresh = false;
@@ -824,6 +828,7 @@ __global__ void k_level_scan(Dev d) {
         d.ctl->step_dec[0] = d.ctl->step_dec[1] = 0;
         d.ctl->n_cl = 0;
         d.ctl->n_exit = 0;
+        d.ctl->n_steps = 0;
         d.ctl->sum_up = 0;
         for (int q = 0; q < 2; q++) {
             d.ctl->n_chunks2[q] = 0;
@@ -1573,6 +1578,7 @@ __device__ void sum_parts(Dev &d, int nparts, int64_t out[3]) {
 __device__ void ins_account(Dev &d, const InsStep &st, int32_t nmv, int64_t items) {
     Ctl *c = d.ctl;
     int64_t steps = st.l + 1 - st.phys;
+    c->n_steps++;
     c->sweeps += steps;
     c->moves += (int64_t)nmv * steps;
     c->top = max(c->top, (int64_t)(st.l + 1));
@@ -2373,6 +2379,12 @@ struct plds {
     plds_stats_t stats{};
     int32_t latched = 0;
     bool broken = false;
+    // the call's range checks were launched but not yet read back (the first
+    // batch application's sync reads them, before the state changes)
+    bool range_pending = false;
+    // steps of the last insertion sweep: that many are issued before the
+    // first wait for the sweep's end
+    int64_t ins_steps_hint = 0;
     // insertion sweep as one cooperative launch (0 blocks = not available)
     int sweep_mode = 1;          // 0: cooperative when possible, 1: one kernel per part
     int coop_blocks = -1;        // -1 = not yet determined
@@ -2629,7 +2641,10 @@ int ctl_reset_batch(plds *h, hipStream_t s) {
     c->top = 0;
     c->m_out = 0;
     c->pool_top = h->pool_top;
-    HIPCHK(hipMemcpyAsync(h->d.ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    // everything but err, which may hold the call's range-check result
+    const size_t e0 = offsetof(Ctl, err), e1 = e0 + sizeof(c->err);
+    HIPCHK(hipMemcpyAsync(h->d.ctl, c, e0, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((char *)h->d.ctl + e1, (const char *)c + e1, sizeof(Ctl) - e1, hipMemcpyHostToDevice, s));
     return PLDS_OK;
 }
 
@@ -2665,6 +2680,17 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
     HIPCHK(hipGetLastError());
     rc = sync_ctl(h, s);
     if (rc) return rc;
+    if (h->range_pending) {
+        h->range_pending = false;
+        if (h->h_ctl->err & kErrRange) {
+            // nothing is applied yet: only the endpoint counts of this list are undone
+            h->h_ctl->err = 0;
+            HIPCHK(hipMemsetAsync(d.addc, 0, (size_t)h->n * sizeof(int32_t), s));
+            HIPCHK(hipMemcpyAsync(&d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            return PLDS_ERANGE;
+        }
+    }
     *applied = h->h_ctl->n_valid;
     if (insert) {
         if (h->h_ctl->n_grow > 0) {
@@ -2791,6 +2817,10 @@ int insertion_sweep(plds *h, hipStream_t s) {
     // a timed step kernel is launched directly, so that its events bracket the dispatch alone
     bool use_graph = h->timed_kind != 1 && h->timed_kind != 4;
     int run = use_graph ? kGraphSteps : 8;
+    // before the first wait, issue about as many steps as the last sweep
+    // took (rounded down to whole step graphs); steps issued after the
+    // sweep's end return at once
+    int64_t first = std::min<int64_t>(std::max<int64_t>(h->ins_steps_hint / kGraphSteps, 1), 8);
     while (!h->h_ctl->done && !h->h_ctl->err) {
         if (steps > 2 * (int64_t)h->K + 2) {   // a level gets at most an exit step and a moving step
             h->broken = true;
@@ -2799,8 +2829,9 @@ int insertion_sweep(plds *h, hipStream_t s) {
         if (use_graph) {
             rc = ins_graph(h);
             if (rc) return rc;
-            HIPCHK(hipGraphLaunch(h->ins_exec, s));
-            steps += kGraphSteps;
+            for (int64_t i = 0; i < first; i++) HIPCHK(hipGraphLaunch(h->ins_exec, s));
+            steps += first * kGraphSteps;
+            first = 1;
         } else {
             steps += run;
             for (int i = 0; i < run; i++) {      // run is even: every run starts at parity 0
@@ -2823,6 +2854,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
     rc = sync_ctl(h, s);
     if (rc) return rc;
     Ctl *c = h->h_ctl;
+    h->ins_steps_hint = c->n_steps + 1;   // the steps and the one that found the sweep done
     h->stats.sweeps_ins += c->sweeps;
     h->stats.moves_up += c->moves;
     h->stats.alg_bytes_up += 8 * (c->alg_U + c->alg_up1) + 4 * c->moves;
@@ -3044,6 +3076,7 @@ namespace {
 // bits (host mirror and device).
 int begin_call(plds *h, hipStream_t s) {
     memset(&h->stats, 0, sizeof(h->stats));
+    h->range_pending = false;
     h->h_ctl->err = 0;
     h->h_ctl->n_log = 0;
     HIPCHK(hipMemcpyAsync(&h->d.ctl->n_log, &h->h_ctl->n_log, sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -3053,30 +3086,22 @@ int begin_call(plds *h, hipStream_t s) {
 
 // After the range checks of a call: PLDS_ERANGE (nothing applied) if any id
 // was out of range.
-int end_range_check(plds *h, hipStream_t s) {
-    int rc = sync_ctl(h, s);
-    if (rc) return rc;
-    if (h->h_ctl->err & kErrRange) {
-        h->h_ctl->err = 0;
-        HIPCHK(hipMemcpyAsync(&h->d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return PLDS_ERANGE;
-    }
-    return PLDS_OK;
-}
 
 // Algorithm 1 on range-checked lists of global ids: insertions and their
 // sweep, then deletions and theirs.
 int run_update(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, hipStream_t s) {
     int rc;
+    bool synced = false;   // the last step ended with a wait, nothing launched since
     if (n_ins) {
         int64_t applied = 0;
         rc = apply_list(h, ins, n_ins, 1, s, &applied);
         if (rc) return rc;
         h->stats.applied_ins = applied;
+        synced = false;
         if (applied) {
             rc = insertion_sweep(h, s);
             if (rc) return rc;
+            synced = true;
         }
     }
     if (n_del) {
@@ -3084,13 +3109,17 @@ int run_update(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *del, i
         rc = apply_list(h, del, n_del, 0, s, &applied);
         if (rc) return rc;
         h->stats.applied_del = applied;
+        synced = false;
         if (applied) {
             rc = deletion_sweep(h, s);
             if (rc) return rc;
+            synced = true;
         }
     }
-    rc = sync_ctl(h, s);
-    if (rc) return rc;
+    if (!synced) {
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+    }
     return check_err(h);
 }
 
@@ -3112,8 +3141,7 @@ int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del
     if (n_ins) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_ins)), dim3(kBlock), 0, s, ins, n_ins, h->d.n, h->d.ctl);
     if (n_del) hipLaunchKernelGGL(k_range_check, dim3(grid_for(2 * n_del)), dim3(kBlock), 0, s, del, n_del, h->d.n, h->d.ctl);
     HIPCHK(hipGetLastError());
-    rc = end_range_check(h, s);
-    if (rc) return rc;
+    h->range_pending = true;   // read back by the first batch application
     return run_update(h, ins, n_ins, del, n_del, s);
 }
 
@@ -3162,8 +3190,7 @@ int plds_update_multi(plds_t *h, const int32_t *const *ins, const int64_t *n_ins
     hipLaunchKernelGGL(k_stage, dim3(grid_for(ti + td)), dim3(kBlock), 0, s, h->d_segs, nseg, ti + td, h->stage,
                        h->d.ctl);
     HIPCHK(hipGetLastError());
-    rc = end_range_check(h, s);
-    if (rc) return rc;
+    h->range_pending = true;   // read back by the first batch application
     return run_update(h, h->stage, ti, h->stage + 2 * ti, td, s);
 }
 
