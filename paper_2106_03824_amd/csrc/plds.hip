@@ -108,6 +108,7 @@ struct Ctl {
     int32_t n_valid;      // valid unique edges of the batch being applied
     int32_t n_touch;      // distinct endpoints of those edges
     int32_t n_grow;       // slabs to regrow
+    int32_t n_pieces;     // work items of the large regrown slabs
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
     int32_t phys;         // level the movers of the current insertion step sit at
@@ -615,86 +616,124 @@ __global__ void k_plan_growth(Dev d) {
 // Allocate the new slabs from the pool, one atomic per wavefront.  All slabs
 // of one batch are carved from one contiguous region that the host has
 // already filled with empty slots.
+constexpr int kGrowLds = 2048;     // slots of a new slab built in LDS (per wavefront)
+constexpr int kGrowPiece = 1024;   // old slots per work item of a larger regrown slab
+
 __global__ void k_grow_alloc(Dev d) {
     int32_t ng = d.ctl->n_grow;
     int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
     int stride = gridDim.x * blockDim.x;
-    for (int g0 = gid - lane; g0 < ng; g0 += stride) {
+    for (int g0 = gid - lane; g0 < ng; g0 += stride) {   // wave-uniform
         int g = g0 + lane;
-        int32_t nc = g < ng ? d.newcap[g] : 0;
+        const bool in = g < ng;
+        int32_t nc = in ? d.newcap[g] : 0;
         int32_t total = 0;
         int32_t off = wave_excl(nc, &total);
         int64_t base = 0;
         if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)&d.ctl->pool_top, (unsigned long long)total);
         base = __shfl(base, 0, kWave);
-        if (g >= ng) continue;
-        int32_t x = d.grow[g];
-        d.oldoff[g] = d.off[x];
-        d.oldcap[g] = d.cap[x];
-        if (base + off + nc > d.pool_cap) {
-            latch(d.ctl, kErrPool);
-            d.newcap[g] = 0;
-            continue;
+        int32_t npc = 0;   // work items of a new slab too large for LDS: pieces of its old slab
+        if (in) {
+            int32_t x = d.grow[g];
+            int32_t oc = d.cap[x];
+            d.oldoff[g] = d.off[x];
+            d.oldcap[g] = oc;
+            if (base + off + nc > d.pool_cap) {
+                latch(d.ctl, kErrPool);
+                d.newcap[g] = 0;
+            } else {
+                d.off[x] = base + off;
+                d.cap[x] = nc;
+                d.fill[x] = 0;
+                if (nc > kGrowLds) npc = (oc + kGrowPiece - 1) / kGrowPiece;
+            }
         }
-        d.off[x] = base + off;
-        d.cap[x] = nc;
-        d.fill[x] = 0;
+        int32_t ptot = 0;
+        int32_t poff = wave_excl(npc, &ptot);
+        int32_t pbase = 0;
+        if (lane == 0 && ptot) pbase = atomicAdd(&d.ctl->n_pieces, ptot);
+        pbase = __shfl(pbase, 0, kWave);
+        if ((int64_t)pbase + ptot > d.chunk_cap) {
+            if (lane == 0 && ptot) latch(d.ctl, kErrPool);
+        } else {
+            for (int32_t k = 0; k < npc; k++) d.chunks[pbase + poff + k] = ((int64_t)g << 32) | (uint32_t)k;
+        }
     }
 }
 
-// Move the live entries of each regrown slab into its new slab.  A
-// wavefront takes 8 regrown slabs: a slab of at most 64 old slots is
-// served by a group of 8 lanes, larger ones by the whole wavefront in turn.
-// The new slab starts empty and only its mover writes it, so every entry
-// lands on an empty slot: its fill is the number of entries moved, stored
-// once (no per-entry counter atomics on one address).
-__global__ void k_grow_move(Dev d) {
-    int32_t ng = d.ctl->n_grow;
-    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
-    int nw = gridDim.x * blockDim.x / kWave;
-    int grp = lane / 8, q = lane % 8;
-    for (int base = wid * 8; base < ng; base += nw * 8) {
-        int g = base + grp;
-        bool has = g < ng && d.newcap[g] != 0;
-        int32_t x = has ? d.grow[g] : -1, oc = has ? d.oldcap[g] : 0;
-        bool small = has && oc <= 64;
+// Move the live entries of each regrown slab into its new slab.  The new
+// slab starts empty and only its movers write it, so every entry lands on an
+// empty slot and its fill is the number of entries moved.  A new slab of at
+// most kGrowLds slots is built by one wavefront in LDS (CAS on LDS, then one
+// coalesced write of the whole slab; fill stored once); any linear-probing
+// placement is a valid slab, since the new slab has no tombstones.  Larger
+// ones are filled in place, kGrowPiece old slots per wavefront (fill added
+// once per piece), so that a hub's slab is spread over many wavefronts.
+
+__device__ __forceinline__ bool lds_put(int32_t *t, int32_t cap, int32_t key) {
+    uint32_t i = home(key, cap);
+    for (int32_t p = 0; p < cap; p++) {
+        if (atomicCAS(&t[i], kEmpty, key) == kEmpty) return true;
+        if (++i == (uint32_t)cap) i = 0;
+    }
+    return false;
+}
+
+__global__ void __launch_bounds__(kBlock) k_grow_move(Dev d) {
+    __shared__ int32_t tab[kBlock / kWave][kGrowLds];
+    const int32_t ng = d.ctl->n_grow;
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
+    int32_t *t = tab[wv];
+    // the slabs up to kGrowLds slots (larger ones are done in pieces below)
+    // rounds are block-uniform: each wavefront takes one slab per round
+    for (int base = blockIdx.x * wpb; base < ng; base += gridDim.x * wpb) {
+        const int g = base + wv;
+        const bool has = g < ng && d.newcap[g] != 0;
+        const int32_t x = has ? d.grow[g] : -1;
+        const int32_t nc = has ? d.cap[x] : 0, oc = has ? d.oldcap[g] : 0;
+        const bool in_lds = has && nc <= kGrowLds;
+        if (in_lds)
+            for (int i = lane; i < nc; i += kWave) t[i] = kEmpty;
+        __syncthreads();
         int32_t moved = 0;
-        if (small) {
+        if (in_lds) {
             const int32_t *os = d.pool + d.oldoff[g];
+            for (int i = lane; i < oc; i += kWave) {
+                const int32_t w = os[i];
+                if (w >= 0) {
+                    if (lds_put(t, nc, w)) moved++;
+                    else latch(d.ctl, kErrFull);
+                }
+            }
+        }
+        __syncthreads();
+        if (in_lds) {
             int32_t *ns = d.pool + d.off[x];
-            const int32_t nc = d.cap[x];
-            for (int32_t t = q; t < oc; t += 8) {
-                int32_t w = os[t];
-                if (w >= 0) {
-                    if (slab_put(ns, nc, w, nullptr)) moved++;
-                    else latch(d.ctl, kErrFull);
-                }
+            for (int i = lane; i < nc; i += kWave) ns[i] = t[i];
+            moved = wave_sum(moved);
+            if (lane == 0) d.fill[x] = moved;
+        }
+        __syncthreads();   // the next round reuses the tables
+    }
+    // the larger slabs, a piece per wavefront
+    const int32_t np = (int32_t)min((int64_t)d.ctl->n_pieces, d.chunk_cap);
+    for (int i = blockIdx.x * wpb + wv; i < np; i += gridDim.x * wpb) {
+        const int64_t desc = d.chunks[i];
+        const int32_t g = (int32_t)(desc >> 32), k = (int32_t)(desc & 0xffffffff);
+        const int32_t x = d.grow[g], oc = d.oldcap[g], nc = d.cap[x];
+        const int32_t *os = d.pool + d.oldoff[g];
+        int32_t *ns = d.pool + d.off[x];
+        const int32_t lo = k * kGrowPiece, hi = min(lo + kGrowPiece, oc);
+        int32_t moved = 0;
+        for (int32_t e = lo + lane; e < hi; e += kWave) {
+            const int32_t w = os[e];
+            if (w >= 0) {
+                if (slab_put(ns, nc, w, nullptr)) moved++;
+                else latch(d.ctl, kErrFull);
             }
         }
-        moved += __shfl_xor(moved, 1, kWave);
-        moved += __shfl_xor(moved, 2, kWave);
-        moved += __shfl_xor(moved, 4, kWave);
-        if (small && q == 0) d.fill[x] = moved;
-        uint64_t big = __ballot(has && !small && q == 0);
-        while (big) {
-            int leader = __ffsll((unsigned long long)big) - 1;
-            big &= big - 1;
-            int gb = base + leader / 8;
-            int32_t xb = d.grow[gb], ob = d.oldcap[gb];
-            const int32_t *os = d.pool + d.oldoff[gb];
-            int32_t *ns = d.pool + d.off[xb];
-            const int32_t nc = d.cap[xb];
-            int32_t mb = 0;
-            for (int32_t t = lane; t < ob; t += kWave) {
-                int32_t w = os[t];
-                if (w >= 0) {
-                    if (slab_put(ns, nc, w, nullptr)) mb++;
-                    else latch(d.ctl, kErrFull);
-                }
-            }
-            mb = wave_sum(mb);
-            if (lane == 0) d.fill[xb] = mb;
-        }
+        moved = wave_sum(moved);
+        if (lane == 0 && moved) atomicAdd(&d.fill[x], moved);
     }
 }
 
@@ -2614,7 +2653,7 @@ int ensure_pool(plds *h, hipStream_t s, int64_t extra) {
 // reset the per-call fields of the control block (host mirror -> device)
 int ctl_reset_batch(plds *h, hipStream_t s) {
     Ctl *c = h->h_ctl;
-    c->n_valid = c->n_touch = c->n_grow = c->n_cand = 0;
+    c->n_valid = c->n_touch = c->n_grow = c->n_cand = c->n_pieces = 0;
     c->grow_req = 0;
     c->l = 0;
     c->done = 0;
@@ -2699,8 +2738,9 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
             if (rc) return rc;
             HIPCHK(hipMemsetAsync(d.pool + h->pool_top, 0xff, (size_t)req * sizeof(int32_t), s));
             hipLaunchKernelGGL(k_grow_alloc, dim3(grid_for(h->h_ctl->n_grow)), dim3(kBlock), 0, s, d);
-            hipLaunchKernelGGL(k_grow_move, dim3(grid_for((int64_t)h->h_ctl->n_grow * 8)), dim3(kBlock), 0, s,
-                               d);
+            // a wavefront per slab (at least 256 blocks, for the pieces of large slabs)
+            int gm = std::max(grid_for((int64_t)h->h_ctl->n_grow * kWave, kBlock, 2048), 256);
+            hipLaunchKernelGGL(k_grow_move, dim3(gm), dim3(kBlock), 0, s, d);
             h->pool_top += req;
         }
         hipLaunchKernelGGL(k_apply_ins, dim3(grid_for(*applied)), dim3(kBlock), 0, s, d);
