@@ -2432,6 +2432,11 @@ struct plds {
     hipGraph_t ins_graph = nullptr;
     hipGraphExec_t ins_exec = nullptr;
     Dev ins_graph_dev{};
+    // the deletion step sequence as a prebuilt graph of kDelGraphSteps steps
+    hipGraph_t del_graph = nullptr;
+    hipGraphExec_t del_exec = nullptr;
+    Dev del_graph_dev{};
+    int64_t del_steps_hint = 0;   // steps of the last deletion sweep
     int par[2] = {0, 1};
     // optional event timing of one sweep kernel
     int32_t timed_kind = 0;
@@ -2514,6 +2519,10 @@ void free_all(plds *h) {
     if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
     h->ins_exec = nullptr;
     h->ins_graph = nullptr;
+    if (h->del_exec) (void)hipGraphExecDestroy(h->del_exec);
+    if (h->del_graph) (void)hipGraphDestroy(h->del_graph);
+    h->del_exec = nullptr;
+    h->del_graph = nullptr;
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     h->ev.clear();
@@ -2791,6 +2800,52 @@ int ins_graph(plds *h) {
     return 0;
 }
 
+constexpr int kDelGraphSteps = 4;
+
+// The deletion step sequence (select, scan, fin, desire-levels, next) x
+// kDelGraphSteps as one graph of kernel nodes, rebuilt when the device
+// buffers move.
+int del_graph(plds *h, size_t lds) {
+    if (h->del_exec && !memcmp(&h->del_graph_dev, &h->d, sizeof(Dev))) return 0;
+    if (h->del_exec) (void)hipGraphExecDestroy(h->del_exec);
+    if (h->del_graph) (void)hipGraphDestroy(h->del_graph);
+    h->del_exec = nullptr;
+    h->del_graph = nullptr;
+    h->del_graph_dev = h->d;
+    if (hipGraphCreate(&h->del_graph, 0) != hipSuccess) return PLDS_EHIP;
+    Dev *dv = &h->del_graph_dev;
+    void *a0[] = {(void *)dv};
+    void *a1[] = {(void *)dv, (void *)&h->par[1]};   // mode 1
+    struct K {
+        const void *f;
+        int grid;
+        size_t lds;
+        void **args;
+    } ks[5] = {{(const void *)k_del_select, kSweepGrid / 4, 0, a0},
+               {(const void *)k_del_scan, kSweepGrid, 0, a0},
+               {(const void *)k_del_fin, kSweepGrid / 4, 0, a0},
+               {(const void *)k_dl, kDlGrid, lds, a1},
+               {(const void *)k_del_next, 1, 0, a1}};
+    hipGraphNode_t prev = nullptr;
+    for (int i = 0; i < kDelGraphSteps; i++) {
+        for (int k = 0; k < 5; k++) {
+            hipGraphNode_t node;
+            hipKernelNodeParams p{};
+            p.func = const_cast<void *>(ks[k].f);
+            p.gridDim = dim3(ks[k].grid);
+            p.blockDim = dim3(k == 4 ? 1 : kBlock);
+            p.sharedMemBytes = (unsigned)ks[k].lds;
+            p.kernelParams = ks[k].args;
+            p.extra = nullptr;
+            if (hipGraphAddKernelNode(&node, h->del_graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+                return PLDS_EHIP;
+            prev = node;
+        }
+    }
+    if (hipGraphInstantiate(&h->del_exec, h->del_graph, nullptr, nullptr, 0) != hipSuccess) return PLDS_EHIP;
+    return 0;
+}
+
 // Blocks of the cooperative sweep: up to 4 resident blocks per compute unit
 // (fewer if the occupancy calculator says so), at most kSweepGrid.
 int coop_blocks(plds *h) {
@@ -2916,20 +2971,33 @@ int deletion_sweep(plds *h, hipStream_t s) {
     if (rc) return rc;
     take_timing(h, h->ev_used);
     h->stats.viol_del0 = h->h_ctl->p_n[0];
+    // timed step kernels are launched one by one, in runs of 4, 8, ...; else
+    // the step graph, before the first wait as many times as the last sweep
+    // took steps (rounded down to whole graphs)
+    const bool use_graph = h->timed_kind != 2 && h->timed_kind != 3;
     int run = 4;
+    int64_t first = std::min<int64_t>(std::max<int64_t>(h->del_steps_hint / kDelGraphSteps, 1), 8);
     int64_t steps = 0;
     while (!h->h_ctl->done && !h->h_ctl->err) {
         if (steps > (int64_t)h->K + 1) {
             h->broken = true;
             return PLDS_ESTATE;
         }
-        steps += run;
-        for (int i = 0; i < run; i++) {
-            hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-            tlaunch(h, 2, k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
-            hipLaunchKernelGGL(k_del_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-            tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 1);
-            hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 1);
+        if (use_graph) {
+            rc = del_graph(h, lds);
+            if (rc) return rc;
+            for (int64_t i = 0; i < first; i++) HIPCHK(hipGraphLaunch(h->del_exec, s));
+            steps += first * kDelGraphSteps;
+            first = 1;
+        } else {
+            steps += run;
+            for (int i = 0; i < run; i++) {
+                hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+                tlaunch(h, 2, k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
+                hipLaunchKernelGGL(k_del_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+                tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 1);
+                hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 1);
+            }
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
@@ -2938,6 +3006,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
         run = std::min(run * 2, 128);
     }
     Ctl *c = h->h_ctl;
+    h->del_steps_hint = c->sweeps;
     h->stats.sweeps_del += c->sweeps;
     h->stats.moves_down += c->moves;
     h->stats.slots_scanned += c->scanned;

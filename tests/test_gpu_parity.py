@@ -44,14 +44,16 @@ class Pair:
 
     def __init__(self, n, delta=0.4, lam=3.0, L=0, sweep_mode=1, direct=False):
         """sweep_mode 0: one cooperative launch; 1: step kernels (prebuilt
-        graph) with climbing steps for large groups; 2: without climbing
+        graphs) with climbing steps for large groups; 2: without climbing
         steps; 3: climbing steps for groups of any size.  direct: step
-        kernels launched one by one (what kernel timing of the preparation
-        kernel selects)."""
+        kernels launched one by one instead of from the step graphs (what
+        kernel timing selects): True or "ins" for the insertion steps (the
+        preparation kernel timed), "del" for the deletion steps (the
+        deletion scan timed)."""
         self.g = lib().PLDS(n, delta, lam, L)
         lib().plds_set_sweep_mode(self.g.h, sweep_mode)
         if direct:
-            lib().plds_set_timing(self.g.h, "ins_prep")
+            lib().plds_set_timing(self.g.h, "del_scan" if direct == "del" else "ins_prep")
         self.o = O.Oracle(n, delta, lam, L)
         self.n = n
 
@@ -159,7 +161,7 @@ def test_random_small(seed):
     L = rng.choice([0, 0, 2, 3])
     delta, lam = rng.choice([(0.4, 3.0), (1.0, 3.0), (0.2, 6.0)])
     say("random small", seed, n, L, delta, lam)
-    p = Pair(n, delta, lam, L, sweep_mode=seed % 4, direct=seed % 5 == 1)
+    p = Pair(n, delta, lam, L, sweep_mode=seed % 4, direct={1: "ins", 3: "del"}.get(seed % 5, False))
     for it in range(6):
         ins = [(rng.randrange(n), rng.randrange(n)) for _ in range(rng.randrange(0, 4 * n))]
         cur = p.o.edges().tolist()
@@ -187,7 +189,8 @@ def test_rmat_tiny_config():
     p.step(ins=W.new_pairs(n, cur, 5000, 1003), dele=W.sample_edges(cur, 5000, 1004))
 
 
-@pytest.mark.parametrize("mode,direct", [(0, False), (1, False), (1, True), (2, False), (3, False), (3, True)])
+@pytest.mark.parametrize("mode,direct", [(0, False), (1, False), (1, True), (1, "del"), (2, False), (3, False),
+                                         (3, True)])
 def test_rmat_multi_batch(mode, direct):
     """RMAT scale 14, edge factor 16, built in 4 insertion batches, then mixed
     and deletion batches, each compared with the oracle; every way of running
