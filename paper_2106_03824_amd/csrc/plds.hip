@@ -764,8 +764,7 @@ __global__ void k_apply_del(Dev d) {
         if (!slab_del(d.pool + d.off[a], d.cap[a], b)) latch(d.ctl, kErrFull);
         if (!slab_del(d.pool + d.off[b], d.cap[b], a)) latch(d.ctl, kErrFull);
         int32_t la = d.level[a], lb = d.level[b];
-        atomicSub(&d.deg[a], 1);
-        atomicSub(&d.deg[b], 1);
+        // deg drops by the endpoint counts in k_del_cand (a hub would serialise here)
         if (lb >= la) atomicSub(&d.up[a], 1);
         if (lb >= la - 1) atomicSub(&d.ups[a], 1);
         if (la >= lb) atomicSub(&d.up[b], 1);
@@ -2006,20 +2005,50 @@ __device__ int32_t block_dl(Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_
 // mode 0: seed from the endpoints of deleted edges (list = touch, pending
 // list = cur).  mode 1: recompute for the vertices listed in rc during a
 // step (pending list = next); the last block then closes the step.
+// The batch's touched endpoints that violate Invariant 2 (Algorithm 3's
+// first candidates), a thread each, into the recompute list; on the way each
+// endpoint's degree drops by its count of deleted edges, and the count is
+// cleared.  Usually a handful of the
+// touched endpoints violate, so the desire-level kernel (a block per vertex)
+// only sees those.
+__global__ void k_del_cand(Dev d) {
+    __shared__ Stage q;
+    stage_init(q);
+    const int32_t nt = d.ctl->n_touch;
+    const int stride = gridDim.x * blockDim.x;
+    for (int ib = blockIdx.x * blockDim.x; ib < nt; ib += stride) {
+        const int i = ib + threadIdx.x;
+        bool viol = false;
+        int32_t w = -1;
+        if (i < nt) {
+            w = d.touch[i];
+            d.deg[w] -= d.addc[w];   // the endpoint's deleted edges (counted by k_touch)
+            d.addc[w] = 0;
+            const int32_t lw = d.level[w];
+            viol = lw > 0 && d.ups[w] < dn_floor(d, gp(d, w), lw);
+        }
+        stage_push(q, viol, w);
+        stage_flush(q, blockDim.x, d.rc, &d.ctl->n_rc, d.n, d.ctl);
+    }
+    stage_flush(q, kStage, d.rc, &d.ctl->n_rc, d.n, d.ctl);
+}
+
+// Desire-levels of the vertices of the recompute list that violate
+// Invariant 2, a block each (mode 0: the batch's candidates listed by
+// k_del_cand; mode 1: the neighbours a step's moves left violating).
 __global__ void k_dl(Dev d, int mode) {
     extern __shared__ int32_t lds[];
     int32_t *seg = lds, *red = lds + kBlock, *hist = lds + kBlock + 16;
     Ctl *c = d.ctl;
     int32_t cur = c->cur, tgt = mode == 0 ? cur : (cur ^ 1);
     int32_t *plist = tgt ? d.p1 : d.p0;
-    int32_t cnt = mode == 0 ? c->n_touch : c->n_rc;
-    const int32_t *list = mode == 0 ? d.touch : d.rc;
+    int32_t cnt = c->n_rc;
+    const int32_t *list = d.rc;
     int32_t l = mode == 0 ? -1 : c->l;
     bool skip = mode == 1 && c->done;
     int32_t ncalc = 0;
     for (int i = blockIdx.x; !skip && i < cnt; i += gridDim.x) {
         int32_t w = list[i];
-        if (mode == 0 && threadIdx.x == 0) d.addc[w] = 0;
         int32_t lw = d.level[w];
         bool viol = lw > 0 && d.ups[w] < dn_floor(d, gp(d, w), lw);
         if (!viol) continue;                  // block-uniform
@@ -2058,6 +2087,7 @@ __global__ void k_del_next(Dev d, int mode) {
         c->n_rc = 0;
         c->step_id += 1;
     }
+    if (mode == 0) c->n_rc = 0;   // the candidates' list has been read
     int32_t nm = c->nm;
     c->nm = kInf;
     if (nm == kInf) c->done = 1;
@@ -2964,6 +2994,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void *)k_dl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return PLDS_EINVAL;
+    hipLaunchKernelGGL(k_del_cand, dim3(grid_for(h->h_ctl->n_touch, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
     tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 0);
     hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 0);
     HIPCHK(hipGetLastError());
