@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--batched", action="store_true", help="the batched form: 256 graphs in one handle")
     ap.add_argument("--graphs", type=int, default=256)
     ap.add_argument("--serve", action="store_true", help="the serving form: resident graphs behind a request loop")
+    ap.add_argument("--orient", action="store_true",
+                    help="the RMAT-20 stream with the orientation outputs (flips F, oriented updates J) per batch")
     ap.add_argument("--serve-graphs", type=int, default=64)
     ap.add_argument("--serve-scales", type=int, nargs=2, default=[16, 22])
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -186,6 +188,8 @@ def main():
         return run_batched(args, P, W, torch, np)
     if args.serve:
         return run_serve(args, P, W, torch, np)
+    if args.orient:
+        return run_orient(args, P, W, torch, np)
     if args.scale != 20:
         return run_stream(args, P, W, torch, np)
     scale, B = args.scale, args.batch
@@ -461,6 +465,102 @@ def run_batched(args, P, W, torch, np):
         "per_graph_loop": {"value": u_loop / t_loop, "ms": t_loop * 1e3},
         "speedup_vs_loop": t_loop / t_fused,
         "identical_levels": same, "updates": u_fused, "sweeps": s["sweeps_ins"] + s["sweeps_del"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_orient(args, P, W, torch, np):
+    """The RMAT-20 stream of the default run with orientation tracking on:
+    every 1e6 batch (insertions, deletions, mixed) is followed by its flips F
+    and oriented updates J (Algorithm 5).  Each batch is timed from before the
+    update to after both outputs are in HBM; `value` counts the batch's
+    applied updates over those times.  The roofline is the flip scan's: per
+    searched edge 4 bytes of neighbour id and 8 of its two levels, per moved
+    vertex 8 bytes of its own levels, per flip 8 bytes out."""
+    scale, B = 20, args.batch
+    m0 = 16 * 2 ** scale
+    dev = torch.device("cuda", 0)
+    st = W.RmatStream(scale, m0, seed=1, build_batches=16, cfg=2)
+    n = st.n
+    g = P.PLDS(n, 0.4, 3.0, 0, 2 * m0)
+    for b in st.build:
+        P.plds_batch_insert(g.h, torch.from_numpy(np.ascontiguousarray(b)).to(dev))
+    P.plds_track_orientation(g.h, True)
+    rounds = args.warmup + args.steps
+    batches = []
+    for r in range(rounds):
+        ins = st.insert_batch(B)
+        dele = st.delete_batch(B)
+        mi, md = st.mixed_batch(B)
+        batches += [("ins", torch.from_numpy(ins).to(dev), None), ("del", None, torch.from_numpy(dele).to(dev)),
+                    ("mix", torch.from_numpy(mi).to(dev), torch.from_numpy(md).to(dev))]
+    fcap = 16 * B
+    fout = torch.empty((fcap, 2), dtype=torch.int32, device=dev)
+    ji = torch.empty((B, 2), dtype=torch.int32, device=dev)
+    jd = torch.empty((B, 2), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    log("orient: built, batches ready")
+    tot = {"updates": 0, "seconds": 0.0, "flips": 0, "moved": 0, "searched": 0, "timed_ms": 0.0, "launches": 0,
+           "out_s": 0.0}
+    prev = g.levels().clone()
+    for i, (kind, ins, dele) in enumerate(batches):
+        timed = i >= 3 * args.warmup
+        if timed and i == 3 * args.warmup:
+            P.plds_set_timing(g.h, "flip_scan")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.plds_update(g.h, ins, dele)
+        s = g.stats()
+        t1 = time.perf_counter()
+        k = P.plds_flips(g.h, fout)
+        ni, nd = P.plds_oriented_updates(g.h, ji, jd)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s2 = g.stats()
+        cur = g.levels()
+        moved = cur != prev
+        deg = g.degrees()
+        nm = int(moved.sum().item())
+        srch = int(deg[moved].sum().item())
+        prev = cur.clone()
+        if k > fcap:
+            raise RuntimeError(f"{k} flips exceed the buffer of {fcap}")
+        u = s["applied_ins"] + s["applied_del"]
+        assert (ni, nd) == (s["applied_ins"], s["applied_del"])
+        log(f"batch {i} {kind}: {u} updates, {k} flips, {nm} moved vertices, {srch} searched edges, "
+            f"update {1e3 * (t1 - t0):.2f} ms + F,J {1e3 * (t2 - t1):.2f} ms")
+        if timed:
+            tot["updates"] += u
+            tot["seconds"] += t2 - t0
+            tot["out_s"] += t2 - t1
+            tot["flips"] += k
+            tot["moved"] += nm
+            tot["searched"] += srch
+            tot["timed_ms"] += s2["timed_ms"]
+            tot["launches"] += s2["timed_launches"]
+    P.plds_set_timing(g.h, 0)
+    nb = 3 * args.steps
+    alg = 12 * tot["searched"] + 8 * tot["moved"] + 8 * tot["flips"]
+    roof = None
+    if tot["launches"] and tot["timed_ms"] > 0:
+        avg_ms = tot["timed_ms"] / tot["launches"]
+        per = alg / tot["launches"]
+        ach = per / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_flip_scan",
+                "avg_launch_us": round(avg_ms * 1e3, 3), "launches": tot["launches"],
+                "alg_bytes_per_launch": round(per, 1)}
+    out = {
+        "metric": "edge updates/s with orientation outputs (F, J) at 1e6 batch",
+        "value": tot["updates"] / tot["seconds"], "unit": "edge updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": tot["seconds"] / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"rmat{scale}-ef16-build16-then-ins/del/mix-{B}-with-flips", "n": n, "m0": m0,
+                   "delta": 0.4, "lambda": 3.0, "batch": B,
+                   "step": "1 insertion + 1 deletion + 1 mixed batch, each followed by F and J"},
+        "flips_per_batch": tot["flips"] / nb, "moved_per_batch": tot["moved"] / nb,
+        "searched_edges_per_batch": tot["searched"] / nb, "orientation_ms_per_batch": tot["out_s"] / nb * 1e3,
+        "roofline": roof,
     }
     print(json.dumps(out), flush=True)
 

@@ -144,6 +144,52 @@ int plds_batch_delete(plds_t *h, const int32_t *edges, int64_t count, void *stre
  * outside [0, n) yields -1.0 and latches PLDS_ERANGE for plds_sync. */
 int plds_coreness(plds_t *h, const int32_t *vertices, int64_t count, double *out, void *stream);
 
+/* Low out-degree orientation (orientation section, Algorithm 5): an edge
+ * points from the endpoint at the lower level to the one at the higher
+ * level; on equal levels the edge {u, v} with u < v points u -> v (the rule
+ * of Algorithm 5's flip conditions; the section's prose states the other tie
+ * order).  Every vertex's out-degree is then at most its up-degree, hence
+ * within the cap of its group (Invariant 1).
+ *
+ * plds_orient: (tail, head) of each of `count` pairs of the device int32
+ * [count][2] list `edges` under the current levels, into device int32
+ * [count][2] `out` (any pair of vertices, present in the graph or not).  An
+ * id outside [0, n) yields (-1, -1) and latches PLDS_ERANGE for plds_sync.
+ * Only enqueues work. */
+int plds_orient(plds_t *h, const int32_t *edges, int64_t count, int32_t *out, void *stream);
+
+/* Orientation tracking (Algorithm 5's outputs F and J).  While switched on
+ * (on != 0; allocates n int32 of device memory on first use), every update
+ * call keeps the levels it started from and its applied updates; the two
+ * calls below then report on the last update call (PLDS_EINVAL if tracking
+ * was off during it, if it failed, or after plds_load_state).  A call
+ * without updates reports empty sets. */
+int plds_track_orientation(plds_t *h, int32_t on);
+
+/* F: the edges present both before and after the last update call whose
+ * orientation changed, each as oriented before the call (tail, head), in no
+ * particular order, into device int32 [cap][2] `out`.  *count receives the
+ * number of such edges (only the first `cap` are written).  Found from the
+ * edges of the vertices whose level the call changed (Algorithm 5's searched
+ * edges).  Returns after the work on `stream` is complete. */
+int plds_flips(plds_t *h, int32_t *out, int64_t cap, int64_t *count, void *stream);
+
+/* J: the last update call's applied insertions oriented under the levels
+ * after the call, and its applied deletions under the levels before it, as
+ * (tail, head) into device int32 [ins_cap][2] / [del_cap][2]; *n_ins and
+ * *n_del receive the full counts (only the first caps are written; the order
+ * is the call's internal one).  Only enqueues work. */
+int plds_oriented_updates(plds_t *h, int32_t *ins_out, int64_t ins_cap, int64_t *n_ins, int32_t *del_out,
+                          int64_t del_cap, int64_t *n_del, void *stream);
+
+/* Densest-subgraph value (densest-subgraph corollary): the largest coreness
+ * estimate over the vertices of graph `graph` (0 for a plain handle; a graph
+ * of a multi-graph handle otherwise), 0.0 for a graph without edges.  With
+ * degeneracy d, the densest subgraph's density lies in [d/2, d], so this is a
+ * constant-factor approximation of it.  Written to host *out; returns after
+ * the work on `stream` is complete. */
+int plds_densest_value(plds_t *h, int32_t graph, double *out, void *stream);
+
 /* Current level of every vertex: device int32 [n]. */
 int plds_levels(plds_t *h, int32_t *out, void *stream);
 /* Current degree of every vertex: device int32 [n]. */
@@ -180,10 +226,10 @@ int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
  * identical. */
 int plds_set_sweep_mode(plds_t *h, int32_t mode);
 
-/* Time one kernel of the level sweeps (0 = off, 1 = insertion scan (which
- * also finishes the movers), 2 = deletion scan, 3 = desire-level, 4 =
- * insertion step preparation, 5 = unused, 6 = the cooperative insertion
- * sweep).  Each launch of that kernel carries a HIP event pair that the
+/* Time one kernel (0 = off, 1 = insertion scan (which also finishes the
+ * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
+ * preparation, 5 = the edge scan of plds_flips, 6 = the cooperative
+ * insertion sweep).  Each launch of that kernel carries a HIP event pair that the
  * runtime stamps at the dispatch's own start and end (hipExtLaunchKernel);
  * the cooperative sweep has events recorded around it on the stream.
  * While kind 1 or 4 is timed, insertion steps are launched one by one

@@ -109,6 +109,9 @@ struct Ctl {
     int32_t n_touch;      // distinct endpoints of those edges
     int32_t n_grow;       // slabs to regrow
     int32_t n_pieces;     // work items of the large regrown slabs
+    int32_t n_moved;      // vertices whose level the last update call changed
+    int64_t n_flip;       // flipped edges found
+    uint64_t dv_bits;     // largest coreness estimate of a graph (bits of a non-negative double)
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
     int32_t phys;         // level the movers of the current insertion step sit at
@@ -172,6 +175,8 @@ struct Dev {
     int32_t *sl0, *sl1;               // [n] vertices that stopped, by step parity
     int64_t *cw;                      // [cw_cap] climbing-step work items (vertex, role, 64-slot piece)
     int64_t cw_cap;
+    // orientation tracking (allocated when switched on)
+    int32_t *prevlvl;                 // [n] levels at the start of the last update call
 };
 
 // Levels per group and table offset of the graph that holds vertex v.
@@ -2217,6 +2222,153 @@ __global__ void k_coreness(Dev d, const int32_t *vs, int64_t cnt, double *out) {
 // Full check, one wave per vertex; bad[0..5] count violations of:
 // counters, Invariant 1, Invariant 2, isolated at level 0, level range,
 // slab live count == degree.
+// ---- orientation (the orientation section, Algorithm 5): an edge points
+// from the endpoint at the lower level to the one at the higher level; on
+// equal levels the edge {u, v}, u < v, points u -> v.
+__device__ __forceinline__ bool points_up(int32_t u, int32_t v, int32_t lu, int32_t lv) {
+    // true: min(u, v) -> max(u, v)
+    return u < v ? lu <= lv : lv <= lu;
+}
+
+// (tail, head) of each edge under the levels lv; ids out of range give
+// (-1, -1) and latch a range error.
+__global__ void k_orient(Dev d, const int32_t *e, int64_t cnt, const int32_t *lv, int32_t *out) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        const int32_t a = e[2 * i], b = e[2 * i + 1];
+        if (a < 0 || a >= d.n || b < 0 || b >= d.n) {
+            out[2 * i] = out[2 * i + 1] = -1;
+            latch(d.ctl, kErrRange);
+            continue;
+        }
+        const int32_t u = min(a, b), v = max(a, b);
+        const bool fwd = points_up(u, v, lv[u], lv[v]);
+        out[2 * i] = fwd ? u : v;
+        out[2 * i + 1] = fwd ? v : u;
+    }
+}
+
+// Vertices whose level differs from the call's starting level, into d.mv.
+__global__ void k_flip_moved(Dev d) {
+    __shared__ Stage q;
+    stage_init(q);
+    const int stride = gridDim.x * blockDim.x;
+    for (int vb = blockIdx.x * blockDim.x; vb < d.n; vb += stride) {
+        const int v = vb + threadIdx.x;
+        const bool mv = v < d.n && d.level[v] != d.prevlvl[v];
+        stage_push(q, mv, v);
+        stage_flush(q, blockDim.x, d.mv, &d.ctl->n_moved, d.n, d.ctl);
+    }
+    stage_flush(q, kStage, d.mv, &d.ctl->n_moved, d.n, d.ctl);
+}
+
+// The call's applied insertions into the batch hash set (empty before).
+__global__ void k_flip_inserted(Dev d, const int32_t *ins, int64_t cnt) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        const uint64_t key = ((uint64_t)(uint32_t)ins[2 * i] << 32) | (uint32_t)ins[2 * i + 1];
+        uint64_t j = mix64(key) & d.hmask;
+        for (uint64_t p = 0; p <= d.hmask; p++) {
+            const uint64_t prev =
+                atomicCAS((unsigned long long *)&d.hset[j], (unsigned long long)kEmpty64, (unsigned long long)key);
+            if (prev == kEmpty64 || prev == key) break;
+            j = (j + 1) & d.hmask;
+        }
+    }
+}
+
+__device__ __forceinline__ bool flip_was_inserted(const Dev &d, uint64_t key) {
+    uint64_t j = mix64(key) & d.hmask;
+    for (uint64_t p = 0; p <= d.hmask; p++) {
+        const uint64_t x = d.hset[j];
+        if (x == key) return true;
+        if (x == kEmpty64) return false;
+        j = (j + 1) & d.hmask;
+    }
+    return false;
+}
+
+// Algorithm 5's first loop: the moved vertices search their edges; an edge
+// whose orientation under the starting levels differs from the one under
+// the current levels is a flip, reported as it was.  An edge with both
+// endpoints moved is reported by its smaller endpoint; edges the call
+// inserted (in the hash set when with_ins) had no orientation before.
+// A wavefront searches one vertex's slab at a time.  Each wavefront stages
+// its flips in LDS and appends them with one atomic per 256; positions at
+// or beyond cap are counted, not written.
+constexpr int kFlipStage = 256;
+__global__ void __launch_bounds__(kBlock) k_flip_scan(Dev d, int with_ins, int32_t *out, int64_t cap) {
+    __shared__ int32_t buf[kBlock / kWave][2 * (kFlipStage + kWave)];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int32_t *b = buf[wv];
+    int32_t nb = 0;   // wave-uniform
+    auto flush = [&]() {
+        __threadfence_block();   // the wavefront's staged entries are visible to all its lanes
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long *)&d.ctl->n_flip, (unsigned long long)nb);
+        base = __shfl(base, 0, kWave);
+        for (int i = lane; i < 2 * nb; i += kWave)
+            if ((int64_t)base + i / 2 < cap) out[2 * base + i] = b[i];
+        nb = 0;
+    };
+    // one searched slot: stage the edge (u, w) if it flipped (every lane of
+    // the wavefront calls it together)
+    auto slot = [&](int32_t u, int32_t lu0, int32_t lu1, int32_t w) {
+        bool f = false;
+        int32_t t = 0, hd = 0;
+        if (w >= 0) {
+            const int32_t lw0 = d.prevlvl[w], lw1 = d.level[w];
+            const bool b0 = points_up(u, w, lu0, lw0), b1 = points_up(u, w, lu1, lw1);
+            const int32_t lo = min(u, w), hi = max(u, w);
+            f = b0 != b1 && (lw0 == lw1 || u < w);
+            if (f && with_ins) f = !flip_was_inserted(d, ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi);
+            t = b0 ? lo : hi;
+            hd = b0 ? hi : lo;
+        }
+        const uint64_t m = __ballot(f);
+        if (f) {
+            const int k = nb + __popcll(m & ((1ull << lane) - 1));
+            b[2 * k] = t;
+            b[2 * k + 1] = hd;
+        }
+        nb += __popcll(m);
+        if (nb >= kFlipStage) flush();
+    };
+    const int nw = gridDim.x * blockDim.x / kWave;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int32_t nm = d.ctl->n_moved;
+    for (int i = wid; i < nm; i += nw) {
+        const int32_t u = d.mv[i];
+        const int32_t lu0 = d.prevlvl[u], lu1 = d.level[u];
+        const int32_t cap_u = d.cap[u];
+        const int32_t *sl = d.pool + d.off[u];
+        for (int32_t e0 = 0; e0 < cap_u; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            slot(u, lu0, lu1, e < cap_u ? sl[e] : -1);
+        }
+    }
+    if (nb) flush();
+}
+
+// Largest coreness estimate over the vertices [v0, v0 + cnt) (one graph).
+__global__ void k_max_estimate(Dev d, int32_t v0, int32_t cnt) {
+    uint64_t best = 0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        const int32_t v = v0 + i;
+        if (d.deg[v] == 0) continue;
+        const GP p = gp(d, v);
+        const int32_t e = (d.level[v] + 1) / p.L - 1;
+        const double est = d.pow_tab[p.tab + (e > 0 ? e : 0)];
+        best = max(best, (uint64_t)__double_as_longlong(est));
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor((unsigned long long)best, o, kWave);
+        best = max(best, y);
+    }
+    if (threadIdx.x % kWave == 0 && best) atomicMax((unsigned long long *)&d.ctl->dv_bits, (unsigned long long)best);
+}
+
 __global__ void k_check(Dev d, int32_t *bad) {
     int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     int nw = gridDim.x * blockDim.x / kWave;
@@ -2467,6 +2619,12 @@ struct plds {
     hipGraphExec_t del_exec = nullptr;
     Dev del_graph_dev{};
     int64_t del_steps_hint = 0;   // steps of the last deletion sweep
+    // orientation tracking: the last update call's starting levels and its
+    // applied updates (pairs (min, max))
+    bool track = false;
+    bool tracked_call = false;
+    int32_t *t_ins = nullptr, *t_del = nullptr;
+    int64_t t_ins_cap = 0, t_del_cap = 0, n_tins = 0, n_tdel = 0;
     int par[2] = {0, 1};
     // optional event timing of one sweep kernel
     int32_t timed_kind = 0;
@@ -2545,6 +2703,7 @@ void free_all(plds *h) {
     dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.mv1), dfree(d.sp), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
     dfree(d.lvb_start), dfree(d.lvb_fill), dfree(d.lvb), dfree(d.cl), dfree(d.sl0), dfree(d.sl1), dfree(d.cw);
     dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
+    dfree(d.prevlvl), dfree(h->t_ins), dfree(h->t_del);
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
     if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
     h->ins_exec = nullptr;
@@ -2739,6 +2898,23 @@ int check_err(plds *h) {
     return PLDS_OK;
 }
 
+// Orientation tracking: keep a copy of the call's applied list (pairs
+// (min, max)) for plds_oriented_updates and plds_flips.
+int track_list(plds *h, int insert, int64_t applied, hipStream_t s) {
+    int32_t *&buf = insert ? h->t_ins : h->t_del;
+    int64_t &cap = insert ? h->t_ins_cap : h->t_del_cap;
+    if (applied > cap) {
+        dfree(buf);
+        cap = 0;
+        if (dalloc(&buf, 2 * applied)) return PLDS_ENOMEM;
+        cap = applied;
+    }
+    if (applied)
+        HIPCHK(hipMemcpyAsync(buf, h->d.valid, (size_t)applied * 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    (insert ? h->n_tins : h->n_tdel) = applied;
+    return PLDS_OK;
+}
+
 // Preprocess one list and apply it to the slabs.  insert=1: keep absent
 // pairs, regrow slabs, insert; insert=0: keep present pairs, delete.
 // On return the touched endpoints are in d.touch (count in ctl).
@@ -2770,6 +2946,10 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
         }
     }
     *applied = h->h_ctl->n_valid;
+    if (h->track) {
+        rc = track_list(h, insert, *applied, s);
+        if (rc) return rc;
+    }
     if (insert) {
         if (h->h_ctl->n_grow > 0) {
             int64_t req = h->h_ctl->grow_req;
@@ -3229,9 +3409,24 @@ int begin_call(plds *h, hipStream_t s) {
 
 // Algorithm 1 on range-checked lists of global ids: insertions and their
 // sweep, then deletions and theirs.
-int run_update(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, hipStream_t s) {
+// A call without updates: its flips and oriented updates are empty.
+int track_empty(plds *h, hipStream_t s) {
+    if (!h->track) return PLDS_OK;
+    h->n_tins = h->n_tdel = 0;
+    HIPCHK(hipMemcpyAsync(h->d.prevlvl, h->d.level, (size_t)h->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    h->tracked_call = true;
+    return PLDS_OK;
+}
+
+int run_update_body(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, hipStream_t s) {
     int rc;
     bool synced = false;   // the last step ended with a wait, nothing launched since
+    h->tracked_call = false;
+    if (h->track) {   // the levels the call starts from (the range checks are ahead on the stream)
+        h->n_tins = h->n_tdel = 0;
+        HIPCHK(hipMemcpyAsync(h->d.prevlvl, h->d.level, (size_t)h->n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              s));
+    }
     if (n_ins) {
         int64_t applied = 0;
         rc = apply_list(h, ins, n_ins, 1, s, &applied);
@@ -3263,6 +3458,12 @@ int run_update(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *del, i
     return check_err(h);
 }
 
+int run_update(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *del, int64_t n_del, hipStream_t s) {
+    int rc = run_update_body(h, ins, n_ins, del, n_del, s);
+    h->tracked_call = h->track && rc == PLDS_OK;
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3274,7 +3475,7 @@ int plds_update(plds_t *h, const int32_t *ins, int64_t n_ins, const int32_t *del
     if ((uint64_t)n_ins > (uint64_t)INT32_MAX / 2 || (uint64_t)n_del > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
     hipStream_t s = S(stream);
     memset(&h->stats, 0, sizeof(h->stats));
-    if (n_ins + n_del == 0) return PLDS_OK;
+    if (n_ins + n_del == 0) return track_empty(h, s);
     rc = begin_call(h, s);
     if (rc) return rc;
     // range check of both lists before anything changes
@@ -3300,7 +3501,7 @@ int plds_update_multi(plds_t *h, const int32_t *const *ins, const int64_t *n_ins
     if ((uint64_t)ti > (uint64_t)INT32_MAX / 2 || (uint64_t)td > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
     hipStream_t s = S(stream);
     memset(&h->stats, 0, sizeof(h->stats));
-    if (ti + td == 0) return PLDS_OK;
+    if (ti + td == 0) return track_empty(h, s);
     if (ti + td > h->stage_cap) {
         dfree(h->stage);
         h->stage_cap = 0;
@@ -3365,6 +3566,93 @@ int plds_coreness(plds_t *h, const int32_t *vertices, int64_t count, double *out
     if (cnt == 0) return PLDS_OK;
     hipLaunchKernelGGL(k_coreness, dim3(grid_for(cnt)), dim3(kBlock), 0, S(stream), h->d, vertices, cnt, out);
     HIPCHK(hipGetLastError());
+    return PLDS_OK;
+}
+
+int plds_track_orientation(plds_t *h, int32_t on) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (on && !h->d.prevlvl && dalloc(&h->d.prevlvl, h->n)) return PLDS_ENOMEM;
+    h->track = on != 0;
+    h->tracked_call = false;
+    return PLDS_OK;
+}
+
+int plds_orient(plds_t *h, const int32_t *edges, int64_t count, int32_t *out, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (count < 0 || (count && (!edges || !out))) return PLDS_EINVAL;
+    if (count == 0) return PLDS_OK;
+    hipLaunchKernelGGL(k_orient, dim3(grid_for(count)), dim3(kBlock), 0, S(stream), h->d, edges, count, h->d.level,
+                       out);
+    HIPCHK(hipGetLastError());
+    return PLDS_OK;
+}
+
+int plds_oriented_updates(plds_t *h, int32_t *ins_out, int64_t ins_cap, int64_t *n_ins, int32_t *del_out,
+                          int64_t del_cap, int64_t *n_del, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!n_ins || !n_del || ins_cap < 0 || del_cap < 0 || (ins_cap && !ins_out) || (del_cap && !del_out))
+        return PLDS_EINVAL;
+    if (!h->tracked_call) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    *n_ins = h->n_tins;
+    *n_del = h->n_tdel;
+    int64_t ki = std::min(h->n_tins, ins_cap), kd = std::min(h->n_tdel, del_cap);
+    if (ki) hipLaunchKernelGGL(k_orient, dim3(grid_for(ki)), dim3(kBlock), 0, s, h->d, h->t_ins, ki, h->d.level, ins_out);
+    if (kd)
+        hipLaunchKernelGGL(k_orient, dim3(grid_for(kd)), dim3(kBlock), 0, s, h->d, h->t_del, kd, h->d.prevlvl, del_out);
+    HIPCHK(hipGetLastError());
+    return PLDS_OK;
+}
+
+int plds_flips(plds_t *h, int32_t *out, int64_t cap, int64_t *count, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!count || cap < 0 || (cap && !out)) return PLDS_EINVAL;
+    if (!h->tracked_call) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    Dev &d = h->d;
+    h->h_ctl->n_moved = 0;
+    h->h_ctl->n_flip = 0;
+    HIPCHK(hipMemcpyAsync(&d.ctl->n_moved, &h->h_ctl->n_moved, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(&d.ctl->n_flip, &h->h_ctl->n_flip, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const int with_ins = h->n_tins > 0;
+    if (with_ins) {   // the call's insertions had no orientation before it
+        rc = ensure_batch(h, h->n_tins);
+        if (rc) return rc;
+        HIPCHK(hipMemsetAsync(d.hset, 0xff, (size_t)(d.hmask + 1) * sizeof(uint64_t), s));
+        hipLaunchKernelGGL(k_flip_inserted, dim3(grid_for(h->n_tins)), dim3(kBlock), 0, s, d, h->t_ins, h->n_tins);
+    }
+    hipLaunchKernelGGL(k_flip_moved, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
+    tlaunch(h, 5, k_flip_scan, dim3(grid_for((int64_t)h->n * kWave, kBlock, 2048)), dim3(kBlock), 0, s, d, with_ins,
+            out, cap);
+    HIPCHK(hipGetLastError());
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    take_timing(h, h->ev_used);
+    *count = h->h_ctl->n_flip;
+    return check_err(h);
+}
+
+int plds_densest_value(plds_t *h, int32_t graph, double *out, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!out || graph < 0 || graph >= h->d.ng) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    int64_t v0 = h->d.ng > 1 ? h->gbase[graph] : 0, cnt = h->d.ng > 1 ? h->gn[graph] : h->n;
+    h->h_ctl->dv_bits = 0;
+    HIPCHK(hipMemcpyAsync(&h->d.ctl->dv_bits, &h->h_ctl->dv_bits, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    if (cnt)
+        hipLaunchKernelGGL(k_max_estimate, dim3(grid_for(cnt, kBlock, kApplyGrid)), dim3(kBlock), 0, s, h->d,
+                           (int32_t)v0, (int32_t)cnt);
+    HIPCHK(hipGetLastError());
+    uint64_t bits = 0;
+    HIPCHK(hipMemcpyAsync(&h->h_ctl->dv_bits, &h->d.ctl->dv_bits, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bits = h->h_ctl->dv_bits;
+    memcpy(out, &bits, sizeof(double));
     return PLDS_OK;
 }
 
@@ -3488,6 +3776,7 @@ int plds_load_state(plds_t *h, const int32_t *edges, int64_t m, const int32_t *l
     if (m < 0 || (m && !edges) || !levels || (uint64_t)m > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
     hipStream_t s = S(stream);
     Dev &d = h->d;
+    h->tracked_call = false;   // a loaded state has no last update call
     // validate ids and levels before touching the state
     h->h_ctl->err = 0;
     HIPCHK(hipMemcpyAsync(&d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));

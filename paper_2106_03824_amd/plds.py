@@ -36,7 +36,7 @@ class plds_stats_t(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS[:-1]] + [("timed_ms", ctypes.c_double),
                                                                    ("reserved", ctypes.c_int64)]
 
-TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "ins_sweep": 6}
+TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "flip_scan": 5, "ins_sweep": 6}
 
 
 _lib = None
@@ -74,6 +74,12 @@ def lib():
         L.plds_load_state.argtypes = [_VP, _VP, _I64, _VP, _VP]
         L.plds_check.argtypes = [_VP, _VP]
         L.plds_sync.argtypes = [_VP, _VP]
+        L.plds_orient.argtypes = [_VP, _VP, _I64, _VP, _VP]
+        L.plds_track_orientation.argtypes = [_VP, ctypes.c_int32]
+        L.plds_flips.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64), _VP]
+        L.plds_oriented_updates.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64), _VP, _I64, ctypes.POINTER(_I64),
+                                            _VP]
+        L.plds_densest_value.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP]
         L.plds_strerror.restype = ctypes.c_char_p
         L.plds_strerror.argtypes = [ctypes.c_int]
         _lib = L
@@ -83,7 +89,8 @@ def lib():
 EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi", "plds_update_multi",
            "plds_graph_info", "plds_update", "plds_batch_insert",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
-           "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror")
+           "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror",
+           "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value")
 
 
 def strerror(code):
@@ -199,6 +206,40 @@ def plds_batch_delete(h, edges, stream=None, check=True):
 def plds_coreness(h, vertices, out, stream=None):
     cnt = 0 if vertices is None else int(vertices.numel())
     return _chk(lib().plds_coreness(h, _ptr(vertices), cnt, _ptr(out), _stream(stream)), "plds_coreness")
+
+
+def plds_orient(h, edges, out, stream=None):
+    p, c = _edges_arg(edges)
+    return _chk(lib().plds_orient(h, p, c, _ptr(out), _stream(stream)), "plds_orient")
+
+
+def plds_track_orientation(h, on):
+    return _chk(lib().plds_track_orientation(h, 1 if on else 0), "plds_track_orientation")
+
+
+def plds_flips(h, out, stream=None):
+    """Returns the number of flipped edges (rows of `out` beyond it are unset;
+    only the first out.shape[0] are written)."""
+    cnt = _I64()
+    cap = 0 if out is None else int(out.shape[0])
+    _chk(lib().plds_flips(h, _ptr(out), cap, ctypes.byref(cnt), _stream(stream)), "plds_flips")
+    return cnt.value
+
+
+def plds_oriented_updates(h, ins_out, del_out, stream=None):
+    """Returns (applied insertions, applied deletions) of the last call."""
+    ni, nd = _I64(), _I64()
+    ci = 0 if ins_out is None else int(ins_out.shape[0])
+    cd = 0 if del_out is None else int(del_out.shape[0])
+    _chk(lib().plds_oriented_updates(h, _ptr(ins_out), ci, ctypes.byref(ni), _ptr(del_out), cd, ctypes.byref(nd),
+                                     _stream(stream)), "plds_oriented_updates")
+    return ni.value, nd.value
+
+
+def plds_densest_value(h, graph=0, stream=None):
+    out = ctypes.c_double()
+    _chk(lib().plds_densest_value(h, int(graph), ctypes.byref(out), _stream(stream)), "plds_densest_value")
+    return out.value
 
 
 def plds_levels(h, out, stream=None):
@@ -349,6 +390,37 @@ class PLDS:
         import torch
         lv = torch.as_tensor(levels, dtype=torch.int32).to("cuda").contiguous()
         return plds_load_state(self.h, self._dev(edges), lv, check=check)
+
+    def orient(self, edges):
+        import torch
+        e = self._dev(edges)
+        out = torch.empty_like(e)
+        plds_orient(self.h, e, out)
+        return out
+
+    def track_orientation(self, on=True):
+        plds_track_orientation(self.h, on)
+
+    def flips(self):
+        """F of the last update call: device int32 [k, 2] (tail, head) as before."""
+        import torch
+        k = plds_flips(self.h, None)
+        out = torch.empty((max(k, 1), 2), dtype=torch.int32, device="cuda")
+        k2 = plds_flips(self.h, out)
+        assert k2 == k
+        return out[:k]
+
+    def oriented_updates(self):
+        """J of the last update call: (insertions after, deletions before)."""
+        import torch
+        ni, nd = plds_oriented_updates(self.h, None, None)
+        a = torch.empty((max(ni, 1), 2), dtype=torch.int32, device="cuda")
+        b = torch.empty((max(nd, 1), 2), dtype=torch.int32, device="cuda")
+        plds_oriented_updates(self.h, a, b)
+        return a[:ni], b[:nd]
+
+    def densest_value(self, graph=0):
+        return plds_densest_value(self.h, graph)
 
 
 class MultiPLDS(PLDS):
