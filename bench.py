@@ -156,6 +156,9 @@ def main():
     ap.add_argument("--batched", action="store_true", help="the batched form: 256 graphs in one handle")
     ap.add_argument("--graphs", type=int, default=256)
     ap.add_argument("--serve", action="store_true", help="the serving form: resident graphs behind a request loop")
+    ap.add_argument("--opt", action="store_true",
+                    help="the default RMAT-20 stream with the PLDSOpt level structure (ceil(log_{1+delta} n / 50) "
+                         "levels per group)")
     ap.add_argument("--orient", action="store_true",
                     help="the RMAT-20 stream with the orientation outputs (flips F, oriented updates J) per batch")
     ap.add_argument("--serve-graphs", type=int, default=64)
@@ -197,8 +200,11 @@ def main():
     log("generating R-MAT", scale, m0)
     st = W.RmatStream(scale, m0, seed=1, build_batches=16, cfg=2)
     n = st.n
-    g = P.PLDS(n, 0.4, 3.0, 0, 2 * m0)
-    trace = json.load(open(TRACE)) if (scale == 20 and B == 10 ** 6 and os.path.exists(TRACE)) else None
+    lpg = P.PLDS_LPG_OPT if args.opt else 0
+    g = P.PLDS(n, 0.4, 3.0, lpg, 2 * m0)
+    # the stored oracle trace is of the paper's level structure
+    trace = json.load(open(TRACE)) if (scale == 20 and B == 10 ** 6 and not args.opt and os.path.exists(TRACE)) \
+        else None
     parity = {"batches_checked": 0, "mismatches": 0}
 
     def check(idx, lv=None, s=None):
@@ -296,8 +302,9 @@ def main():
         "metric": METRIC, "value": value, "unit": "edge updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"rmat{scale}-ef16-build16-then-ins/del/mix-{B}", "n": n, "m0": m0,
-                   "delta": 0.4, "lambda": 3.0, "batch": B, "step": "1 insertion + 1 deletion + 1 mixed batch"},
+        "config": {"workload": f"rmat{scale}-ef16-build16-then-ins/del/mix-{B}" + ("-pldsopt" if args.opt else ""),
+                   "n": n, "m0": m0, "delta": 0.4, "lambda": 3.0, "levels_per_group": g.L, "batch": B,
+                   "step": "1 insertion + 1 deletion + 1 mixed batch"},
         "rates": {k: (v[0] / v[1] if v[1] else None) for k, v in per_kind.items()},
         "batch_latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1,
                                                                               int(0.99 * len(lat_ms)))]},
@@ -306,7 +313,9 @@ def main():
         "roofline": roof,
         "parity_vs_oracle_trace": parity if trace is not None else None,
     }
-    if not args.no_cpu_baseline:
+    if args.opt:
+        out["invariants_hold"] = g.check() == 0   # no stored oracle trace for this level structure
+    elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -83,7 +83,11 @@ typedef struct {
 int plds_create(int64_t n, double delta, double lambda, plds_t **out);
 
 /* As plds_create; levels_per_group > 0 overrides 4t (e.g. 3 for the paper's
- * worked examples); edge_capacity_hint (>= 0) pre-sizes the adjacency pool. */
+ * worked examples), PLDS_LPG_OPT selects the experiments' PLDSOpt variant
+ * (ceil(log_{1+delta} n / 50) levels per group, that is ceil(t / 50): fewer
+ * levels, a looser approximation); edge_capacity_hint (>= 0) pre-sizes the
+ * adjacency pool. */
+#define PLDS_LPG_OPT (-1)
 int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int64_t edge_capacity_hint,
                    plds_t **out);
 
@@ -92,7 +96,8 @@ int plds_destroy(plds_t *h);
 /* Batched form: one handle holding `ngraphs` independent graphs, graph g
  * with n[g] vertices (host array), all with the same delta and lambda.  Each
  * graph keeps its own levels per group (4t_g from its own n[g], or
- * levels_per_group when > 0) and its own thresholds, exactly as a handle
+ * levels_per_group when > 0, or ceil(t_g / 50) for PLDS_LPG_OPT) and its own
+ * thresholds, exactly as a handle
  * made by plds_create_ex(n[g], ...) would, so every graph goes through the
  * same states as it would alone: no edge joins two graphs, and whether a
  * vertex moves at a level depends only on its own neighbours and its own

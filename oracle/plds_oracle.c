@@ -110,7 +110,9 @@ static int cmp_u64(const void *a, const void *b) {
 
 /* ------------------------------------------------------------ parameters */
 /* Levels and groups (Section "Detailed PLDS Algorithm"): groups
- * g_0..g_t with t = ceil(log_{1+delta} n), 4t levels per group. */
+ * g_0..g_t with t = ceil(log_{1+delta} n), 4t levels per group; the
+ * experiments' PLDSOpt variant has ceil(log_{1+delta} n / 50) levels per
+ * group (levels_per_group == -1). */
 static void build_tables(ora_t *o, int32_t levels_per_group) {
     double p = 1.0;
     int32_t t = 0;
@@ -119,7 +121,12 @@ static void build_tables(ora_t *o, int32_t levels_per_group) {
         t++;
     }
     o->t = t;
-    o->L = levels_per_group > 0 ? levels_per_group : (4 * t > 1 ? 4 * t : 1);
+    if (levels_per_group > 0)
+        o->L = levels_per_group;
+    else if (levels_per_group == -1)            /* PLDSOpt: ceil(log_{1+delta} n / 50) = ceil(t / 50) */
+        o->L = (t + 49) / 50 > 1 ? (t + 49) / 50 : 1;
+    else
+        o->L = 4 * t > 1 ? 4 * t : 1;
     o->G = t + 1;
     o->K = o->G * o->L;
     o->up_max = (int32_t *)malloc((size_t)o->G * sizeof(int32_t));

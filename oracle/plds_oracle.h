@@ -30,7 +30,9 @@ typedef struct ora ora_t;
  * mode 1: full-scan mode -- every level 0..K-1 is visited and every vertex is
  *         re-examined with degrees recounted from the adjacency.  Slow; used
  *         to pin mode 0 on tiny graphs.
- * levels_per_group <= 0 selects the default 4*ceil(log_{1+delta} n). */
+ * levels_per_group > 0 overrides the levels per group; -1 selects the
+ * experiments' PLDSOpt variant, ceil(log_{1+delta} n / 50); 0 (or any other
+ * value <= 0) the default 4*ceil(log_{1+delta} n). */
 ora_t *ora_create(int64_t n, double delta, double lambda, int32_t levels_per_group, int32_t mode);
 void ora_destroy(ora_t *o);
 

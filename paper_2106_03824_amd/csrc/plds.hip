@@ -2542,7 +2542,8 @@ __global__ void k_stage(const Seg *segs, int32_t nseg, int64_t total, int32_t *o
 // ===================================================================== host
 // Levels, groups and thresholds of one graph (Section "Detailed PLDS
 // Algorithm"): t = least integer with (1+delta)^t >= n, L = 4t (or the
-// override, at least 1), G = t+1, K = G*L; up_max[g] = floor((2+3/lambda)
+// override, at least 1; or the experiments' PLDSOpt ceil(t/50), which is
+// ceil(log_{1+delta} n / 50)), G = t+1, K = G*L; up_max[g] = floor((2+3/lambda)
 // x_g) and dn_min[g] = ceil(x_g) as exact integer rewrites of Invariants
 // 1-2, where x_g = (1+delta)^g is formed by repeated IEEE double
 // multiplication.  Entry G of up_max/dn_min is INT32_MAX.
@@ -2559,7 +2560,7 @@ static Tables make_tables(int64_t n, double delta, double lambda, int32_t lpg) {
         p *= 1.0 + delta;
         T.t++;
     }
-    T.L = lpg > 0 ? lpg : std::max(1, 4 * T.t);
+    T.L = lpg > 0 ? lpg : lpg == PLDS_LPG_OPT ? std::max(1, (T.t + 49) / 50) : std::max(1, 4 * T.t);
     T.G = T.t + 1;
     T.K = T.G * T.L;
     T.up.assign(T.G + 1, INT32_MAX);
@@ -3253,7 +3254,7 @@ int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double l
     if (!out) return PLDS_EINVAL;
     *out = nullptr;
     if (ngraphs < 1 || !ns || !(delta > 0) || !(lambda > 0) || !std::isfinite(delta) || !std::isfinite(lambda) ||
-        levels_per_group < 0 || edge_capacity_hint < 0)
+        (levels_per_group < 0 && levels_per_group != PLDS_LPG_OPT) || edge_capacity_hint < 0)
         return PLDS_EINVAL;
     int64_t n = 0;
     for (int32_t g = 0; g < ngraphs; g++) {

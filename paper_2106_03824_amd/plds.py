@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libplds.so")
 
 PLDS_OK, PLDS_EINVAL, PLDS_ERANGE, PLDS_ENOMEM, PLDS_EHIP, PLDS_ESTATE = 0, -1, -2, -3, -4, -5
+PLDS_LPG_OPT = -1   # levels per group of the PLDSOpt variant: ceil(log_{1+delta} n / 50)
 
 
 class PLDSError(RuntimeError):

@@ -81,7 +81,7 @@ class Pair:
 
 def test_thresholds_match_oracle():
     for n, d, l, L in [(2 ** 12, 0.4, 3.0, 0), (2 ** 20, 0.4, 3.0, 0), (2 ** 24, 0.4, 3.0, 0), (1000, 1.0, 3.0, 3),
-                       (5000, 0.2, 6.0, 0), (1, 0.4, 3.0, 0)]:
+                       (5000, 0.2, 6.0, 0), (1, 0.4, 3.0, 0), (2 ** 20, 0.4, 3.0, -1), (10 ** 6, 0.1, 3.0, -1)]:
         say("thresholds", n, d, l, L)
         g = lib().PLDS(n, d, l, L)
         o = O.Oracle(n, d, l, L)
@@ -158,7 +158,7 @@ def test_out_of_range_rejected_state_unchanged():
 def test_random_small(seed):
     rng = random.Random(seed)
     n = rng.choice([8, 20, 64, 200])
-    L = rng.choice([0, 0, 2, 3])
+    L = rng.choice([0, 0, 2, 3, -1])
     delta, lam = rng.choice([(0.4, 3.0), (1.0, 3.0), (0.2, 6.0)])
     say("random small", seed, n, L, delta, lam)
     p = Pair(n, delta, lam, L, sweep_mode=seed % 4, direct={1: "ins", 3: "del"}.get(seed % 5, False))
@@ -206,6 +206,24 @@ def test_rmat_multi_batch(mode, direct):
     say("rmat14 mixed")
     p.step(ins=W.new_pairs(n, cur, 20000, 2002), dele=W.sample_edges(cur, 20000, 2003))
     say("rmat14 delete")
+    p.step(dele=W.sample_edges(p.o.edges(), 50000, 2004))
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_rmat_multi_batch_pldsopt(mode):
+    """The RMAT scale-14 stream of test_rmat_multi_batch with the PLDSOpt
+    level structure (ceil(log_{1+delta} n / 50) levels per group)."""
+    n = 2 ** 14
+    e = W.permute_edges(W.rmat(14, 16 * n, seed=3), 2001)
+    p = Pair(n, L=lib().PLDS_LPG_OPT, sweep_mode=mode)
+    assert p.g.L == p.o.L == 1
+    for i, c in enumerate(np.array_split(e, 4)):
+        say("rmat14 pldsopt build", i)
+        p.step(ins=c)
+    cur = p.o.edges()
+    say("rmat14 pldsopt mixed")
+    p.step(ins=W.new_pairs(n, cur, 20000, 2002), dele=W.sample_edges(cur, 20000, 2003))
+    say("rmat14 pldsopt delete")
     p.step(dele=W.sample_edges(p.o.edges(), 50000, 2004))
 
 

@@ -33,6 +33,28 @@ def test_level_structure(n, t, L, G, K):
     assert (o.t, o.L, o.G, o.K) == (t, L, G, K)
 
 
+@pytest.mark.parametrize("n,delta,t,L", [(2 ** 20, "2/5", 42, 1), (2 ** 24, "2/5", 50, 1), (2 ** 12, "1/5", 46, 1),
+                                         (42851237, "2/5", 53, 2), (42851237, "4/5", 30, 1),
+                                         (10 ** 9, "1/10", 218, 5)])
+def test_pldsopt_levels(n, delta, t, L):
+    """PLDSOpt (experiments): ceil(log_{1+delta} n / 50) levels per group, the
+    same groups.  t comes from exact rational arithmetic (least t with
+    (1+delta)^t >= n); with n = 42,851,237 (the experiments' livejournal
+    count) the rule gives 2 levels per group at delta = 0.4 and 1 at 0.8
+    (the paper's remark that it is 1 for every delta below 0.42 has the
+    comparison the wrong way round)."""
+    d = Fraction(delta)
+    p, tt = Fraction(1), 0
+    while p < n:
+        p *= 1 + d
+        tt += 1
+    assert tt == t and -(-t // 50) == L
+    assert math.ceil(math.log(n) / math.log(1 + float(d)) / 50) == L
+    if n <= 2 ** 24:
+        o = O.Oracle(n, float(d), 3.0, -1)
+        assert (o.t, o.L, o.G, o.K) == (t, L, t + 1, (t + 1) * L)
+
+
 @pytest.mark.parametrize("n,delta,lam", [(2 ** 12, "2/5", 3), (2 ** 20, "2/5", 3), (2 ** 24, "2/5", 3),
                                          (1000, "1", 3), (5000, "1/5", 6), (2 ** 16, "4/5", 12),
                                          (300, "8/5", 24), (2 ** 22, "2/5", 3)])
