@@ -195,6 +195,23 @@ int plds_oriented_updates(plds_t *h, int32_t *ins_out, int64_t ins_cap, int64_t 
  * the work on `stream` is complete. */
 int plds_densest_value(plds_t *h, int32_t graph, double *out, void *stream);
 
+/* Static approximate k-core of the handle's current graph (static section,
+ * Algorithm 6): bucketed peeling with bucket base 1+eps (eps > 0), the
+ * (2+eps')-approximation with (2+eps)(1+eps) = 2+eps'.  Read as follows
+ * (the section's prose, listing and worked example disagree; this reading
+ * reproduces the worked example): a vertex with count C >= 1 sits in bucket
+ * ceil(log_{1+eps} C) (C starts at the degree); a threshold t is the
+ * smallest bucket; its peels take the smallest bucket in turn while it is
+ * within (2+eps)(1+eps)^t, at most ceil(log_{1+2/eps} n) peels per
+ * threshold; a peel lowers each alive neighbour's C by its peeled
+ * neighbours, to no less than ceil((1+eps)^(t-1)), and re-buckets it to no
+ * less than t; a vertex peeled from bucket b gets the estimate (1+eps)^b;
+ * vertices without edges get 0.  est_out: device float64 [n].  Leaves the
+ * handle's levels unchanged.  Plain handles only (PLDS_EINVAL for a
+ * multi-graph handle, or for eps so small that the powers of 1+eps below n
+ * exceed 4096 buckets).  Returns after the work on `stream` is complete. */
+int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream);
+
 /* Current level of every vertex: device int32 [n]. */
 int plds_levels(plds_t *h, int32_t *out, void *stream);
 /* Current degree of every vertex: device int32 [n]. */

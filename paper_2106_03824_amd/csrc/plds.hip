@@ -112,6 +112,9 @@ struct Ctl {
     int32_t n_moved;      // vertices whose level the last update call changed
     int64_t n_flip;       // flipped edges found
     uint64_t dv_bits;     // largest coreness estimate of a graph (bits of a non-negative double)
+    // static approximate k-core (Algorithm 6)
+    int32_t sk_t, sk_bp, sk_peels, sk_round, sk_done, sk_nI, sk_nT;
+    int64_t sk_alive;
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
     int32_t phys;         // level the movers of the current insertion step sit at
@@ -2369,6 +2372,219 @@ __global__ void k_max_estimate(Dev d, int32_t v0, int32_t cnt) {
     if (threadIdx.x % kWave == 0 && best) atomicMax((unsigned long long *)&d.ctl->dv_bits, (unsigned long long)best);
 }
 
+// ---- static approximate k-core (the static section, Algorithm 6).  State:
+// C[v] (the count), B[v] (bucket; -1: no edges or peeled, -2: peeled in
+// the current round), stamp[v] (last round that touched v), cnt[b] (alive
+// vertices per bucket), pw[b] = (1+eps)^b by repeated double multiplication
+// on the host.  A round peels bucket bp, lowers the counts of the peeled
+// vertices' alive neighbours, re-buckets them, and picks the next bucket.
+struct SK {
+    int32_t *C, *B, *stamp, *cnt, *I, *T;
+    const double *pw;
+    double *est;
+    int32_t nbk, R;
+    double eps;
+};
+constexpr int kSkBuckets = 4096;   // most buckets (LDS histogram of a block)
+
+// least b with pw[b] >= c (c >= 1)
+__device__ __forceinline__ int32_t sk_bucket(const SK &k, int32_t c) {
+    int32_t lo = 0, hi = k.nbk - 1;
+    const double x = (double)c;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) / 2;
+        if (k.pw[mid] >= x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// flush a block's bucket-count changes (LDS histogram h, nbk entries)
+__device__ void sk_flush_hist(const SK &k, int32_t *h) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < k.nbk; b += blockDim.x)
+        if (h[b]) atomicAdd(&k.cnt[b], h[b]);
+}
+
+__global__ void k_sk_init(Dev d, SK k) {
+    extern __shared__ int32_t hist[];   // [nbk]
+    for (int b = threadIdx.x; b < k.nbk; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    int64_t alive = 0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) {
+        const int32_t dg = d.deg[v];
+        k.C[v] = dg;
+        k.stamp[v] = -1;
+        k.est[v] = 0.0;
+        int32_t b = -1;
+        if (dg > 0) {
+            b = sk_bucket(k, dg);
+            atomicAdd(&hist[b], 1);
+            alive++;
+        }
+        k.B[v] = b;
+    }
+    alive = wave_sum64(alive);
+    if (threadIdx.x % kWave == 0 && alive) atomicAdd((unsigned long long *)&d.ctl->sk_alive, (unsigned long long)alive);
+    sk_flush_hist(k, hist);
+}
+
+// The smallest non-empty bucket, or -1 (one block).
+__device__ int32_t sk_min_bucket(const SK &k, int32_t *red) {
+    int32_t best = INT32_MAX;
+    for (int b = threadIdx.x; b < k.nbk; b += blockDim.x)
+        if (k.cnt[b] > 0) best = min(best, b);
+    for (int o = kWave / 2; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, kWave));
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = best;
+    __syncthreads();
+    int32_t r = INT32_MAX;
+    for (int i = 0; i < (int)blockDim.x / kWave; i++) r = min(r, red[i]);
+    __syncthreads();
+    return r == INT32_MAX ? -1 : r;
+}
+
+// the first threshold (one block)
+__global__ void k_sk_first(Dev d, SK k) {
+    __shared__ int32_t red[kBlock / kWave];
+    Ctl *c = d.ctl;
+    const int32_t b = sk_min_bucket(k, red);
+    if (threadIdx.x == 0) {
+        c->sk_t = c->sk_bp = b;
+        c->sk_peels = 0;
+        c->sk_round = 0;
+        c->sk_nI = c->sk_nT = 0;
+        c->sk_done = b < 0 ? 1 : 0;
+    }
+}
+
+// Part 1 of a round: the alive vertices of bucket bp are peeled (estimate
+// (1+eps)^bp) and listed; the previous round's peeled vertices become dead.
+__global__ void k_sk_peel(Dev d, SK k) {
+    __shared__ Stage q;
+    const Ctl *c = d.ctl;
+    if (c->sk_done) return;
+    const int32_t bp = c->sk_bp;
+    const double e = k.pw[bp];
+    stage_init(q);
+    const int stride = gridDim.x * blockDim.x;
+    for (int vb = blockIdx.x * blockDim.x; vb < d.n; vb += stride) {
+        const int v = vb + threadIdx.x;
+        bool pe = false;
+        if (v < d.n) {
+            const int32_t b = k.B[v];
+            if (b == -2) k.B[v] = -1;
+            pe = b == bp;
+            if (pe) {
+                k.B[v] = -2;
+                k.est[v] = e;
+            }
+        }
+        stage_push(q, pe, v);
+        stage_flush(q, blockDim.x, k.I, &d.ctl->sk_nI, d.n, d.ctl);
+    }
+    stage_flush(q, kStage, k.I, &d.ctl->sk_nI, d.n, d.ctl);
+}
+
+// Part 2: every alive neighbour w of a peeled vertex loses one from C[w]
+// per peeled neighbour (r_w in all); the first touch in the round lists w.
+// A wavefront per peeled vertex; touched vertices staged per wavefront.
+__global__ void __launch_bounds__(kBlock) k_sk_relax(Dev d, SK k) {
+    __shared__ int32_t buf[kBlock / kWave][kFlipStage + kWave];
+    const Ctl *c = d.ctl;
+    if (c->sk_done) return;
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int32_t *b = buf[wv];
+    int32_t nb = 0;   // wave-uniform
+    auto flush = [&]() {
+        __threadfence_block();
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(&d.ctl->sk_nT, nb);
+        base = __shfl(base, 0, kWave);
+        for (int i = lane; i < nb; i += kWave)
+            if (base + i < d.n) k.T[base + i] = b[i];
+        if (lane == 0 && base + nb > d.n) latch(d.ctl, kErrLevel);
+        nb = 0;
+    };
+    const int32_t ni = c->sk_nI, round = c->sk_round;
+    const int nw = gridDim.x * blockDim.x / kWave;
+    for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < ni; i += nw) {
+        const int32_t u = k.I[i];
+        const int32_t cu = d.cap[u];
+        const int32_t *sl = d.pool + d.off[u];
+        for (int32_t e0 = 0; e0 < cu; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            const int32_t w = e < cu ? sl[e] : -1;
+            bool first = false;
+            if (w >= 0 && k.B[w] >= 0) {
+                atomicSub(&k.C[w], 1);
+                first = atomicExch(&k.stamp[w], round) != round;
+            }
+            const uint64_t m = __ballot(first);
+            if (first) b[nb + __popcll(m & ((1ull << lane) - 1))] = w;
+            nb += __popcll(m);
+            if (nb >= kFlipStage) flush();
+        }
+    }
+    if (nb) flush();
+}
+
+// Part 3: the touched vertices: C = max(C, ceil((1+eps)^(t-1))), bucket
+// max(b(C), t); bucket counts moved through an LDS histogram per block.
+__global__ void k_sk_fix(Dev d, SK k) {
+    extern __shared__ int32_t hist[];   // [nbk]
+    const Ctl *c = d.ctl;
+    if (c->sk_done) return;
+    for (int b = threadIdx.x; b < k.nbk; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int32_t t = c->sk_t, nt = min(c->sk_nT, d.n);
+    const int32_t floor_t = t >= 1 ? (int32_t)ceil(k.pw[t - 1]) : 1;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
+        const int32_t w = k.T[i];
+        const int32_t ob = k.B[w];
+        const int32_t cw = max(k.C[w], floor_t);
+        k.C[w] = cw;
+        const int32_t nb = max(sk_bucket(k, cw), t);
+        if (nb != ob) {
+            k.B[w] = nb;
+            atomicSub(&hist[ob], 1);
+            atomicAdd(&hist[nb], 1);
+        }
+    }
+    sk_flush_hist(k, hist);
+}
+
+// Part 4 (one block): the round's bookkeeping and the next bucket to peel:
+// the smallest non-empty one, in the same threshold while it is within
+// (2+eps)(1+eps)^t and fewer than R peels were made at t, else as the next
+// threshold.
+__global__ void k_sk_next(Dev d, SK k) {
+    __shared__ int32_t red[kBlock / kWave];
+    Ctl *c = d.ctl;
+    if (c->sk_done) return;
+    const int32_t bp = c->sk_bp, t = c->sk_t, ni = c->sk_nI;
+    __syncthreads();
+    if (threadIdx.x == 0) k.cnt[bp] -= ni;   // the peeled vertices (vertices re-bucketed to bp stay)
+    __syncthreads();
+    const int32_t nb = sk_min_bucket(k, red);
+    if (threadIdx.x == 0) {
+        c->sk_alive -= ni;
+        c->sk_peels += 1;
+        c->sk_round += 1;
+        c->sk_nI = 0;
+        c->sk_nT = 0;
+        if (nb < 0 || c->sk_alive <= 0) {
+            c->sk_done = 1;
+        } else if (c->sk_peels < k.R && k.pw[nb] <= (2.0 + k.eps) * k.pw[t]) {
+            c->sk_bp = nb;
+        } else {
+            c->sk_t = c->sk_bp = nb;
+            c->sk_peels = 0;
+        }
+    }
+}
+
 __global__ void k_check(Dev d, int32_t *bad) {
     int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     int nw = gridDim.x * blockDim.x / kWave;
@@ -2622,6 +2838,9 @@ struct plds {
     int64_t del_steps_hint = 0;   // steps of the last deletion sweep
     // orientation tracking: the last update call's starting levels and its
     // applied updates (pairs (min, max))
+    // static approximate k-core scratch (allocated on first use)
+    int32_t *sk_C = nullptr, *sk_B = nullptr, *sk_stamp = nullptr, *sk_cnt = nullptr;
+    double *sk_pw = nullptr;
     bool track = false;
     bool tracked_call = false;
     int32_t *t_ins = nullptr, *t_del = nullptr;
@@ -2705,6 +2924,7 @@ void free_all(plds *h) {
     dfree(d.lvb_start), dfree(d.lvb_fill), dfree(d.lvb), dfree(d.cl), dfree(d.sl0), dfree(d.sl1), dfree(d.cw);
     dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
     dfree(d.prevlvl), dfree(h->t_ins), dfree(h->t_del);
+    dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_stamp), dfree(h->sk_cnt), dfree(h->sk_pw);
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
     if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
     h->ins_exec = nullptr;
@@ -3655,6 +3875,65 @@ int plds_densest_value(plds_t *h, int32_t graph, double *out, void *stream) {
     bits = h->h_ctl->dv_bits;
     memcpy(out, &bits, sizeof(double));
     return PLDS_OK;
+}
+
+int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!est_out || !(eps > 0) || !std::isfinite(eps) || h->d.ng != 1) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    Dev &d = h->d;
+    // (1+eps)^b by repeated multiplication, up to the first power >= n (>= any degree + 1)
+    std::vector<double> pw(1, 1.0);
+    while (pw.back() < (double)h->n) {
+        if ((int)pw.size() >= kSkBuckets) return PLDS_EINVAL;   // eps too small for the bucket table
+        pw.push_back(pw.back() * (1.0 + eps));
+    }
+    pw.push_back(pw.back() * (1.0 + eps));
+    if ((int)pw.size() > kSkBuckets) return PLDS_EINVAL;
+    // peels per threshold: ceil(log_{1+delta} n), delta = 2/eps
+    int32_t R = 0;
+    for (double x = 1.0; x < (double)h->n; x *= 1.0 + 2.0 / eps) R++;
+    if (!h->sk_C) {
+        if (dalloc(&h->sk_C, h->n) || dalloc(&h->sk_B, h->n) || dalloc(&h->sk_stamp, h->n) ||
+            dalloc(&h->sk_cnt, kSkBuckets) || dalloc(&h->sk_pw, kSkBuckets)) {
+            dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_stamp), dfree(h->sk_cnt), dfree(h->sk_pw);
+            h->sk_C = nullptr;
+            return PLDS_ENOMEM;
+        }
+    }
+    SK k{h->sk_C, h->sk_B, h->sk_stamp, h->sk_cnt, d.mv, d.mv1, h->sk_pw, est_out, (int32_t)pw.size(), R, eps};
+    HIPCHK(hipMemcpyAsync(h->sk_pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(h->sk_cnt, 0, kSkBuckets * sizeof(int32_t), s));
+    h->h_ctl->sk_alive = 0;
+    HIPCHK(hipMemcpyAsync(&d.ctl->sk_alive, &h->h_ctl->sk_alive, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const size_t hist = (size_t)k.nbk * sizeof(int32_t);
+    hipLaunchKernelGGL(k_sk_init, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
+    hipLaunchKernelGGL(k_sk_first, dim3(1), dim3(kBlock), 0, s, d, k);
+    HIPCHK(hipGetLastError());
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    int run = 8;
+    int64_t rounds = 0;
+    while (!h->h_ctl->sk_done && !h->h_ctl->err) {
+        if (rounds > h->n + 1) {   // every round peels at least one vertex
+            h->broken = true;
+            return PLDS_ESTATE;
+        }
+        for (int i = 0; i < run; i++) {
+            hipLaunchKernelGGL(k_sk_peel, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, k);
+            hipLaunchKernelGGL(k_sk_relax, dim3(grid_for((int64_t)h->n * kWave, kBlock, 2048)), dim3(kBlock), 0, s,
+                               d, k);
+            hipLaunchKernelGGL(k_sk_fix, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
+            hipLaunchKernelGGL(k_sk_next, dim3(1), dim3(kBlock), 0, s, d, k);
+        }
+        rounds += run;
+        HIPCHK(hipGetLastError());
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+        run = std::min(run * 2, 256);
+    }
+    return check_err(h);
 }
 
 int plds_levels(plds_t *h, int32_t *out, void *stream) {

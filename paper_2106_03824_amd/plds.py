@@ -81,6 +81,7 @@ def lib():
         L.plds_oriented_updates.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64), _VP, _I64, ctypes.POINTER(_I64),
                                             _VP]
         L.plds_densest_value.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP]
+        L.plds_static_kcore.argtypes = [_VP, ctypes.c_double, _VP, _VP]
         L.plds_strerror.restype = ctypes.c_char_p
         L.plds_strerror.argtypes = [ctypes.c_int]
         _lib = L
@@ -91,7 +92,8 @@ EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi",
            "plds_graph_info", "plds_update", "plds_batch_insert",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
            "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror",
-           "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value")
+           "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value",
+           "plds_static_kcore")
 
 
 def strerror(code):
@@ -241,6 +243,10 @@ def plds_densest_value(h, graph=0, stream=None):
     out = ctypes.c_double()
     _chk(lib().plds_densest_value(h, int(graph), ctypes.byref(out), _stream(stream)), "plds_densest_value")
     return out.value
+
+
+def plds_static_kcore(h, eps, out, stream=None):
+    return _chk(lib().plds_static_kcore(h, float(eps), _ptr(out), _stream(stream)), "plds_static_kcore")
 
 
 def plds_levels(h, out, stream=None):
@@ -422,6 +428,13 @@ class PLDS:
 
     def densest_value(self, graph=0):
         return plds_densest_value(self.h, graph)
+
+    def static_kcore(self, eps):
+        """Algorithm 6's estimates of the current graph: device float64 [n]."""
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        plds_static_kcore(self.h, eps, out)
+        return out
 
 
 class MultiPLDS(PLDS):
