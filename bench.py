@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--static", action="store_true",
                     help="the static approximate k-core (Algorithm 6) of the RMAT-20 graph after the build")
     ap.add_argument("--static-eps", type=float, nargs="+", default=[0.5, 1.0, 0.1])
+    ap.add_argument("--vertex", action="store_true",
+                    help="vertex deletions (1e4 vertices per batch) and a renumbering rebuild on the RMAT-20 graph")
     ap.add_argument("--orient", action="store_true",
                     help="the RMAT-20 stream with the orientation outputs (flips F, oriented updates J) per batch")
     ap.add_argument("--serve-graphs", type=int, default=64)
@@ -198,6 +200,8 @@ def main():
         return run_orient(args, P, W, torch, np)
     if args.static:
         return run_static(args, P, W, torch, np)
+    if args.vertex:
+        return run_vertex(args, P, W, torch, np)
     if args.scale != 20:
         return run_stream(args, P, W, torch, np)
     scale, B = args.scale, args.batch
@@ -479,6 +483,61 @@ def run_batched(args, P, W, torch, np):
         "per_graph_loop": {"value": u_loop / t_loop, "ms": t_loop * 1e3},
         "speedup_vs_loop": t_loop / t_fused,
         "identical_levels": same, "updates": u_fused, "sweeps": s["sweeps_ins"] + s["sweeps_del"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_vertex(args, P, W, torch, np):
+    """Vertex updates on the RMAT-20 graph of the default run (after its build):
+    batches of 1e4 uniform random vertex deletions (each a batch of its edges'
+    deletions), then a rebuild that renumbers the vertices left with edges
+    consecutively.  `value` is deleted edges per second over the timed
+    vertex-deletion batches."""
+    scale = 20
+    m0 = 16 * 2 ** scale
+    dev = torch.device("cuda", 0)
+    st = W.RmatStream(scale, m0, seed=1, build_batches=16, cfg=2)
+    n = st.n
+    g = P.PLDS(n, 0.4, 3.0, 0, 2 * m0)
+    for b in st.build:
+        P.plds_batch_insert(g.h, torch.from_numpy(np.ascontiguousarray(b)).to(dev))
+    rng = np.random.default_rng(4100)
+    batches = [torch.from_numpy(rng.integers(0, n, 10 ** 4).astype(np.int32)).to(dev)
+               for _ in range(args.warmup + args.steps)]
+    torch.cuda.synchronize()
+    edges, secs = 0, 0.0
+    for i, vs in enumerate(batches):
+        m_before = g.info()["m"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.plds_delete_vertices(g.h, vs)
+        dt = time.perf_counter() - t0
+        k = m_before - g.info()["m"]
+        log(f"vertex batch {i}: 1e4 vertices, {k} edges deleted in {dt * 1e3:.2f} ms")
+        if i >= args.warmup:
+            edges += k
+            secs += dt
+    deg = g.degrees()
+    keep = deg > 0
+    relabel = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    n2 = int(keep.sum().item())
+    relabel[keep] = torch.arange(n2, dtype=torch.int32, device=dev)
+    m_now = g.info()["m"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g2 = g.rebuild(n2, relabel)
+    torch.cuda.synchronize()
+    t_rb = time.perf_counter() - t0
+    ok = g2.check() == 0 and g2.info()["m"] == m_now
+    log(f"rebuild: {n2} vertices, {m_now} edges in {t_rb * 1e3:.1f} ms, invariants {ok}")
+    out = {
+        "metric": "vertex deletions: deleted edges/s", "value": edges / secs, "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"rmat{scale}-ef16-delete-1e4-vertices-then-rebuild", "n": n, "delta": 0.4,
+                   "lambda": 3.0},
+        "rebuild": {"vertices": n2, "edges": m_now, "ms": t_rb * 1e3, "edges_per_s": m_now / t_rb,
+                    "invariants_hold": ok},
     }
     print(json.dumps(out), flush=True)
 

@@ -212,6 +212,29 @@ int plds_densest_value(plds_t *h, int32_t graph, double *out, void *stream);
  * exceed 4096 buckets).  Returns after the work on `stream` is complete. */
 int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream);
 
+/* Vertex updates (section on vertex insertions and deletions).
+ *
+ * plds_delete_vertices: every edge incident to one of the `count` vertices of
+ * the device int32 list `vertices` is deleted as one batch of edge deletions
+ * (Algorithm 3); the vertices stay, without edges, at level 0.  Listing a
+ * vertex twice, or both ends of an edge, deletes the edge once.  An id
+ * outside [0, n) rejects the call with PLDS_ERANGE before anything changes.
+ * Statistics as plds_update.  Returns after the work on `stream` is
+ * complete.
+ *
+ * plds_rebuild: a new plain handle (*out, owned by the caller) with new_n
+ * vertices, the same delta, lambda and levels-per-group rule, holding the
+ * graph of `h`, rebuilt from scratch by one batch of insertions of all its
+ * edges (Algorithm 2).  Without `relabel`, new_n >= n and ids are kept (new
+ * vertices join at level 0: vertex insertion past n).  With `relabel`
+ * (device int32 [n]: the new id of each vertex, or -1 to drop it with its
+ * edges), ids are renumbered; a new id outside [0, new_n) fails with
+ * PLDS_ERANGE.  The level structure follows new_n (4 ceil(log_{1+delta}
+ * new_n) levels per group by default).  `h` is unchanged.  Plain handles
+ * only.  Returns after the work on `stream` is complete. */
+int plds_delete_vertices(plds_t *h, const int32_t *vertices, int64_t count, void *stream);
+int plds_rebuild(plds_t *h, int64_t new_n, const int32_t *relabel, plds_t **out, void *stream);
+
 /* Current level of every vertex: device int32 [n]. */
 int plds_levels(plds_t *h, int32_t *out, void *stream);
 /* Current degree of every vertex: device int32 [n]. */

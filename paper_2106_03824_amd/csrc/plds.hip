@@ -115,6 +115,8 @@ struct Ctl {
     // static approximate k-core (Algorithm 6)
     int32_t sk_t, sk_bp, sk_peels, sk_round, sk_done, sk_nI, sk_nT;
     int64_t sk_alive;
+    // vertex deletion: incident edges counted, then gathered
+    int64_t vd_deg, vd_n;
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
     int32_t phys;         // level the movers of the current insertion step sit at
@@ -2585,6 +2587,64 @@ __global__ void k_sk_next(Dev d, SK k) {
     }
 }
 
+// ---- vertex updates (the section on vertex insertions and deletions).
+// Degrees of the listed vertices, summed (ids out of range latch an error).
+__global__ void k_vd_deg(Dev d, const int32_t *vs, int64_t cnt) {
+    int64_t sum = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += stride) {
+        const int32_t v = vs[i];
+        if (v < 0 || v >= d.n) {
+            latch(d.ctl, kErrRange);
+            continue;
+        }
+        sum += d.deg[v];
+    }
+    sum = wave_sum64(sum);
+    if (threadIdx.x % kWave == 0 && sum) atomicAdd((unsigned long long *)&d.ctl->vd_deg, (unsigned long long)sum);
+}
+
+// Every edge of the listed vertices as a pair (v, w), a wavefront per vertex;
+// each wavefront appends a slab's 64 slots with one atomic.
+__global__ void k_vd_gather(Dev d, const int32_t *vs, int64_t cnt, int32_t *out, int64_t cap) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < cnt; i += nw) {
+        const int32_t v = vs[i];
+        const int32_t cv = d.cap[v];
+        const int32_t *sl = d.pool + d.off[v];
+        for (int32_t e0 = 0; e0 < cv; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            const int32_t w = e < cv ? sl[e] : -1;
+            const uint64_t m = __ballot(w >= 0);
+            unsigned long long base = 0;
+            if (lane == 0 && m) base = atomicAdd((unsigned long long *)&d.ctl->vd_n, (unsigned long long)__popcll(m));
+            base = __shfl(base, 0, kWave);
+            const int64_t at = (int64_t)base + __popcll(m & ((1ull << lane) - 1));
+            if (w >= 0) {
+                if (at < cap) {
+                    out[2 * at] = v;
+                    out[2 * at + 1] = w;
+                } else {
+                    latch(d.ctl, kErrLevel);
+                }
+            }
+        }
+    }
+}
+
+// A rebuild's edge list through the renumbering: an edge with a dropped end
+// (new id < 0) becomes the self-loop (0, 0), which the batch drops.
+__global__ void k_relabel(int32_t *e, int64_t m, const int32_t *relabel) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += stride) {
+        const int32_t a = relabel[e[2 * i]], b = relabel[e[2 * i + 1]];
+        const bool keep = a >= 0 && b >= 0;
+        e[2 * i] = keep ? a : 0;
+        e[2 * i + 1] = keep ? b : 0;
+    }
+}
+
 __global__ void k_check(Dev d, int32_t *bad) {
     int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     int nw = gridDim.x * blockDim.x / kWave;
@@ -2838,6 +2898,9 @@ struct plds {
     int64_t del_steps_hint = 0;   // steps of the last deletion sweep
     // orientation tracking: the last update call's starting levels and its
     // applied updates (pairs (min, max))
+    int32_t lpg = 0;              // levels_per_group as given at create
+    int32_t *vd_buf = nullptr;    // incident edges of deleted vertices
+    int64_t vd_cap = 0;
     // static approximate k-core scratch (allocated on first use)
     int32_t *sk_C = nullptr, *sk_B = nullptr, *sk_stamp = nullptr, *sk_cnt = nullptr;
     double *sk_pw = nullptr;
@@ -2925,6 +2988,7 @@ void free_all(plds *h) {
     dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
     dfree(d.prevlvl), dfree(h->t_ins), dfree(h->t_del);
     dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_stamp), dfree(h->sk_cnt), dfree(h->sk_pw);
+    dfree(h->vd_buf);
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
     if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
     h->ins_exec = nullptr;
@@ -3487,6 +3551,7 @@ int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double l
     h->n = n;
     h->delta = delta;
     h->lambda = lambda;
+    h->lpg = levels_per_group;
     for (int32_t g = 0, b = 0; g < ngraphs; b += (int32_t)ns[g], g++) {
         h->gbase.push_back(b);
         h->gn.push_back(ns[g]);
@@ -3898,6 +3963,7 @@ int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
         if (dalloc(&h->sk_C, h->n) || dalloc(&h->sk_B, h->n) || dalloc(&h->sk_stamp, h->n) ||
             dalloc(&h->sk_cnt, kSkBuckets) || dalloc(&h->sk_pw, kSkBuckets)) {
             dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_stamp), dfree(h->sk_cnt), dfree(h->sk_pw);
+    dfree(h->vd_buf);
             h->sk_C = nullptr;
             return PLDS_ENOMEM;
         }
@@ -3934,6 +4000,79 @@ int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
         run = std::min(run * 2, 256);
     }
     return check_err(h);
+}
+
+int plds_delete_vertices(plds_t *h, const int32_t *vertices, int64_t count, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (count < 0 || (count && !vertices)) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    Dev &d = h->d;
+    if (count == 0) return plds_update(h, nullptr, 0, nullptr, 0, stream);
+    h->h_ctl->err = 0;
+    h->h_ctl->vd_deg = h->h_ctl->vd_n = 0;
+    HIPCHK(hipMemcpyAsync(&d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(&d.ctl->vd_deg, &h->h_ctl->vd_deg, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_vd_deg, dim3(grid_for(count, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, vertices, count);
+    HIPCHK(hipGetLastError());
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    if (h->h_ctl->err & kErrRange) {
+        h->h_ctl->err = 0;
+        HIPCHK(hipMemcpyAsync(&d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return PLDS_ERANGE;
+    }
+    const int64_t k = h->h_ctl->vd_deg;
+    if ((uint64_t)k > (uint64_t)INT32_MAX / 2) return PLDS_EINVAL;
+    if (k > h->vd_cap) {
+        dfree(h->vd_buf);
+        h->vd_cap = 0;
+        if (dalloc(&h->vd_buf, 2 * k)) return PLDS_ENOMEM;
+        h->vd_cap = k;
+    }
+    if (k) {
+        hipLaunchKernelGGL(k_vd_gather, dim3(grid_for(count * kWave, kBlock, 2048)), dim3(kBlock), 0, s, d, vertices,
+                           count, h->vd_buf, k);
+        HIPCHK(hipGetLastError());
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+        if (h->h_ctl->vd_n != k) return PLDS_ESTATE;
+    }
+    // one batch of edge deletions (duplicates, from vertices listed twice or
+    // edges between two listed vertices, collapse)
+    return plds_update(h, nullptr, 0, h->vd_buf, k, stream);
+}
+
+int plds_rebuild(plds_t *h, int64_t new_n, const int32_t *relabel, plds_t **out, void *stream) {
+    if (!out) return PLDS_EINVAL;
+    *out = nullptr;
+    int rc = guard(h);
+    if (rc) return rc;
+    if (h->d.ng != 1 || new_n < 1 || new_n > INT32_MAX || (!relabel && new_n < h->n)) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    int32_t *e = nullptr;
+    const int64_t m = h->m;
+    if (m && dalloc(&e, 2 * m)) return PLDS_ENOMEM;
+    int64_t got = 0;
+    rc = m ? plds_dump_state(h, e, m, &got, nullptr, stream) : PLDS_OK;
+    if (!rc && m && relabel) {
+        hipLaunchKernelGGL(k_relabel, dim3(grid_for(m)), dim3(kBlock), 0, s, e, m, relabel);
+        if (hipGetLastError() != hipSuccess) rc = PLDS_EHIP;
+    }
+    plds_t *nh = nullptr;
+    if (!rc) rc = plds_create_multi(1, &new_n, h->delta, h->lambda, h->lpg, 2 * m, &nh);
+    if (!rc) {
+        nh->sweep_mode = h->sweep_mode;
+        if (m) rc = plds_update(nh, e, m, nullptr, 0, stream);   // Algorithm 2 on every edge
+    }
+    dfree(e);
+    if (rc) {
+        if (nh) plds_destroy(nh);
+        return rc;
+    }
+    *out = nh;
+    return PLDS_OK;
 }
 
 int plds_levels(plds_t *h, int32_t *out, void *stream) {

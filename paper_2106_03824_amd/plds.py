@@ -82,6 +82,8 @@ def lib():
                                             _VP]
         L.plds_densest_value.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP]
         L.plds_static_kcore.argtypes = [_VP, ctypes.c_double, _VP, _VP]
+        L.plds_delete_vertices.argtypes = [_VP, _VP, _I64, _VP]
+        L.plds_rebuild.argtypes = [_VP, _I64, _VP, ctypes.POINTER(_VP), _VP]
         L.plds_strerror.restype = ctypes.c_char_p
         L.plds_strerror.argtypes = [ctypes.c_int]
         _lib = L
@@ -93,7 +95,7 @@ EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
            "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror",
            "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value",
-           "plds_static_kcore")
+           "plds_static_kcore", "plds_delete_vertices", "plds_rebuild")
 
 
 def strerror(code):
@@ -247,6 +249,19 @@ def plds_densest_value(h, graph=0, stream=None):
 
 def plds_static_kcore(h, eps, out, stream=None):
     return _chk(lib().plds_static_kcore(h, float(eps), _ptr(out), _stream(stream)), "plds_static_kcore")
+
+
+def plds_delete_vertices(h, vertices, stream=None, check=True):
+    cnt = 0 if vertices is None else int(vertices.numel())
+    rc = lib().plds_delete_vertices(h, _ptr(vertices), cnt, _stream(stream))
+    return _chk(rc, "plds_delete_vertices") if check else rc
+
+
+def plds_rebuild(h, new_n, relabel=None, stream=None):
+    """Returns the new handle."""
+    out = _VP()
+    _chk(lib().plds_rebuild(h, int(new_n), _ptr(relabel), ctypes.byref(out), _stream(stream)), "plds_rebuild")
+    return out.value
 
 
 def plds_levels(h, out, stream=None):
@@ -428,6 +443,17 @@ class PLDS:
 
     def densest_value(self, graph=0):
         return plds_densest_value(self.h, graph)
+
+    def delete_vertices(self, vertices, check=True):
+        import torch
+        v = torch.as_tensor(vertices, dtype=torch.int32).reshape(-1).to("cuda").contiguous()
+        return plds_delete_vertices(self.h, v, check=check)
+
+    def rebuild(self, new_n, relabel=None):
+        """A new PLDS holding this graph with new_n vertices (see plds_rebuild)."""
+        import torch
+        r = None if relabel is None else torch.as_tensor(relabel, dtype=torch.int32).to("cuda").contiguous()
+        return PLDS(new_n, _handle=plds_rebuild(self.h, new_n, r))
 
     def static_kcore(self, eps):
         """Algorithm 6's estimates of the current graph: device float64 [n]."""
