@@ -37,7 +37,12 @@ constexpr int kBlock = 256;          // threads per block of the sweep kernels
 constexpr int kWave = 64;            // CDNA wavefront
 constexpr int32_t kChunk = 256;      // slab slots per work item of a sweep
 constexpr int32_t kMinCap = 8;       // smallest slab, slots
-constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels
+constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels (most blocks of the insertion scan)
+// Insertion scan blocks per compute unit.  The scan fits 7 (about 20 KB of
+// LDS each); on the RMAT-20 stream 4 to 6 per unit measured best (1,024 to
+// 1,536 blocks within 1% of each other), 7 about 12% slower, 2,048 (more
+// than one resident round) 14% slower.
+constexpr int kScanPerCU = 5;
 constexpr int kDlGrid = 1024;        // blocks of the desire-level kernel
 constexpr int kListGrid = 256;       // blocks of the per-mover list kernels
 constexpr int kApplyGrid = 1024;     // most blocks of the batch-application kernels
@@ -1058,7 +1063,16 @@ __device__ bool ins_prep_phase(Dev &d, const InsStep &st, int p, int bid, int nb
 // stays marked and also gets the next step's flag, since it moves again.
 // The flag of this step stays on, so other scans never touch its counters.
 // Per-block statistics go to d.part[3*bid..] (stored, or added when accum).
-__device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, bool accum) {
+// The two LDS queues of a scan (its cascade or joiner appends, its
+// stoppers), declared once by the kernel and shared by the pull and the
+// climbing phases (a launch runs one of them), which keeps the scan's LDS
+// at about 20 KB per block: 7 blocks per compute unit.
+struct ScanQ {
+    Stage a;
+    StageT<int32_t, 1024> b;
+};
+
+__device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, bool accum, ScanQ &sq) {
     int32_t l = st.l, nxt = st.cur ^ 1, jump = st.jump;
     int32_t Mp = p ? kMover1 : kMover0, Mn = p ? kMover0 : kMover1;
     int32_t *casc = nxt ? d.casc1 : d.casc0;
@@ -1074,8 +1088,8 @@ __device__ void ins_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nb
     int32_t scanned = 0, nU = 0, n1 = 0;
     // pushes of one round: per wavefront up to kChunk neighbours plus 8 movers
     const int32_t room = wpb * (kChunk + kWave / 8);
-    __shared__ Stage q_casc;
-    __shared__ StageT<int32_t, 1024> q_stop;   // movers that stop at l+1 (residents of the next step)
+    Stage &q_casc = sq.a;
+    StageT<int32_t, 1024> &q_stop = sq.b;   // movers that stop at l+1 (residents of the next step)
     int32_t *slist = p ? d.sl1 : d.sl0;
     stage_init(q_casc);
     st_init(q_stop);
@@ -1456,9 +1470,9 @@ __device__ void exit_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, i
 
 // Part 2 of a climbing step: the work items of part 1, a wavefront each
 // (kCw slots).  Exit steps have none.
-__device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nblk) {
-    __shared__ Stage q_join;
-    __shared__ StageT<int32_t, 1024> q_stop;
+__device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int nblk, ScanQ &sq) {
+    Stage &q_join = sq.a;
+    StageT<int32_t, 1024> &q_stop = sq.b;
     __shared__ int64_t red[kBlock / kWave];
     Ctl *c = d.ctl;
     const bool climb = st.mode == kClimbStep;
@@ -1797,8 +1811,9 @@ __global__ void k_ins_scan(Dev d, int p) {
         }
         c->n_cl_snap = c->n_cl;
     }
-    if (st.mode == kPull) ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, true);
-    else climb_scan_phase(d, st, p, blockIdx.x, gridDim.x);
+    __shared__ ScanQ sq;
+    if (st.mode == kPull) ins_scan_phase(d, st, p, blockIdx.x, gridDim.x, true, sq);
+    else climb_scan_phase(d, st, p, blockIdx.x, gridDim.x, sq);
 }
 
 // Vertices with edges, bucketed by level at the start of an insertion sweep
@@ -1912,6 +1927,7 @@ __device__ bool grid_sync(Bar *b, unsigned nblk) {
 __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
     __shared__ int32_t sh[5 * (kBlock / kWave + 2)];
     __shared__ int32_t sh1[2];
+    __shared__ ScanQ sq;
     const int bid = blockIdx.x, nblk = gridDim.x;
     const bool writer = bid == 0 && threadIdx.x == 0;
     Ctl *c = d.ctl;
@@ -1943,7 +1959,7 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
             d.occ[prev.l + 1] += prev_nmv;
             occ_pending = false;
         }
-        ins_scan_phase(d, st, p, bid, nblk, true);
+        ins_scan_phase(d, st, p, bid, nblk, true, sq);
         if (!grid_sync(bar, nblk)) break;
         prev_nmv = c->nmvb[p];
         prev = st;
@@ -2886,6 +2902,7 @@ struct plds {
     // insertion sweep as one cooperative launch (0 blocks = not available)
     int sweep_mode = 1;          // 0: cooperative when possible, 1: one kernel per part
     int coop_blocks = -1;        // -1 = not yet determined
+    int scan_grid = kSweepGrid;  // blocks of the insertion scan: what the device holds at once
     Bar *bar = nullptr;
     // the insertion step sequence as a prebuilt graph of kGraphSteps steps
     hipGraph_t ins_graph = nullptr;
@@ -3274,7 +3291,7 @@ int ins_graph(plds *h) {
     struct K {
         const void *f;
         int grid;
-    } ks[2] = {{(const void *)k_ins_prep, kListGrid}, {(const void *)k_ins_scan, kSweepGrid}};
+    } ks[2] = {{(const void *)k_ins_prep, kListGrid}, {(const void *)k_ins_scan, h->scan_grid}};
     hipGraphNode_t prev = nullptr;
     for (int i = 0; i < kGraphSteps; i++) {
         for (int k = 0; k < 2; k++) {
@@ -3427,7 +3444,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
             for (int i = 0; i < run; i++) {      // run is even: every run starts at parity 0
                 int par = i & 1;
                 tlaunch(h, 4, k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d, par);
-                tlaunch(h, 1, k_ins_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d, par);
+                tlaunch(h, 1, k_ins_scan, dim3(h->scan_grid), dim3(kBlock), 0, s, d, par);
             }
             run = std::min(run * 2, 256);
         }
@@ -3436,7 +3453,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
         if (rc) return rc;
         take_timing(h, h->ev_used);
     }
-    hipLaunchKernelGGL(k_ins_totals, dim3(1), dim3(kBlock), 0, s, d, kSweepGrid);
+    hipLaunchKernelGGL(k_ins_totals, dim3(1), dim3(kBlock), 0, s, d, h->scan_grid);
     if (h->h_ctl->n_rc > 0)
         hipLaunchKernelGGL(k_ups_recount, dim3(grid_for((int64_t)h->h_ctl->n_rc * kWave, kBlock, 2048)),
                            dim3(kBlock), 0, s, d);
@@ -3559,6 +3576,15 @@ int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double l
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return PLDS_EHIP;
+    }
+    {   // scan blocks: at most one resident round (a scan launched with more
+        // blocks than the device holds at once runs its latency chain once
+        // per round of blocks), and at most kScanPerCU per compute unit
+        int per = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_ins_scan, kBlock, 0) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+            per > 0 && ncu > 0)
+            h->scan_grid = std::max(256, std::min(std::min(per, kScanPerCU) * ncu, kSweepGrid));
     }
     build_tables(h, levels_per_group);
     if ((int64_t)h->G * h->L >= (int64_t)kLevelMask) {   // levels must fit under the mover flags
