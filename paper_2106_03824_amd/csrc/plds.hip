@@ -122,6 +122,7 @@ struct Ctl {
     int64_t sk_alive;
     // vertex deletion: incident edges counted, then gathered
     int64_t vd_deg, vd_n;
+    int32_t viol_del0;    // the deletion sweep's first candidates (Invariant-2 violators)
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
     int32_t phys;         // level the movers of the current insertion step sit at
@@ -2113,7 +2114,10 @@ __global__ void k_del_next(Dev d, int mode) {
         c->n_rc = 0;
         c->step_id += 1;
     }
-    if (mode == 0) c->n_rc = 0;   // the candidates' list has been read
+    if (mode == 0) {
+        c->n_rc = 0;   // the candidates' list has been read
+        c->viol_del0 = c->p_n[c->cur];
+    }
     int32_t nm = c->nm;
     c->nm = kInf;
     if (nm == kInf) c->done = 1;
@@ -3391,11 +3395,18 @@ int insertion_sweep(plds *h, hipStream_t s) {
     hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, d);
     hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(nt, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d);
     HIPCHK(hipGetLastError());
-    int rc = sync_ctl(h, s);
-    if (rc) return rc;
-    h->stats.viol_ins0 = h->h_ctl->n_cand;
+    // After a sweep of many steps the next one is expected to have
+    // candidates too: the buckets and the first step graphs follow the
+    // seeding without a wait (the steps of a sweep without candidates return
+    // at once).  Otherwise, and for the cooperative or timed forms, wait.
+    const bool eager = h->sweep_mode != 0 && h->timed_kind != 1 && h->timed_kind != 4 && h->ins_steps_hint >= 32;
+    int rc = PLDS_OK;
+    if (!eager) {
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+    }
     HIPCHK(hipMemsetAsync(d.part, 0, 3 * kSweepGrid * sizeof(int64_t), s));
-    if (d.climb_ok && !h->h_ctl->done) {
+    if (d.climb_ok && (eager || !h->h_ctl->done)) {
         HIPCHK(hipMemsetAsync(d.lvb_fill, 0, (size_t)(h->K + 2) * sizeof(int32_t), s));
         size_t lds = (size_t)h->K * sizeof(int32_t);
         hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), lds, s, d);
@@ -3423,7 +3434,13 @@ int insertion_sweep(plds *h, hipStream_t s) {
     int64_t steps = 0;
     // a timed step kernel is launched directly, so that its events bracket the dispatch alone
     bool use_graph = h->timed_kind != 1 && h->timed_kind != 4;
-    int run = use_graph ? kGraphSteps : 8;
+    // launched one by one: a first run of 7/8 of the steps the last sweep
+    // took (even, so that every run starts at parity 0), then runs of 16,
+    // 32, ... (a step launched after the sweep's end still costs its launches
+    // on the host)
+    int run = use_graph ? kGraphSteps
+                        : (int)std::min<int64_t>(std::max<int64_t>((h->ins_steps_hint * 7 / 8) & ~1LL, 8), 256);
+    int next_run = 16;
     // before the first wait, issue about as many steps as the last sweep
     // took (rounded down to whole step graphs); steps issued after the
     // sweep's end return at once
@@ -3446,7 +3463,8 @@ int insertion_sweep(plds *h, hipStream_t s) {
                 tlaunch(h, 4, k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d, par);
                 tlaunch(h, 1, k_ins_scan, dim3(h->scan_grid), dim3(kBlock), 0, s, d, par);
             }
-            run = std::min(run * 2, 256);
+            run = next_run;
+            next_run = std::min(next_run * 2, 256);
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
@@ -3461,6 +3479,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
     rc = sync_ctl(h, s);
     if (rc) return rc;
     Ctl *c = h->h_ctl;
+    h->stats.viol_ins0 = c->n_cand;
     h->ins_steps_hint = c->n_steps + 1;   // the steps and the one that found the sweep done
     h->stats.sweeps_ins += c->sweeps;
     h->stats.moves_up += c->moves;
@@ -3480,14 +3499,18 @@ int deletion_sweep(plds *h, hipStream_t s) {
     tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 0);
     hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 0);
     HIPCHK(hipGetLastError());
-    int rc = sync_ctl(h, s);
-    if (rc) return rc;
-    take_timing(h, h->ev_used);
-    h->stats.viol_del0 = h->h_ctl->p_n[0];
-    // timed step kernels are launched one by one, in runs of 4, 8, ...; else
-    // the step graph, before the first wait as many times as the last sweep
-    // took steps (rounded down to whole graphs)
+    int rc;
+    // timed step kernels are launched one by one, in runs of 4, 8, ..., after
+    // a wait for the candidates; else the step graph follows at once (its
+    // steps return at once if there are no candidates), as many times before
+    // the first wait as the last sweep took steps (rounded down to whole
+    // graphs)
     const bool use_graph = h->timed_kind != 2 && h->timed_kind != 3;
+    if (!use_graph) {
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+        take_timing(h, h->ev_used);
+    }
     int run = 4;
     int64_t first = std::min<int64_t>(std::max<int64_t>(h->del_steps_hint / kDelGraphSteps, 1), 8);
     int64_t steps = 0;
@@ -3519,6 +3542,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
         run = std::min(run * 2, 128);
     }
     Ctl *c = h->h_ctl;
+    h->stats.viol_del0 = c->viol_del0;
     h->del_steps_hint = c->sweeps;
     h->stats.sweeps_del += c->sweeps;
     h->stats.moves_down += c->moves;
