@@ -68,6 +68,7 @@ class Oracle:
     mode 1 rescans every vertex at every level (slow cross-check)."""
 
     def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, mode=0):
+        self._destroy = lib().ora_destroy        # bound now: module globals may be gone at exit
         self._h = lib().ora_create(int(n), float(delta), float(lam), int(levels_per_group), int(mode))
         if not self._h:
             raise ValueError("ora_create rejected its arguments")
@@ -77,7 +78,7 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().ora_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def info(self):
