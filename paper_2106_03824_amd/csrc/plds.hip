@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <new>
 #include <vector>
 
@@ -114,7 +115,7 @@ struct Ctl {
     int32_t n_touch;      // distinct endpoints of those edges
     int32_t n_grow;       // slabs to regrow
     int32_t n_pieces;     // work items of the large regrown slabs
-    int32_t n_moved;      // vertices whose level the last update call changed
+    int32_t n_fl[4];      // moved vertices of the flip scan by slab size: 8, 16, up to kFlipHub, larger
     int64_t n_flip;       // flipped edges found
     uint64_t dv_bits;     // largest coreness estimate of a graph (bits of a non-negative double)
     // static approximate k-core (Algorithm 6)
@@ -188,6 +189,7 @@ struct Dev {
     int64_t cw_cap;
     // orientation tracking (allocated when switched on)
     int32_t *prevlvl;                 // [n] levels at the start of the last update call
+    int2 *lvp;                        // [n] (prevlvl, level) side by side, for the flip scan's gathers
 };
 
 // Levels per group and table offset of the graph that holds vertex v.
@@ -2273,18 +2275,51 @@ __global__ void k_orient(Dev d, const int32_t *e, int64_t cnt, const int32_t *lv
     }
 }
 
-// Vertices whose level differs from the call's starting level, into d.mv.
+// Both levels of every vertex side by side (d.lvp), so that the edge scan
+// gathers one 8-byte pair per neighbour instead of two 4-byte values from two
+// arrays; and the vertices whose level differs from the call's starting
+// level, sorted by
+// slab size for the edge scan: at most 8 slots (d.mv from the front), 16
+// (d.mv from the back), up to kFlipHub (d.mv1 from the front) and larger
+// (d.mv1 from the back).  The lists hold distinct vertices, so two lists
+// that share an array of n entries never meet.
+constexpr int32_t kFlipHub = 2048;
+constexpr int kFlipQ = 1024;
 __global__ void k_flip_moved(Dev d) {
-    __shared__ Stage q;
-    stage_init(q);
+    __shared__ StageT<int32_t, kFlipQ> q0, q1, q2, q3;
+    st_init(q0), st_init(q1), st_init(q2), st_init(q3);
+    int32_t *n = d.ctl->n_fl;
+    const int32_t nn = d.n;
+    int32_t *mv = d.mv, *mv1 = d.mv1;
+    auto w0 = [=](int32_t i, int32_t x) { mv[i] = x; };
+    auto w1 = [=](int32_t i, int32_t x) { mv[nn - 1 - i] = x; };
+    auto w2 = [=](int32_t i, int32_t x) { mv1[i] = x; };
+    auto w3 = [=](int32_t i, int32_t x) { mv1[nn - 1 - i] = x; };
     const int stride = gridDim.x * blockDim.x;
-    for (int vb = blockIdx.x * blockDim.x; vb < d.n; vb += stride) {
+    for (int vb = blockIdx.x * blockDim.x; vb < nn; vb += stride) {
         const int v = vb + threadIdx.x;
-        const bool mv = v < d.n && d.level[v] != d.prevlvl[v];
-        stage_push(q, mv, v);
-        stage_flush(q, blockDim.x, d.mv, &d.ctl->n_moved, d.n, d.ctl);
+        int cls = -1;
+        if (v < nn) {
+            const int32_t l0 = d.prevlvl[v], l1 = d.level[v];
+            d.lvp[v] = make_int2(l0, l1);
+            if (l0 != l1) {
+                const int32_t c = d.cap[v];
+                cls = c <= 8 ? 0 : c <= 16 ? 1 : c <= kFlipHub ? 2 : 3;
+            }
+        }
+        st_push(q0, cls == 0, v);
+        st_push(q1, cls == 1, v);
+        st_push(q2, cls == 2, v);
+        st_push(q3, cls == 3, v);
+        st_flush(q0, blockDim.x, &n[0], nn, d.ctl, w0);
+        st_flush(q1, blockDim.x, &n[1], nn, d.ctl, w1);
+        st_flush(q2, blockDim.x, &n[2], nn, d.ctl, w2);
+        st_flush(q3, blockDim.x, &n[3], nn, d.ctl, w3);
     }
-    stage_flush(q, kStage, d.mv, &d.ctl->n_moved, d.n, d.ctl);
+    st_flush(q0, kFlipQ, &n[0], nn, d.ctl, w0);
+    st_flush(q1, kFlipQ, &n[1], nn, d.ctl, w1);
+    st_flush(q2, kFlipQ, &n[2], nn, d.ctl, w2);
+    st_flush(q3, kFlipQ, &n[3], nn, d.ctl, w3);
 }
 
 // The call's applied insertions into the batch hash set (empty before).
@@ -2318,10 +2353,15 @@ __device__ __forceinline__ bool flip_was_inserted(const Dev &d, uint64_t key) {
 // the current levels is a flip, reported as it was.  An edge with both
 // endpoints moved is reported by its smaller endpoint; edges the call
 // inserted (in the hash set when with_ins) had no orientation before.
-// A wavefront searches one vertex's slab at a time.  Each wavefront stages
+// The work is spread by slab size, so that many searches are in flight per
+// wavefront: slabs of more than kFlipHub slots are cut into chunks of 256
+// slots dealt out over all wavefronts; a wavefront searches a slab of up
+// to kFlipHub slots 256 at a time; lane groups of 16 and 8 search the
+// smallest slabs, 4 and 8 vertices per wavefront.  Each wavefront stages
 // its flips in LDS and appends them with one atomic per 256; positions at
 // or beyond cap are counted, not written.
 constexpr int kFlipStage = 256;
+constexpr int kFlipChunk = 4;   // 64-slot pieces per wavefront pass
 __global__ void __launch_bounds__(kBlock) k_flip_scan(Dev d, int with_ins, int32_t *out, int64_t cap) {
     __shared__ int32_t buf[kBlock / kWave][2 * (kFlipStage + kWave)];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -2336,13 +2376,13 @@ __global__ void __launch_bounds__(kBlock) k_flip_scan(Dev d, int with_ins, int32
             if ((int64_t)base + i / 2 < cap) out[2 * base + i] = b[i];
         nb = 0;
     };
-    // one searched slot: stage the edge (u, w) if it flipped (every lane of
-    // the wavefront calls it together)
-    auto slot = [&](int32_t u, int32_t lu0, int32_t lu1, int32_t w) {
+    // one searched slot (w < 0: none) with the levels of both ends gathered;
+    // stages the edge (u, w) if it flipped (every lane of the wavefront
+    // calls it together)
+    auto slot = [&](int32_t u, int32_t lu0, int32_t lu1, int32_t w, int32_t lw0, int32_t lw1) {
         bool f = false;
         int32_t t = 0, hd = 0;
         if (w >= 0) {
-            const int32_t lw0 = d.prevlvl[w], lw1 = d.level[w];
             const bool b0 = points_up(u, w, lu0, lw0), b1 = points_up(u, w, lu1, lw1);
             const int32_t lo = min(u, w), hi = max(u, w);
             f = b0 != b1 && (lw0 == lw1 || u < w);
@@ -2359,19 +2399,98 @@ __global__ void __launch_bounds__(kBlock) k_flip_scan(Dev d, int with_ins, int32
         nb += __popcll(m);
         if (nb >= kFlipStage) flush();
     };
+    // 256 slots of u's slab from slot e0: all loads first, then the decisions
+    auto chunk = [&](int32_t u, int32_t lu0, int32_t lu1, const int32_t *sl, int32_t cu, int32_t e0) {
+        int32_t w[kFlipChunk], lw0[kFlipChunk], lw1[kFlipChunk];
+#pragma unroll
+        for (int k = 0; k < kFlipChunk; k++) {
+            const int32_t e = e0 + k * kWave + lane;
+            w[k] = e < cu ? sl[e] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kFlipChunk; k++) {
+            const int2 x = w[k] >= 0 ? d.lvp[w[k]] : make_int2(0, 0);
+            lw0[k] = x.x;
+            lw1[k] = x.y;
+        }
+#pragma unroll
+        for (int k = 0; k < kFlipChunk; k++) slot(u, lu0, lu1, w[k], lw0[k], lw1[k]);
+    };
     const int nw = gridDim.x * blockDim.x / kWave;
     const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int32_t nm = d.ctl->n_moved;
-    for (int i = wid; i < nm; i += nw) {
-        const int32_t u = d.mv[i];
-        const int32_t lu0 = d.prevlvl[u], lu1 = d.level[u];
-        const int32_t cap_u = d.cap[u];
-        const int32_t *sl = d.pool + d.off[u];
-        for (int32_t e0 = 0; e0 < cap_u; e0 += kWave) {
-            const int32_t e = e0 + lane;
-            slot(u, lu0, lu1, e < cap_u ? sl[e] : -1);
+    const int32_t n8 = d.ctl->n_fl[0], n16 = d.ctl->n_fl[1], nmid = d.ctl->n_fl[2], nhub = d.ctl->n_fl[3];
+    const int32_t nn = d.n;
+    // the largest slabs: 256-slot chunks numbered across the hubs, 64 hubs
+    // at a time (a lane loads one hub's header); a wavefront takes the
+    // chunks whose number is its own modulo the number of wavefronts
+    int64_t before = 0;
+    for (int32_t hb = 0; hb < nhub; hb += kWave) {
+        int32_t hu = -1, h0 = 0, h1 = 0, hc = 0;
+        int64_t ho = 0;
+        if (hb + lane < nhub) {
+            hu = d.mv1[nn - 1 - (hb + lane)];
+            const int2 x = d.lvp[hu];
+            h0 = x.x;
+            h1 = x.y;
+            hc = d.cap[hu];
+            ho = d.off[hu];
         }
+        const int32_t nch = (hc + kFlipChunk * kWave - 1) / (kFlipChunk * kWave);
+        int32_t tot;
+        const int32_t ex = wave_excl(nch, &tot);
+        for (int64_t f = before + ((wid - before) % nw + nw) % nw; f < before + tot; f += nw) {
+            const int32_t r = (int32_t)(f - before);
+            const int j = __popcll(__ballot(ex + nch <= r));   // the hub holding chunk r
+            const int32_t u = __shfl(hu, j, kWave), lu0 = __shfl(h0, j, kWave), lu1 = __shfl(h1, j, kWave);
+            const int32_t cu = __shfl(hc, j, kWave), e0 = (r - __shfl(ex, j, kWave)) * kFlipChunk * kWave;
+            const int64_t o = __shfl(ho, j, kWave);
+            chunk(u, lu0, lu1, d.pool + o, cu, e0);
+        }
+        before += tot;
     }
+    // slabs of 17..kFlipHub slots: a wavefront each
+    for (int32_t i = wid; i < nmid; i += nw) {
+        const int32_t u = d.mv1[i];
+        const int2 x = d.lvp[u];
+        const int32_t lu0 = x.x, lu1 = x.y, cu = d.cap[u];
+        const int32_t *sl = d.pool + d.off[u];
+        for (int32_t e0 = 0; e0 < cu; e0 += kFlipChunk * kWave) chunk(u, lu0, lu1, sl, cu, e0);
+    }
+    // the smallest slabs: lane groups of G lanes, a vertex each, two passes
+    // of the grid in flight
+    auto groups = [&](auto G, int32_t cnt, bool from_back) {
+        constexpr int per = kWave / decltype(G)::value;
+        const int gi = lane / decltype(G)::value, gl = lane % decltype(G)::value;
+        for (int32_t base = wid * per; base < cnt; base += 2 * nw * per) {
+            int32_t u[2], lu0[2], lu1[2], w[2], lw0[2], lw1[2];
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int32_t i = base + k * nw * per + gi;
+                u[k] = i < cnt ? (from_back ? d.mv[nn - 1 - i] : d.mv[i]) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                lu0[k] = lu1[k] = 0;
+                w[k] = -1;
+                if (u[k] >= 0) {
+                    const int2 x = d.lvp[u[k]];
+                    lu0[k] = x.x;
+                    lu1[k] = x.y;
+                    if (gl < d.cap[u[k]]) w[k] = d.pool[d.off[u[k]] + gl];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int2 x = w[k] >= 0 ? d.lvp[w[k]] : make_int2(0, 0);
+                lw0[k] = x.x;
+                lw1[k] = x.y;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; k++) slot(u[k], lu0[k], lu1[k], w[k], lw0[k], lw1[k]);
+        }
+    };
+    groups(std::integral_constant<int, 16>{}, n16, true);
+    groups(std::integral_constant<int, 8>{}, n8, false);
     if (nb) flush();
 }
 
@@ -3007,7 +3126,7 @@ void free_all(plds *h) {
     dfree(d.casc0), dfree(d.casc1), dfree(d.mv), dfree(d.mv1), dfree(d.sp), dfree(d.chunks), dfree(d.p0), dfree(d.p1), dfree(d.rc);
     dfree(d.lvb_start), dfree(d.lvb_fill), dfree(d.lvb), dfree(d.cl), dfree(d.sl0), dfree(d.sl1), dfree(d.cw);
     dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
-    dfree(d.prevlvl), dfree(h->t_ins), dfree(h->t_del);
+    dfree(d.prevlvl), dfree(d.lvp), dfree(h->t_ins), dfree(h->t_del);
     dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_stamp), dfree(h->sk_cnt), dfree(h->sk_pw);
     dfree(h->vd_buf);
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
@@ -3908,7 +4027,14 @@ int plds_coreness(plds_t *h, const int32_t *vertices, int64_t count, double *out
 int plds_track_orientation(plds_t *h, int32_t on) {
     int rc = guard(h);
     if (rc) return rc;
-    if (on && !h->d.prevlvl && dalloc(&h->d.prevlvl, h->n)) return PLDS_ENOMEM;
+    if (on && !h->d.prevlvl) {
+        if (dalloc(&h->d.prevlvl, h->n)) return PLDS_ENOMEM;
+        if (dalloc(&h->d.lvp, h->n)) {
+            dfree(h->d.prevlvl);
+            h->d.prevlvl = nullptr;
+            return PLDS_ENOMEM;
+        }
+    }
     h->track = on != 0;
     h->tracked_call = false;
     return PLDS_OK;
@@ -3950,9 +4076,9 @@ int plds_flips(plds_t *h, int32_t *out, int64_t cap, int64_t *count, void *strea
     if (!h->tracked_call) return PLDS_EINVAL;
     hipStream_t s = S(stream);
     Dev &d = h->d;
-    h->h_ctl->n_moved = 0;
+    for (int k = 0; k < 4; k++) h->h_ctl->n_fl[k] = 0;
     h->h_ctl->n_flip = 0;
-    HIPCHK(hipMemcpyAsync(&d.ctl->n_moved, &h->h_ctl->n_moved, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.ctl->n_fl, h->h_ctl->n_fl, sizeof(h->h_ctl->n_fl), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(&d.ctl->n_flip, &h->h_ctl->n_flip, sizeof(int64_t), hipMemcpyHostToDevice, s));
     const int with_ins = h->n_tins > 0;
     if (with_ins) {   // the call's insertions had no orientation before it

@@ -115,6 +115,30 @@ def test_flips_rmat14_stream():
     assert total > 0
 
 
+@pytest.mark.parametrize("sweep_mode", [1, 2])
+def test_flips_every_slab_class(sweep_mode):
+    """Moved vertices of every slab size the edge scan sorts apart: slabs of
+    8 and 16 slots, up to 2048, and hubs of several thousand slots whose
+    slabs are cut into chunks over all wavefronts."""
+    n = 2 ** 13
+    rng = np.random.default_rng(11)
+    hubs = [0, 1, 2]
+    e = [(h, v) for h in hubs for v in range(3, n) if rng.random() < 0.8]           # ~6500 each
+    e += [(v, int(x)) for v in range(3, 40) for x in rng.integers(40, n, size=300)]  # mid slabs
+    e += [(int(a), int(b)) for a, b in rng.integers(40, n, size=(4 * n, 2))]         # small slabs
+    say("flips slab classes", sweep_mode, len(e))
+    t = Tracked(n, 0.4, 3.0, 0, sweep_mode=sweep_mode)
+    total = 0
+    for i, c in enumerate(np.array_split(np.array(e, dtype=np.int32), 3)):
+        total += t.step(ins=c)
+    # a dense block on the hubs and some mid vertices lifts them
+    blk = list(range(0, 60))
+    total += t.step(ins=[(a, b) for a in blk for b in blk if a < b])
+    cur = t.o.edges()
+    total += t.step(dele=W.sample_edges(cur, len(cur) // 2, 12))
+    assert total > 0
+
+
 def test_flips_cap_empty_call_and_errors():
     n = 2 ** 10
     e = W.rmat(10, 8 * n, seed=8)
