@@ -115,11 +115,12 @@ struct Ctl {
     int32_t n_touch;      // distinct endpoints of those edges
     int32_t n_grow;       // slabs to regrow
     int32_t n_pieces;     // work items of the large regrown slabs
-    int32_t n_fl[4];      // moved vertices of the flip scan by slab size: 8, 16, up to kFlipHub, larger
+    int32_t n_fl[4];      // moved vertices of the flip scan by slab class
     int64_t n_flip;       // flipped edges found
     uint64_t dv_bits;     // largest coreness estimate of a graph (bits of a non-negative double)
     // static approximate k-core (Algorithm 6)
-    int32_t sk_t, sk_bp, sk_peels, sk_round, sk_done, sk_nI, sk_nT;
+    int32_t sk_t, sk_bp, sk_peels, sk_round, sk_done, sk_nT;
+    int32_t sk_ncl[4];    // the round's peeled vertices by slab class
     int64_t sk_alive;
     // vertex deletion: incident edges counted, then gathered
     int64_t vd_deg, vd_n;
@@ -2275,26 +2276,146 @@ __global__ void k_orient(Dev d, const int32_t *e, int64_t cnt, const int32_t *lv
     }
 }
 
+// ---- slab traversal by slab size (flip scan, static peeling)
+// A pass that visits every slot of the slabs of a list of vertices keeps
+// many searches in flight per wavefront when the vertices are sorted by slab
+// size first: class 0 (at most 8 slots) and 1 (9..16) take lane groups of
+// 8 and 16 lanes, class 2 (up to kSlabHub) a wavefront each, class 3 (hubs)
+// is cut into 256-slot chunks dealt out over all wavefronts.  Classes 0 and
+// 1 are listed from the front and the back of one array of n entries,
+// classes 2 and 3 likewise in a second one; the lists hold distinct
+// vertices, so two lists that share an array never meet.
+constexpr int32_t kSlabHub = 2048;
+constexpr int kSlabQ = 1024;
+constexpr int kSlabChunk = 4;   // 64-slot pieces per wavefront pass
+
+__device__ __forceinline__ int slab_class(int32_t cap) {
+    return cap <= 8 ? 0 : cap <= 16 ? 1 : cap <= kSlabHub ? 2 : 3;
+}
+
+struct SlabQ {
+    StageT<int32_t, kSlabQ> q[4];
+};
+
+__device__ __forceinline__ void slabq_init(SlabQ &s) {
+    for (int k = 0; k < 4; k++) st_init(s.q[k]);
+}
+
+// every thread of the block calls both; cls < 0 lists nothing
+__device__ __forceinline__ void slabq_push(SlabQ &s, int cls, int32_t v) {
+    for (int k = 0; k < 4; k++) st_push(s.q[k], cls == k, v);
+}
+
+__device__ __forceinline__ void slabq_flush(SlabQ &s, int32_t room, int32_t *lo, int32_t *hi, int32_t *cnt, int32_t n,
+                                            Ctl *c) {
+    st_flush(s.q[0], room, &cnt[0], n, c, [=](int32_t i, int32_t x) { lo[i] = x; });
+    st_flush(s.q[1], room, &cnt[1], n, c, [=](int32_t i, int32_t x) { lo[n - 1 - i] = x; });
+    st_flush(s.q[2], room, &cnt[2], n, c, [=](int32_t i, int32_t x) { hi[i] = x; });
+    st_flush(s.q[3], room, &cnt[3], n, c, [=](int32_t i, int32_t x) { hi[n - 1 - i] = x; });
+}
+
+// Every slot of every listed vertex's slab.  Every lane of the wavefront
+// calls it with the same lists and counts.  Per vertex u, hu = head(u) is
+// loaded once; the slots are taken in groups, gather(w) (w = -1: no slot)
+// is issued for the whole group before apply(u, hu, w, g) runs for each slot
+// of it, with every lane of the wavefront together.
+template <class Head, class Gather, class Apply>
+__device__ void visit_slabs(const Dev &d, const int32_t *lo, const int32_t *hi, const int32_t cnt[4], Head head,
+                            Gather gather, Apply apply) {
+    using G = decltype(gather(0));
+    const int lane = threadIdx.x % kWave;
+    const int nw = gridDim.x * blockDim.x / kWave;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int32_t nn = d.n, n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
+    // kSlabChunk * 64 slots of u's slab from slot e0
+    auto chunk = [&](int32_t u, int2 hu, const int32_t *sl, int32_t cu, int32_t e0) {
+        int32_t w[kSlabChunk];
+        G g[kSlabChunk];
+#pragma unroll
+        for (int k = 0; k < kSlabChunk; k++) {
+            const int32_t e = e0 + k * kWave + lane;
+            w[k] = e < cu ? sl[e] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kSlabChunk; k++) g[k] = gather(w[k]);
+#pragma unroll
+        for (int k = 0; k < kSlabChunk; k++) apply(u, hu, w[k], g[k]);
+    };
+    // hubs: chunks numbered across the hubs, 64 hubs at a time (a lane
+    // loads one hub's header); a wavefront takes the chunks whose number is
+    // its own modulo the number of wavefronts
+    int64_t before = 0;
+    for (int32_t hb = 0; hb < n3; hb += kWave) {
+        int32_t hv = -1, hc = 0;
+        int2 hh = make_int2(0, 0);
+        int64_t ho = 0;
+        if (hb + lane < n3) {
+            hv = hi[nn - 1 - (hb + lane)];
+            hh = head(hv);
+            hc = d.cap[hv];
+            ho = d.off[hv];
+        }
+        const int32_t nch = (hc + kSlabChunk * kWave - 1) / (kSlabChunk * kWave);
+        int32_t tot;
+        const int32_t ex = wave_excl(nch, &tot);
+        for (int64_t f = before + ((wid - before) % nw + nw) % nw; f < before + tot; f += nw) {
+            const int32_t r = (int32_t)(f - before);
+            const int j = __popcll(__ballot(ex + nch <= r));   // the hub holding chunk r
+            const int32_t u = __shfl(hv, j, kWave), cu = __shfl(hc, j, kWave);
+            const int2 hu = make_int2(__shfl(hh.x, j, kWave), __shfl(hh.y, j, kWave));
+            const int64_t o = __shfl(ho, j, kWave);
+            chunk(u, hu, d.pool + o, cu, (r - __shfl(ex, j, kWave)) * kSlabChunk * kWave);
+        }
+        before += tot;
+    }
+    // class 2: a wavefront each
+    for (int32_t i = wid; i < n2; i += nw) {
+        const int32_t u = hi[i];
+        const int2 hu = head(u);
+        const int32_t cu = d.cap[u];
+        const int32_t *sl = d.pool + d.off[u];
+        for (int32_t e0 = 0; e0 < cu; e0 += kSlabChunk * kWave) chunk(u, hu, sl, cu, e0);
+    }
+    // classes 1 and 0: lane groups, a vertex each, two passes of the grid in flight
+    auto groups = [&](auto GS, int32_t cnt_c, bool from_back) {
+        constexpr int gs = decltype(GS)::value, per = kWave / gs;
+        const int gi = lane / gs, gl = lane % gs;
+        for (int32_t base = wid * per; base < cnt_c; base += 2 * nw * per) {
+            int32_t u[2], w[2];
+            int2 hu[2];
+            G g[2];
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int32_t i = base + k * nw * per + gi;
+                u[k] = i < cnt_c ? (from_back ? lo[nn - 1 - i] : lo[i]) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                hu[k] = make_int2(0, 0);
+                w[k] = -1;
+                if (u[k] >= 0) {
+                    hu[k] = head(u[k]);
+                    if (gl < d.cap[u[k]]) w[k] = d.pool[d.off[u[k]] + gl];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 2; k++) g[k] = gather(w[k]);
+#pragma unroll
+            for (int k = 0; k < 2; k++) apply(u[k], hu[k], w[k], g[k]);
+        }
+    };
+    groups(std::integral_constant<int, 16>{}, n1, true);
+    groups(std::integral_constant<int, 8>{}, n0, false);
+}
+
 // Both levels of every vertex side by side (d.lvp), so that the edge scan
 // gathers one 8-byte pair per neighbour instead of two 4-byte values from two
 // arrays; and the vertices whose level differs from the call's starting
-// level, sorted by
-// slab size for the edge scan: at most 8 slots (d.mv from the front), 16
-// (d.mv from the back), up to kFlipHub (d.mv1 from the front) and larger
-// (d.mv1 from the back).  The lists hold distinct vertices, so two lists
-// that share an array of n entries never meet.
-constexpr int32_t kFlipHub = 2048;
-constexpr int kFlipQ = 1024;
+// level, by slab class (d.mv, d.mv1; counts n_fl).
 __global__ void k_flip_moved(Dev d) {
-    __shared__ StageT<int32_t, kFlipQ> q0, q1, q2, q3;
-    st_init(q0), st_init(q1), st_init(q2), st_init(q3);
-    int32_t *n = d.ctl->n_fl;
+    __shared__ SlabQ q;
+    slabq_init(q);
     const int32_t nn = d.n;
-    int32_t *mv = d.mv, *mv1 = d.mv1;
-    auto w0 = [=](int32_t i, int32_t x) { mv[i] = x; };
-    auto w1 = [=](int32_t i, int32_t x) { mv[nn - 1 - i] = x; };
-    auto w2 = [=](int32_t i, int32_t x) { mv1[i] = x; };
-    auto w3 = [=](int32_t i, int32_t x) { mv1[nn - 1 - i] = x; };
     const int stride = gridDim.x * blockDim.x;
     for (int vb = blockIdx.x * blockDim.x; vb < nn; vb += stride) {
         const int v = vb + threadIdx.x;
@@ -2302,24 +2423,12 @@ __global__ void k_flip_moved(Dev d) {
         if (v < nn) {
             const int32_t l0 = d.prevlvl[v], l1 = d.level[v];
             d.lvp[v] = make_int2(l0, l1);
-            if (l0 != l1) {
-                const int32_t c = d.cap[v];
-                cls = c <= 8 ? 0 : c <= 16 ? 1 : c <= kFlipHub ? 2 : 3;
-            }
+            if (l0 != l1) cls = slab_class(d.cap[v]);
         }
-        st_push(q0, cls == 0, v);
-        st_push(q1, cls == 1, v);
-        st_push(q2, cls == 2, v);
-        st_push(q3, cls == 3, v);
-        st_flush(q0, blockDim.x, &n[0], nn, d.ctl, w0);
-        st_flush(q1, blockDim.x, &n[1], nn, d.ctl, w1);
-        st_flush(q2, blockDim.x, &n[2], nn, d.ctl, w2);
-        st_flush(q3, blockDim.x, &n[3], nn, d.ctl, w3);
+        slabq_push(q, cls, v);
+        slabq_flush(q, blockDim.x, d.mv, d.mv1, d.ctl->n_fl, nn, d.ctl);
     }
-    st_flush(q0, kFlipQ, &n[0], nn, d.ctl, w0);
-    st_flush(q1, kFlipQ, &n[1], nn, d.ctl, w1);
-    st_flush(q2, kFlipQ, &n[2], nn, d.ctl, w2);
-    st_flush(q3, kFlipQ, &n[3], nn, d.ctl, w3);
+    slabq_flush(q, kSlabQ, d.mv, d.mv1, d.ctl->n_fl, nn, d.ctl);
 }
 
 // The call's applied insertions into the batch hash set (empty before).
@@ -2353,15 +2462,10 @@ __device__ __forceinline__ bool flip_was_inserted(const Dev &d, uint64_t key) {
 // the current levels is a flip, reported as it was.  An edge with both
 // endpoints moved is reported by its smaller endpoint; edges the call
 // inserted (in the hash set when with_ins) had no orientation before.
-// The work is spread by slab size, so that many searches are in flight per
-// wavefront: slabs of more than kFlipHub slots are cut into chunks of 256
-// slots dealt out over all wavefronts; a wavefront searches a slab of up
-// to kFlipHub slots 256 at a time; lane groups of 16 and 8 search the
-// smallest slabs, 4 and 8 vertices per wavefront.  Each wavefront stages
-// its flips in LDS and appends them with one atomic per 256; positions at
-// or beyond cap are counted, not written.
+// The slabs are visited by slab class.  Each wavefront stages its flips in
+// LDS and appends them with one atomic per 256; positions at or beyond cap
+// are counted, not written.
 constexpr int kFlipStage = 256;
-constexpr int kFlipChunk = 4;   // 64-slot pieces per wavefront pass
 __global__ void __launch_bounds__(kBlock) k_flip_scan(Dev d, int with_ins, int32_t *out, int64_t cap) {
     __shared__ int32_t buf[kBlock / kWave][2 * (kFlipStage + kWave)];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -2376,16 +2480,15 @@ __global__ void __launch_bounds__(kBlock) k_flip_scan(Dev d, int with_ins, int32
             if ((int64_t)base + i / 2 < cap) out[2 * base + i] = b[i];
         nb = 0;
     };
-    // one searched slot (w < 0: none) with the levels of both ends gathered;
-    // stages the edge (u, w) if it flipped (every lane of the wavefront
-    // calls it together)
-    auto slot = [&](int32_t u, int32_t lu0, int32_t lu1, int32_t w, int32_t lw0, int32_t lw1) {
+    // one slot (w < 0: none) with both levels of both ends; stages the edge
+    // (u, w) if it flipped
+    auto slot = [&](int32_t u, int2 lu, int32_t w, int2 lw) {
         bool f = false;
         int32_t t = 0, hd = 0;
         if (w >= 0) {
-            const bool b0 = points_up(u, w, lu0, lw0), b1 = points_up(u, w, lu1, lw1);
+            const bool b0 = points_up(u, w, lu.x, lw.x), b1 = points_up(u, w, lu.y, lw.y);
             const int32_t lo = min(u, w), hi = max(u, w);
-            f = b0 != b1 && (lw0 == lw1 || u < w);
+            f = b0 != b1 && (lw.x == lw.y || u < w);
             if (f && with_ins) f = !flip_was_inserted(d, ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi);
             t = b0 ? lo : hi;
             hd = b0 ? hi : lo;
@@ -2399,98 +2502,10 @@ __global__ void __launch_bounds__(kBlock) k_flip_scan(Dev d, int with_ins, int32
         nb += __popcll(m);
         if (nb >= kFlipStage) flush();
     };
-    // 256 slots of u's slab from slot e0: all loads first, then the decisions
-    auto chunk = [&](int32_t u, int32_t lu0, int32_t lu1, const int32_t *sl, int32_t cu, int32_t e0) {
-        int32_t w[kFlipChunk], lw0[kFlipChunk], lw1[kFlipChunk];
-#pragma unroll
-        for (int k = 0; k < kFlipChunk; k++) {
-            const int32_t e = e0 + k * kWave + lane;
-            w[k] = e < cu ? sl[e] : -1;
-        }
-#pragma unroll
-        for (int k = 0; k < kFlipChunk; k++) {
-            const int2 x = w[k] >= 0 ? d.lvp[w[k]] : make_int2(0, 0);
-            lw0[k] = x.x;
-            lw1[k] = x.y;
-        }
-#pragma unroll
-        for (int k = 0; k < kFlipChunk; k++) slot(u, lu0, lu1, w[k], lw0[k], lw1[k]);
-    };
-    const int nw = gridDim.x * blockDim.x / kWave;
-    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int32_t n8 = d.ctl->n_fl[0], n16 = d.ctl->n_fl[1], nmid = d.ctl->n_fl[2], nhub = d.ctl->n_fl[3];
-    const int32_t nn = d.n;
-    // the largest slabs: 256-slot chunks numbered across the hubs, 64 hubs
-    // at a time (a lane loads one hub's header); a wavefront takes the
-    // chunks whose number is its own modulo the number of wavefronts
-    int64_t before = 0;
-    for (int32_t hb = 0; hb < nhub; hb += kWave) {
-        int32_t hu = -1, h0 = 0, h1 = 0, hc = 0;
-        int64_t ho = 0;
-        if (hb + lane < nhub) {
-            hu = d.mv1[nn - 1 - (hb + lane)];
-            const int2 x = d.lvp[hu];
-            h0 = x.x;
-            h1 = x.y;
-            hc = d.cap[hu];
-            ho = d.off[hu];
-        }
-        const int32_t nch = (hc + kFlipChunk * kWave - 1) / (kFlipChunk * kWave);
-        int32_t tot;
-        const int32_t ex = wave_excl(nch, &tot);
-        for (int64_t f = before + ((wid - before) % nw + nw) % nw; f < before + tot; f += nw) {
-            const int32_t r = (int32_t)(f - before);
-            const int j = __popcll(__ballot(ex + nch <= r));   // the hub holding chunk r
-            const int32_t u = __shfl(hu, j, kWave), lu0 = __shfl(h0, j, kWave), lu1 = __shfl(h1, j, kWave);
-            const int32_t cu = __shfl(hc, j, kWave), e0 = (r - __shfl(ex, j, kWave)) * kFlipChunk * kWave;
-            const int64_t o = __shfl(ho, j, kWave);
-            chunk(u, lu0, lu1, d.pool + o, cu, e0);
-        }
-        before += tot;
-    }
-    // slabs of 17..kFlipHub slots: a wavefront each
-    for (int32_t i = wid; i < nmid; i += nw) {
-        const int32_t u = d.mv1[i];
-        const int2 x = d.lvp[u];
-        const int32_t lu0 = x.x, lu1 = x.y, cu = d.cap[u];
-        const int32_t *sl = d.pool + d.off[u];
-        for (int32_t e0 = 0; e0 < cu; e0 += kFlipChunk * kWave) chunk(u, lu0, lu1, sl, cu, e0);
-    }
-    // the smallest slabs: lane groups of G lanes, a vertex each, two passes
-    // of the grid in flight
-    auto groups = [&](auto G, int32_t cnt, bool from_back) {
-        constexpr int per = kWave / decltype(G)::value;
-        const int gi = lane / decltype(G)::value, gl = lane % decltype(G)::value;
-        for (int32_t base = wid * per; base < cnt; base += 2 * nw * per) {
-            int32_t u[2], lu0[2], lu1[2], w[2], lw0[2], lw1[2];
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                const int32_t i = base + k * nw * per + gi;
-                u[k] = i < cnt ? (from_back ? d.mv[nn - 1 - i] : d.mv[i]) : -1;
-            }
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                lu0[k] = lu1[k] = 0;
-                w[k] = -1;
-                if (u[k] >= 0) {
-                    const int2 x = d.lvp[u[k]];
-                    lu0[k] = x.x;
-                    lu1[k] = x.y;
-                    if (gl < d.cap[u[k]]) w[k] = d.pool[d.off[u[k]] + gl];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                const int2 x = w[k] >= 0 ? d.lvp[w[k]] : make_int2(0, 0);
-                lw0[k] = x.x;
-                lw1[k] = x.y;
-            }
-#pragma unroll
-            for (int k = 0; k < 2; k++) slot(u[k], lu0[k], lu1[k], w[k], lw0[k], lw1[k]);
-        }
-    };
-    groups(std::integral_constant<int, 16>{}, n16, true);
-    groups(std::integral_constant<int, 8>{}, n8, false);
+    const int2 *lvp = d.lvp;
+    visit_slabs(
+        d, d.mv, d.mv1, d.ctl->n_fl, [=](int32_t u) { return lvp[u]; },
+        [=](int32_t w) { return w >= 0 ? lvp[w] : make_int2(0, 0); }, slot);
     if (nb) flush();
 }
 
@@ -2515,12 +2530,14 @@ __global__ void k_max_estimate(Dev d, int32_t v0, int32_t cnt) {
 
 // ---- static approximate k-core (the static section, Algorithm 6).  State:
 // C[v] (the count), B[v] (bucket; -1: no edges or peeled, -2: peeled in
-// the current round), stamp[v] (last round that touched v), cnt[b] (alive
-// vertices per bucket), pw[b] = (1+eps)^b by repeated double multiplication
-// on the host.  A round peels bucket bp, lowers the counts of the peeled
-// vertices' alive neighbours, re-buckets them, and picks the next bucket.
+// the current round), r[v] (the round's peeled neighbours of v; zero
+// between rounds), cnt[b] (alive vertices per bucket), pw[b] = (1+eps)^b by
+// repeated double multiplication on the host; Ilo/Ihi list the round's
+// peeled vertices by slab class, T the vertices the round touched.  A round
+// peels bucket bp, lowers the counts of the peeled vertices' alive
+// neighbours, re-buckets them, and picks the next bucket.
 struct SK {
-    int32_t *C, *B, *stamp, *cnt, *I, *T;
+    int32_t *C, *B, *r, *cnt, *Ilo, *Ihi, *T;
     const double *pw;
     double *est;
     int32_t nbk, R;
@@ -2556,7 +2573,7 @@ __global__ void k_sk_init(Dev d, SK k) {
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) {
         const int32_t dg = d.deg[v];
         k.C[v] = dg;
-        k.stamp[v] = -1;
+        k.r[v] = 0;
         k.est[v] = 0.0;
         int32_t b = -1;
         if (dg > 0) {
@@ -2594,7 +2611,8 @@ __global__ void k_sk_first(Dev d, SK k) {
         c->sk_t = c->sk_bp = b;
         c->sk_peels = 0;
         c->sk_round = 0;
-        c->sk_nI = c->sk_nT = 0;
+        c->sk_nT = 0;
+        c->sk_ncl[0] = c->sk_ncl[1] = c->sk_ncl[2] = c->sk_ncl[3] = 0;
         c->sk_done = b < 0 ? 1 : 0;
     }
 }
@@ -2602,34 +2620,35 @@ __global__ void k_sk_first(Dev d, SK k) {
 // Part 1 of a round: the alive vertices of bucket bp are peeled (estimate
 // (1+eps)^bp) and listed; the previous round's peeled vertices become dead.
 __global__ void k_sk_peel(Dev d, SK k) {
-    __shared__ Stage q;
+    __shared__ SlabQ q;
     const Ctl *c = d.ctl;
     if (c->sk_done) return;
     const int32_t bp = c->sk_bp;
     const double e = k.pw[bp];
-    stage_init(q);
+    slabq_init(q);
     const int stride = gridDim.x * blockDim.x;
     for (int vb = blockIdx.x * blockDim.x; vb < d.n; vb += stride) {
         const int v = vb + threadIdx.x;
-        bool pe = false;
+        int cls = -1;
         if (v < d.n) {
             const int32_t b = k.B[v];
             if (b == -2) k.B[v] = -1;
-            pe = b == bp;
-            if (pe) {
+            if (b == bp) {
                 k.B[v] = -2;
                 k.est[v] = e;
+                cls = slab_class(d.cap[v]);
             }
         }
-        stage_push(q, pe, v);
-        stage_flush(q, blockDim.x, k.I, &d.ctl->sk_nI, d.n, d.ctl);
+        slabq_push(q, cls, v);
+        slabq_flush(q, blockDim.x, k.Ilo, k.Ihi, d.ctl->sk_ncl, d.n, d.ctl);
     }
-    stage_flush(q, kStage, k.I, &d.ctl->sk_nI, d.n, d.ctl);
+    slabq_flush(q, kSlabQ, k.Ilo, k.Ihi, d.ctl->sk_ncl, d.n, d.ctl);
 }
 
-// Part 2: every alive neighbour w of a peeled vertex loses one from C[w]
-// per peeled neighbour (r_w in all); the first touch in the round lists w.
-// A wavefront per peeled vertex; touched vertices staged per wavefront.
+// Part 2: every alive neighbour w of a peeled vertex counts its peeled
+// neighbours in r[w]; the first count in the round lists w.  The peeled
+// vertices' slabs are visited by slab class; touched vertices are staged per
+// wavefront.
 __global__ void __launch_bounds__(kBlock) k_sk_relax(Dev d, SK k) {
     __shared__ int32_t buf[kBlock / kWave][kFlipStage + kWave];
     const Ctl *c = d.ctl;
@@ -2647,30 +2666,21 @@ __global__ void __launch_bounds__(kBlock) k_sk_relax(Dev d, SK k) {
         if (lane == 0 && base + nb > d.n) latch(d.ctl, kErrLevel);
         nb = 0;
     };
-    const int32_t ni = c->sk_nI, round = c->sk_round;
-    const int nw = gridDim.x * blockDim.x / kWave;
-    for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < ni; i += nw) {
-        const int32_t u = k.I[i];
-        const int32_t cu = d.cap[u];
-        const int32_t *sl = d.pool + d.off[u];
-        for (int32_t e0 = 0; e0 < cu; e0 += kWave) {
-            const int32_t e = e0 + lane;
-            const int32_t w = e < cu ? sl[e] : -1;
-            bool first = false;
-            if (w >= 0 && k.B[w] >= 0) {
-                atomicSub(&k.C[w], 1);
-                first = atomicExch(&k.stamp[w], round) != round;
-            }
-            const uint64_t m = __ballot(first);
-            if (first) b[nb + __popcll(m & ((1ull << lane) - 1))] = w;
-            nb += __popcll(m);
-            if (nb >= kFlipStage) flush();
-        }
-    }
+    auto slot = [&](int32_t, int2, int32_t w, int32_t bw) {
+        const bool first = w >= 0 && bw >= 0 && atomicAdd(&k.r[w], 1) == 0;
+        const uint64_t m = __ballot(first);
+        if (first) b[nb + __popcll(m & ((1ull << lane) - 1))] = w;
+        nb += __popcll(m);
+        if (nb >= kFlipStage) flush();
+    };
+    const int32_t *B = k.B;
+    visit_slabs(
+        d, k.Ilo, k.Ihi, c->sk_ncl, [](int32_t) { return make_int2(0, 0); },
+        [=](int32_t w) { return w >= 0 ? B[w] : -1; }, slot);
     if (nb) flush();
 }
 
-// Part 3: the touched vertices: C = max(C, ceil((1+eps)^(t-1))), bucket
+// Part 3: the touched vertices: C = max(C - r, ceil((1+eps)^(t-1))), r = 0, bucket
 // max(b(C), t); bucket counts moved through an LDS histogram per block.
 __global__ void k_sk_fix(Dev d, SK k) {
     extern __shared__ int32_t hist[];   // [nbk]
@@ -2684,8 +2694,9 @@ __global__ void k_sk_fix(Dev d, SK k) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
         const int32_t w = k.T[i];
         const int32_t ob = k.B[w];
-        const int32_t cw = max(k.C[w], floor_t);
+        const int32_t cw = max(k.C[w] - k.r[w], floor_t);
         k.C[w] = cw;
+        k.r[w] = 0;
         const int32_t nb = max(sk_bucket(k, cw), t);
         if (nb != ob) {
             k.B[w] = nb;
@@ -2704,7 +2715,8 @@ __global__ void k_sk_next(Dev d, SK k) {
     __shared__ int32_t red[kBlock / kWave];
     Ctl *c = d.ctl;
     if (c->sk_done) return;
-    const int32_t bp = c->sk_bp, t = c->sk_t, ni = c->sk_nI;
+    const int32_t bp = c->sk_bp, t = c->sk_t;
+    const int32_t ni = c->sk_ncl[0] + c->sk_ncl[1] + c->sk_ncl[2] + c->sk_ncl[3];
     __syncthreads();
     if (threadIdx.x == 0) k.cnt[bp] -= ni;   // the peeled vertices (vertices re-bucketed to bp stay)
     __syncthreads();
@@ -2713,7 +2725,7 @@ __global__ void k_sk_next(Dev d, SK k) {
         c->sk_alive -= ni;
         c->sk_peels += 1;
         c->sk_round += 1;
-        c->sk_nI = 0;
+        c->sk_ncl[0] = c->sk_ncl[1] = c->sk_ncl[2] = c->sk_ncl[3] = 0;
         c->sk_nT = 0;
         if (nb < 0 || c->sk_alive <= 0) {
             c->sk_done = 1;
@@ -3042,7 +3054,7 @@ struct plds {
     int32_t *vd_buf = nullptr;    // incident edges of deleted vertices
     int64_t vd_cap = 0;
     // static approximate k-core scratch (allocated on first use)
-    int32_t *sk_C = nullptr, *sk_B = nullptr, *sk_stamp = nullptr, *sk_cnt = nullptr;
+    int32_t *sk_C = nullptr, *sk_B = nullptr, *sk_r = nullptr, *sk_cnt = nullptr;
     double *sk_pw = nullptr;
     bool track = false;
     bool tracked_call = false;
@@ -3127,7 +3139,7 @@ void free_all(plds *h) {
     dfree(d.lvb_start), dfree(d.lvb_fill), dfree(d.lvb), dfree(d.cl), dfree(d.sl0), dfree(d.sl1), dfree(d.cw);
     dfree(h->tile), dfree(h->newoff), dfree(h->bad), dfree(h->bar);
     dfree(d.prevlvl), dfree(d.lvp), dfree(h->t_ins), dfree(h->t_del);
-    dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_stamp), dfree(h->sk_cnt), dfree(h->sk_pw);
+    dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_r), dfree(h->sk_cnt), dfree(h->sk_pw);
     dfree(h->vd_buf);
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
     if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
@@ -4136,15 +4148,15 @@ int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
     int32_t R = 0;
     for (double x = 1.0; x < (double)h->n; x *= 1.0 + 2.0 / eps) R++;
     if (!h->sk_C) {
-        if (dalloc(&h->sk_C, h->n) || dalloc(&h->sk_B, h->n) || dalloc(&h->sk_stamp, h->n) ||
+        if (dalloc(&h->sk_C, h->n) || dalloc(&h->sk_B, h->n) || dalloc(&h->sk_r, h->n) ||
             dalloc(&h->sk_cnt, kSkBuckets) || dalloc(&h->sk_pw, kSkBuckets)) {
-            dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_stamp), dfree(h->sk_cnt), dfree(h->sk_pw);
-    dfree(h->vd_buf);
-            h->sk_C = nullptr;
+            dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_r), dfree(h->sk_cnt), dfree(h->sk_pw);
             return PLDS_ENOMEM;
         }
     }
-    SK k{h->sk_C, h->sk_B, h->sk_stamp, h->sk_cnt, d.mv, d.mv1, h->sk_pw, est_out, (int32_t)pw.size(), R, eps};
+    // the peeled and touched lists use arrays of n entries that are idle
+    // outside update calls
+    SK k{h->sk_C, h->sk_B, h->sk_r, h->sk_cnt, d.mv, d.casc0, d.mv1, h->sk_pw, est_out, (int32_t)pw.size(), R, eps};
     HIPCHK(hipMemcpyAsync(h->sk_pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(h->sk_cnt, 0, kSkBuckets * sizeof(int32_t), s));
     h->h_ctl->sk_alive = 0;
