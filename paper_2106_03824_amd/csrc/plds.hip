@@ -477,7 +477,9 @@ __device__ bool slab_has(const int32_t *s, int32_t cap, int32_t key) {
     return false;
 }
 
-// key is known absent; space is guaranteed by the growth plan
+// key is known absent; space is guaranteed by the growth plan.  The
+// slab's fill count grows by the endpoint's new edges after the batch
+// (k_ins_seed); a put that reuses a tombstone takes its slot back from it.
 __device__ bool slab_put(int32_t *s, int32_t cap, int32_t key, int32_t *fill) {
     if (cap == 0) return false;
     uint32_t i = home(key, cap);
@@ -486,7 +488,7 @@ __device__ bool slab_put(int32_t *s, int32_t cap, int32_t key, int32_t *fill) {
         if (x == kEmpty || x == kTomb) {
             int32_t prev = atomicCAS(&s[i], x, key);
             if (prev == x) {
-                if (x == kEmpty && fill) atomicAdd(fill, 1);
+                if (x == kTomb && fill) atomicSub(fill, 1);
                 return true;
             }
         }
@@ -810,7 +812,9 @@ __global__ void k_ins_seed(Dev d) {
         int32_t x = -1, key = -1;
         if (i < nt) {
             x = d.touch[i];
-            d.deg[x] += d.addc[x];   // the endpoint's new edges (counted by k_touch)
+            const int32_t k = d.addc[x];   // the endpoint's new edges (counted by k_touch)
+            d.deg[x] += k;
+            d.fill[x] += k;
             d.addc[x] = 0;
             int32_t lx = d.level[x];
             if (d.up[x] > up_cap(d, gp(d, x), lx)) key = lx;
@@ -2869,7 +2873,9 @@ __global__ void k_clear_touch(Dev d) {
     int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
         int32_t x = d.touch[i];
-        d.deg[x] += d.addc[x];
+        const int32_t k = d.addc[x];   // the endpoint's new edges
+        d.deg[x] += k;
+        d.fill[x] += k;
         d.addc[x] = 0;
     }
 }
