@@ -2310,12 +2310,42 @@ __device__ __forceinline__ void slabq_push(SlabQ &s, int cls, int32_t v) {
     for (int k = 0; k < 4; k++) st_push(s.q[k], cls == k, v);
 }
 
-__device__ __forceinline__ void slabq_flush(SlabQ &s, int32_t room, int32_t *lo, int32_t *hi, int32_t *cnt, int32_t n,
-                                            Ctl *c) {
-    st_flush(s.q[0], room, &cnt[0], n, c, [=](int32_t i, int32_t x) { lo[i] = x; });
-    st_flush(s.q[1], room, &cnt[1], n, c, [=](int32_t i, int32_t x) { lo[n - 1 - i] = x; });
-    st_flush(s.q[2], room, &cnt[2], n, c, [=](int32_t i, int32_t x) { hi[i] = x; });
-    st_flush(s.q[3], room, &cnt[3], n, c, [=](int32_t i, int32_t x) { hi[n - 1 - i] = x; });
+// Moves every queue with fewer than `room` free entries to its list (all
+// non-empty ones when room = kSlabQ), deciding for the four queues at once,
+// so that a round without a flush costs two barriers.
+__device__ void slabq_flush(SlabQ &s, int32_t room, int32_t *lo, int32_t *hi, int32_t *cnt, int32_t n, Ctl *c) {
+    __shared__ int32_t base[4];
+    __syncthreads();
+    int32_t k[4];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        k[q] = s.q[q].n;
+        if (k[q] == 0 || k[q] + room <= kSlabQ) k[q] = 0;   // not flushed this time
+        any |= k[q] != 0;
+    }
+    __syncthreads();
+    if (!any) return;   // block-uniform
+    if (threadIdx.x < 4 && k[threadIdx.x]) {
+        base[threadIdx.x] = atomicAdd(&cnt[threadIdx.x], k[threadIdx.x]);
+        if (base[threadIdx.x] + k[threadIdx.x] > n) latch(c, kErrLevel);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int32_t b = base[q];
+        for (int i = threadIdx.x; i < k[q]; i += blockDim.x) {
+            if (b + i >= n) continue;
+            const int32_t x = s.q[q].buf[i];
+            if (q == 0) lo[b + i] = x;
+            else if (q == 1) lo[n - 1 - (b + i)] = x;
+            else if (q == 2) hi[b + i] = x;
+            else hi[n - 1 - (b + i)] = x;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && k[threadIdx.x]) s.q[threadIdx.x].n = 0;
+    __syncthreads();
 }
 
 // Every slot of every listed vertex's slab.  Every lane of the wavefront
