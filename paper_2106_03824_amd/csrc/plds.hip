@@ -685,11 +685,15 @@ __global__ void k_grow_alloc(Dev d) {
 // Move the live entries of each regrown slab into its new slab.  The new
 // slab starts empty and only its movers write it, so every entry lands on an
 // empty slot and its fill is the number of entries moved.  A new slab of at
-// most kGrowLds slots is built by one wavefront in LDS (CAS on LDS, then one
-// coalesced write of the whole slab; fill stored once); any linear-probing
-// placement is a valid slab, since the new slab has no tombstones.  Larger
-// ones are filled in place, kGrowPiece old slots per wavefront (fill added
-// once per piece), so that a hub's slab is spread over many wavefronts.
+// most kGrowLds slots is built in LDS (CAS on LDS, then one coalesced write
+// of the whole slab; fill stored once); any linear-probing placement is a
+// valid slab, since the new slab has no tombstones.  A wavefront takes four
+// regrown slabs per pass: when all four new slabs fit in a quarter of its
+// table, lane groups of 16 build them side by side, else the whole
+// wavefront builds them one after another.  The tables are per wavefront,
+// so the phases are ordered by wavefront-local fences.  Larger slabs are
+// filled in place, kGrowPiece old slots per wavefront (fill added once per
+// piece), so that a hub's slab is spread over many wavefronts.
 
 __device__ __forceinline__ bool lds_put(int32_t *t, int32_t cap, int32_t key) {
     uint32_t i = home(key, cap);
@@ -700,45 +704,63 @@ __device__ __forceinline__ bool lds_put(int32_t *t, int32_t cap, int32_t key) {
     return false;
 }
 
+// the new slab (nc slots at ns) of vertex x from its old slab (oc slots at
+// os), in table t, by the lanes l, l + nl, ... of a group of nl lanes;
+// returns the entries this lane moved
+__device__ __forceinline__ int32_t grow_build(Dev &d, int32_t *t, const int32_t *os, int32_t oc, int32_t *ns, int32_t nc,
+                                              int l, int nl) {
+    for (int i = l; i < nc; i += nl) t[i] = kEmpty;
+    __threadfence_block();
+    int32_t moved = 0;
+    for (int i = l; i < oc; i += nl) {
+        const int32_t w = os[i];
+        if (w >= 0) {
+            if (lds_put(t, nc, w)) moved++;
+            else latch(d.ctl, kErrFull);
+        }
+    }
+    __threadfence_block();
+    for (int i = l; i < nc; i += nl) ns[i] = t[i];
+    __threadfence_block();   // the table is reused next
+    return moved;
+}
+
+constexpr int kGrowSub = 4;                       // regrown slabs per wavefront pass
+constexpr int kGrowSubLanes = kWave / kGrowSub;   // lanes per slab when they fit side by side
+constexpr int kGrowSubCap = kGrowLds / kGrowSub;  // slots of each side-by-side table
+
 __global__ void __launch_bounds__(kBlock) k_grow_move(Dev d) {
     __shared__ int32_t tab[kBlock / kWave][kGrowLds];
     const int32_t ng = d.ctl->n_grow;
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int nw = gridDim.x * blockDim.x / kWave;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     int32_t *t = tab[wv];
-    // the slabs up to kGrowLds slots (larger ones are done in pieces below)
-    // rounds are block-uniform: each wavefront takes one slab per round
-    for (int base = blockIdx.x * wpb; base < ng; base += gridDim.x * wpb) {
-        const int g = base + wv;
+    const int sub = lane / kGrowSubLanes, sl = lane % kGrowSubLanes;
+    for (int gb = wid * kGrowSub; gb < ng; gb += nw * kGrowSub) {   // wave-uniform
+        const int g = gb + sub;
         const bool has = g < ng && d.newcap[g] != 0;
         const int32_t x = has ? d.grow[g] : -1;
         const int32_t nc = has ? d.cap[x] : 0, oc = has ? d.oldcap[g] : 0;
-        const bool in_lds = has && nc <= kGrowLds;
-        if (in_lds)
-            for (int i = lane; i < nc; i += kWave) t[i] = kEmpty;
-        __syncthreads();
-        int32_t moved = 0;
-        if (in_lds) {
-            const int32_t *os = d.pool + d.oldoff[g];
-            for (int i = lane; i < oc; i += kWave) {
-                const int32_t w = os[i];
-                if (w >= 0) {
-                    if (lds_put(t, nc, w)) moved++;
-                    else latch(d.ctl, kErrFull);
-                }
+        const int64_t oo = has ? d.oldoff[g] : 0, no = has ? d.off[x] : 0;
+        if (__all(nc <= kGrowSubCap)) {
+            int32_t moved = grow_build(d, t + sub * kGrowSubCap, d.pool + oo, oc, d.pool + no, nc, sl, kGrowSubLanes);
+            for (int o = kGrowSubLanes / 2; o > 0; o >>= 1) moved += __shfl_xor(moved, o, kWave);
+            if (has && sl == 0) d.fill[x] = moved;
+        } else {
+            for (int k = 0; k < kGrowSub; k++) {
+                const int src = k * kGrowSubLanes;
+                const int32_t xk = __shfl(x, src, kWave), nck = __shfl(nc, src, kWave), ock = __shfl(oc, src, kWave);
+                const int64_t ook = __shfl(oo, src, kWave), nok = __shfl(no, src, kWave);
+                if (xk < 0 || nck > kGrowLds) continue;   // wave-uniform; larger slabs go in pieces
+                const int32_t moved = wave_sum(grow_build(d, t, d.pool + ook, ock, d.pool + nok, nck, lane, kWave));
+                if (lane == 0) d.fill[xk] = moved;
             }
         }
-        __syncthreads();
-        if (in_lds) {
-            int32_t *ns = d.pool + d.off[x];
-            for (int i = lane; i < nc; i += kWave) ns[i] = t[i];
-            moved = wave_sum(moved);
-            if (lane == 0) d.fill[x] = moved;
-        }
-        __syncthreads();   // the next round reuses the tables
     }
     // the larger slabs, a piece per wavefront
     const int32_t np = (int32_t)min((int64_t)d.ctl->n_pieces, d.chunk_cap);
-    for (int i = blockIdx.x * wpb + wv; i < np; i += gridDim.x * wpb) {
+    for (int i = wid; i < np; i += nw) {
         const int64_t desc = d.chunks[i];
         const int32_t g = (int32_t)(desc >> 32), k = (int32_t)(desc & 0xffffffff);
         const int32_t x = d.grow[g], oc = d.oldcap[g], nc = d.cap[x];
