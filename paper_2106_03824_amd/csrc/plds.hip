@@ -523,10 +523,14 @@ __global__ void k_range_check(const int32_t *e, int64_t cnt, int32_t n, Ctl *ctl
 
 // Batch preprocessing (framework section): canonical (min,max) pair, no
 // self-loop, first copy only (hash set), then keep it iff its presence in the
-// graph equals want_present (insertions: absent, deletions: present).
+// graph equals want_present (insertions: absent, deletions: present).  A
+// kept edge counts one new (or removed) slot at each endpoint (addc); the
+// first count lists the endpoint (touch).
 __global__ void k_dedupe(Dev d, const int32_t *e, int64_t cnt, int want_present) {
     __shared__ StageT<int64_t, 2048> q;
+    __shared__ Stage qt;
     st_init(q);
+    stage_init(qt);
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t *valid = (int64_t *)d.valid;   // pair (u, v) as one little-endian int64
     auto wr = [=](int32_t k, int64_t x) { valid[k] = x; };
@@ -566,26 +570,16 @@ __global__ void k_dedupe(Dev d, const int32_t *e, int64_t cnt, int want_present)
                 }
             }
         }
+        const bool first_u = keep && atomicAdd(&d.addc[u], 1) == 0;
+        const bool first_v = keep && atomicAdd(&d.addc[v], 1) == 0;
         st_push(q, keep, (int64_t)(((uint64_t)(uint32_t)v << 32) | (uint32_t)u));
+        stage_push(qt, first_u, u);
+        stage_push(qt, first_v, v);
         st_flush(q, (int32_t)blockDim.x, &d.ctl->n_valid, INT32_MAX, d.ctl, wr);
+        stage_flush(qt, 2 * (int32_t)blockDim.x, d.touch, &d.ctl->n_touch, d.n, d.ctl);
     }
     st_flush(q, 2048, &d.ctl->n_valid, INT32_MAX, d.ctl, wr);
-}
-
-// count new slots per endpoint; first touch records the vertex
-__global__ void k_touch(Dev d) {
-    __shared__ Stage q;
-    stage_init(q);
-    int32_t nv = d.ctl->n_valid;
-    int stride = gridDim.x * blockDim.x;
-    for (int ib = blockIdx.x * blockDim.x; ib < 2 * nv; ib += stride) {
-        int i = ib + threadIdx.x;
-        int32_t x = i < 2 * nv ? d.valid[i] : -1;
-        bool first = x >= 0 && atomicAdd(&d.addc[x], 1) == 0;
-        stage_push(q, first, x);
-        stage_flush(q, blockDim.x, d.touch, &d.ctl->n_touch, d.n, d.ctl);
-    }
-    stage_flush(q, kStage, d.touch, &d.ctl->n_touch, d.n, d.ctl);
+    stage_flush(qt, kStage, d.touch, &d.ctl->n_touch, d.n, d.ctl);
 }
 
 // slabs that would exceed 80% occupancy are regrown to 60% of the new size
@@ -834,7 +828,7 @@ __global__ void k_ins_seed(Dev d) {
         int32_t x = -1, key = -1;
         if (i < nt) {
             x = d.touch[i];
-            const int32_t k = d.addc[x];   // the endpoint's new edges (counted by k_touch)
+            const int32_t k = d.addc[x];   // the endpoint's new edges (counted by k_dedupe)
             d.deg[x] += k;
             d.fill[x] += k;
             d.addc[x] = 0;
@@ -2078,7 +2072,7 @@ __global__ void k_del_cand(Dev d) {
         int32_t w = -1;
         if (i < nt) {
             w = d.touch[i];
-            d.deg[w] -= d.addc[w];   // the endpoint's deleted edges (counted by k_touch)
+            d.deg[w] -= d.addc[w];   // the endpoint's deleted edges (counted by k_dedupe)
             d.addc[w] = 0;
             const int32_t lw = d.level[w];
             viol = lw > 0 && d.ups[w] < dn_floor(d, gp(d, w), lw);
@@ -3423,7 +3417,6 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
     HIPCHK(hipMemsetAsync(d.hset, 0xff, (size_t)(d.hmask + 1) * sizeof(uint64_t), s));
     hipLaunchKernelGGL(k_dedupe, dim3(grid_for(cnt, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, e, cnt,
                        insert ? 0 : 1);
-    hipLaunchKernelGGL(k_touch, dim3(grid_for(2 * cnt, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
     if (insert)
         hipLaunchKernelGGL(k_plan_growth, dim3(grid_for(2 * cnt, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
     HIPCHK(hipGetLastError());
