@@ -142,6 +142,110 @@ def cpu_baseline(build_edges, n, seconds_target):
             "rates": {"del": u_del / t_del, "mix": u_mix / t_mix}}
 
 
+def _baseline(value, unit, t_work, sample, **extra):
+    out = {"value": value, "unit": unit, "cores": 1, "kind": "oracle", "sample": sample,
+           "seconds": round(t_work, 2)}
+    out.update(extra)
+    return out
+
+
+def cpu_baseline_opt(st, n):
+    """The oracle at PLDSOpt levels (one core) over the first 8 build batches
+    of the same RMAT-20 stream (8e6 insertions into the growing graph)."""
+    import oracle as O
+    o = O.Oracle(n, 0.4, 3.0, -1)
+    u, t = 0, time.perf_counter()
+    for b in st.build[:8]:
+        assert o.insert(b) == 0
+        u += o.stats()["applied_ins"]
+    dt = time.perf_counter() - t
+    return _baseline(u / dt, "edge updates/s", dt,
+                     "oracle at PLDSOpt levels (one core), the stream's first 8 build batches of 1e6 insertions "
+                     "(the oracle has no stored post-build state at this level structure)")
+
+
+def cpu_baseline_static(eps):
+    """Algorithm 6's oracle (one core) on the RMAT-19 graph of the same
+    generator and edge factor (the RMAT-20 run takes it about 50 s; its cost
+    is linear in m per peel round)."""
+    import oracle.static_kcore as SKO
+    from paper_2106_03824_amd import workloads as W
+    scale = 19
+    e = W.rmat(scale, 16 * 2 ** scale, seed=1)
+    t = time.perf_counter()
+    SKO.static_approx_kcore(2 ** scale, e, eps)
+    dt = time.perf_counter() - t
+    return _baseline(len(e) / dt, "edges/s", dt,
+                     f"oracle (one core), Algorithm 6 at eps={eps} on the RMAT-19 graph of the same generator "
+                     f"and edge factor ({len(e)} edges); the RMAT-20 graph takes it about 50 s")
+
+
+def cpu_baseline_vertex(build_edges, n, vertex_batches, warmup):
+    """The oracle (one core) from the stored post-build state of the RMAT-20
+    stream, deleting the same vertex batches as the timed run (the warm-up
+    batches first, untimed)."""
+    import numpy as np
+    import oracle as O
+    import oracle.vertex as OV
+    if not os.path.exists(LEVELS):
+        return None
+    lv = np.load(LEVELS)["levels"].astype(np.int32)
+    o = O.Oracle(n, 0.4, 3.0)
+    if o.load_state(build_edges, lv) != 0:
+        return None
+    edges, secs = 0, 0.0
+    for i, vs in enumerate(vertex_batches):
+        m0 = o.m
+        t = time.perf_counter()
+        assert OV.delete_vertices(o, vs) == 0
+        dt = time.perf_counter() - t
+        if i >= warmup:
+            edges += m0 - o.m
+            secs += dt
+    return _baseline(edges / secs, "edges/s", secs,
+                     f"oracle (one core) loaded with the stored post-build state (load not timed), deleting the "
+                     f"timed run's {len(vertex_batches) - warmup} batches of 1e4 vertices after its warm-up batch; "
+                     f"the renumbering rebuild is left out")
+
+
+def cpu_baseline_orient():
+    """The oracle (one core) on the same stream recipe at RMAT-14 (batches
+    of 2^14, the 1:16 batch-to-graph ratio of the RMAT-20 run): one round of
+    insertion, deletion and mixed batches, each with its flips F and
+    oriented updates J; the build is not timed.  The oracle's F and J are
+    linear in m per batch (a 1e6 batch on RMAT-20 takes it over 3 minutes)."""
+    import oracle as O
+    import oracle.orient as OR
+    from paper_2106_03824_amd import workloads as W
+    scale, B = 14, 2 ** 14
+    st = W.RmatStream(scale, 16 * 2 ** scale, seed=1, build_batches=16, cfg=2)
+    o = O.Oracle(st.n, 0.4, 3.0)
+    for b in st.build:
+        assert o.insert(b) == 0
+    u, secs = 0, 0.0
+    for kind in ("ins", "del", "mix"):
+        if kind == "ins":
+            ins, dele = st.insert_batch(B), None
+        elif kind == "del":
+            ins, dele = None, st.delete_batch(B)
+        else:
+            ins, dele = st.mixed_batch(B)
+        lv0, e0 = o.levels(), o.edges()
+        t = time.perf_counter()
+        assert o.update(ins, dele) == 0
+        s = o.stats()
+        lv1, e1 = o.levels(), o.edges()
+        OR.flips(lv0, lv1, e0, e1)
+        a_ins, a_del = OR.applied_updates(e0, ins, dele)
+        OR.oriented_updates(lv0, lv1, a_ins, a_del)
+        secs += time.perf_counter() - t
+        u += s["applied_ins"] + s["applied_del"]
+    return _baseline(u / secs, "edge updates/s", secs,
+                     f"oracle (one core) on the same stream recipe at RMAT-14 (build not timed): one round of "
+                     f"{B}-update insertion, deletion and mixed batches, each with F and J (batch:graph 1:16 as "
+                     f"in the RMAT-20 run, whose F and J take the oracle over 3 minutes per batch)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +428,8 @@ def main():
     }
     if args.opt:
         out["invariants_hold"] = g.check() == 0   # no stored oracle trace for this level structure
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_opt(st, n)
     elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -539,13 +645,19 @@ def run_vertex(args, P, W, torch, np):
         "rebuild": {"vertices": n2, "edges": m_now, "ms": t_rb * 1e3, "edges_per_s": m_now / t_rb,
                     "invariants_hold": ok},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_vertex(st_edges_after_build(st), n, [b.cpu().numpy() for b in batches],
+                                                  args.warmup)
     print(json.dumps(out), flush=True)
 
 
 def run_static(args, P, W, torch, np):
     """Algorithm 6 on the RMAT-20 graph of the default run (after its 16
     build batches): `value` is edges per second of one static run at the
-    first eps; the others are reported beside it."""
+    first eps; the others are reported beside it.  The roofline is the relax
+    kernel's over the timed runs at the first eps: per adjacency slot 4 bytes
+    of neighbour id and 4 of its bucket (2m slots per run), per count update
+    of an alive neighbour 8 bytes."""
     scale = 20
     m0 = 16 * 2 ** scale
     dev = torch.device("cuda", 0)
@@ -557,9 +669,15 @@ def run_static(args, P, W, torch, np):
     m = g.info()["m"]
     out_t = torch.empty(n, dtype=torch.float64, device=dev)
     res = {}
+    roof = None
     for eps in args.static_eps:
         for _ in range(args.warmup):
             P.plds_static_kcore(g.h, eps, out_t)
+        # the relax kernel is timed in the runs at the first eps (the value's)
+        first = eps == args.static_eps[0]
+        if first:
+            P.plds_set_timing(g.h, "sk_relax")
+        s0 = g.stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -567,6 +685,18 @@ def run_static(args, P, W, torch, np):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         s = g.stats()
+        if first:
+            P.plds_set_timing(g.h, 0)
+            launches = s["timed_launches"] - s0["timed_launches"]
+            ms = s["timed_ms"] - s0["timed_ms"]
+            alg = s["alg_bytes_peel"] - s0["alg_bytes_peel"]
+            if launches > 0 and ms > 0:
+                per = alg / launches
+                ach = per / (ms / launches * 1e-3) / 1e9
+                roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_sk_relax",
+                        "avg_launch_us": round(ms / launches * 1e3, 3), "launches": launches,
+                        "alg_bytes_per_launch": round(per, 1)}
         est = out_t.cpu().numpy()
         res[eps] = {"ms": dt * 1e3, "edges_per_s": m / dt, "host_syncs": s["host_syncs"],
                     "distinct_estimates": int(np.unique(est).size), "max_estimate": float(est.max())}
@@ -578,7 +708,10 @@ def run_static(args, P, W, torch, np):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"rmat{scale}-ef16-static-kcore", "n": n, "m": m, "eps": e0},
         "per_eps": {str(k): v for k, v in res.items()},
+        "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_static(e0)
     print(json.dumps(out), flush=True)
 
 
@@ -675,6 +808,8 @@ def run_orient(args, P, W, torch, np):
         "searched_edges_per_batch": tot["searched"] / nb, "orientation_ms_per_batch": tot["out_s"] / nb * 1e3,
         "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_orient()
     print(json.dumps(out), flush=True)
 
 

@@ -73,7 +73,10 @@ typedef struct {
                               level write (the paper's U[v] scan model)                 */
     int64_t timed_launches;/* launches of the kernel selected by plds_set_timing         */
     double timed_ms;       /* their summed duration in ms, from HIP events on `stream`   */
-    int64_t reserved;
+    int64_t alg_bytes_peel;/* algorithmic bytes of the static peeling's relax kernel, summed
+                              over plds_static_kcore calls: 8 per adjacency slot (id and
+                              bucket; 2m per call), 8 per count update of an alive
+                              neighbour of a peeled vertex                              */
 } plds_stats_t;
 
 /* Create an empty structure on the current HIP device: all n vertices at
@@ -274,7 +277,7 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode);
 /* Time one kernel (0 = off, 1 = insertion scan (which also finishes the
  * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
  * preparation, 5 = the edge scan of plds_flips, 6 = the cooperative
- * insertion sweep).  Each launch of that kernel carries a HIP event pair that the
+ * insertion sweep, 7 = the relax kernel of plds_static_kcore).  Each launch of that kernel carries a HIP event pair that the
  * runtime stamps at the dispatch's own start and end (hipExtLaunchKernel);
  * the cooperative sweep has events recorded around it on the stream.
  * While kind 1 or 4 is timed, insertion steps are launched one by one

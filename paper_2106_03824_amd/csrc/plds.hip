@@ -122,6 +122,7 @@ struct Ctl {
     int32_t sk_t, sk_bp, sk_peels, sk_round, sk_done, sk_nT;
     int32_t sk_ncl[4];    // the round's peeled vertices by slab class
     int64_t sk_alive;
+    int64_t sk_relaxed;   // count decrements of alive neighbours (sum of r over the rounds)
     // vertex deletion: incident edges counted, then gathered
     int64_t vd_deg, vd_n;
     int32_t viol_del0;    // the deletion sweep's first candidates (Invariant-2 violators)
@@ -2741,10 +2742,13 @@ __global__ void k_sk_fix(Dev d, SK k) {
     const int32_t t = c->sk_t, nt = min(c->sk_nT, d.n);
     const int32_t floor_t = t >= 1 ? (int32_t)ceil(k.pw[t - 1]) : 1;
     const int stride = gridDim.x * blockDim.x;
+    int64_t relaxed = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) {
         const int32_t w = k.T[i];
         const int32_t ob = k.B[w];
-        const int32_t cw = max(k.C[w] - k.r[w], floor_t);
+        const int32_t rw = k.r[w];
+        const int32_t cw = max(k.C[w] - rw, floor_t);
+        relaxed += rw;
         k.C[w] = cw;
         k.r[w] = 0;
         const int32_t nb = max(sk_bucket(k, cw), t);
@@ -2754,6 +2758,9 @@ __global__ void k_sk_fix(Dev d, SK k) {
             atomicAdd(&hist[nb], 1);
         }
     }
+    relaxed = wave_sum64(relaxed);
+    if (threadIdx.x % kWave == 0 && relaxed)
+        atomicAdd((unsigned long long *)&d.ctl->sk_relaxed, (unsigned long long)relaxed);
     sk_flush_hist(k, hist);
 }
 
@@ -4211,7 +4218,8 @@ int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
     HIPCHK(hipMemcpyAsync(h->sk_pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(h->sk_cnt, 0, kSkBuckets * sizeof(int32_t), s));
     h->h_ctl->sk_alive = 0;
-    HIPCHK(hipMemcpyAsync(&d.ctl->sk_alive, &h->h_ctl->sk_alive, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    h->h_ctl->sk_relaxed = 0;
+    HIPCHK(hipMemcpyAsync(&d.ctl->sk_alive, &h->h_ctl->sk_alive, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
     const size_t hist = (size_t)k.nbk * sizeof(int32_t);
     hipLaunchKernelGGL(k_sk_init, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
     hipLaunchKernelGGL(k_sk_first, dim3(1), dim3(kBlock), 0, s, d, k);
@@ -4227,8 +4235,7 @@ int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
         }
         for (int i = 0; i < run; i++) {
             hipLaunchKernelGGL(k_sk_peel, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, k);
-            hipLaunchKernelGGL(k_sk_relax, dim3(grid_for((int64_t)h->n * kWave, kBlock, 2048)), dim3(kBlock), 0, s,
-                               d, k);
+            tlaunch(h, 7, k_sk_relax, dim3(grid_for((int64_t)h->n * kWave, kBlock, 2048)), dim3(kBlock), 0, s, d, k);
             hipLaunchKernelGGL(k_sk_fix, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
             hipLaunchKernelGGL(k_sk_next, dim3(1), dim3(kBlock), 0, s, d, k);
         }
@@ -4236,8 +4243,13 @@ int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
+        take_timing(h, h->ev_used);
         run = std::min(run * 2, 256);
     }
+    // the relax kernel's algorithmic bytes: every vertex's adjacency is read
+    // once (4-byte id and 4-byte bucket per slot of its 2m), plus an 8-byte
+    // count update per alive neighbour of a peeled vertex
+    h->stats.alg_bytes_peel += 16 * h->m + 8 * h->h_ctl->sk_relaxed;
     return check_err(h);
 }
 
@@ -4364,7 +4376,7 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode) {
 }
 
 int plds_set_timing(plds_t *h, int32_t kernel) {
-    if (!h || kernel < 0 || kernel > 6) return PLDS_EINVAL;
+    if (!h || kernel < 0 || kernel > 7) return PLDS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
     if (kernel && h->ev.empty()) {
         h->ev.assign(2 * kEvPairs, nullptr);
