@@ -598,7 +598,10 @@ def run_vertex(args, P, W, torch, np):
     batches of 1e4 uniform random vertex deletions (each a batch of its edges'
     deletions), then a rebuild that renumbers the vertices left with edges
     consecutively.  `value` is deleted edges per second over the timed
-    vertex-deletion batches."""
+    vertex-deletion batches.  The roofline is the deletion list's
+    application (the largest kernel of a vertex batch): 56 bytes per applied
+    deletion (the pair, both endpoints' slab tombstones, levels and
+    counters)."""
     scale = 20
     m0 = 16 * 2 ** scale
     dev = torch.device("cuda", 0)
@@ -612,7 +615,10 @@ def run_vertex(args, P, W, torch, np):
                for _ in range(args.warmup + args.steps)]
     torch.cuda.synchronize()
     edges, secs = 0, 0.0
+    t_launches, t_ms, t_applied = 0, 0.0, 0
     for i, vs in enumerate(batches):
+        if i == args.warmup:
+            P.plds_set_timing(g.h, "apply_del")
         m_before = g.info()["m"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -623,6 +629,19 @@ def run_vertex(args, P, W, torch, np):
         if i >= args.warmup:
             edges += k
             secs += dt
+            s = g.stats()
+            t_launches += s["timed_launches"]
+            t_ms += s["timed_ms"]
+            t_applied += s["applied_del"]
+    P.plds_set_timing(g.h, 0)
+    roof = None
+    if t_launches and t_ms > 0:
+        per = 56 * t_applied / t_launches
+        ach = per / (t_ms / t_launches * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_apply_del",
+                "avg_launch_us": round(t_ms / t_launches * 1e3, 3), "launches": t_launches,
+                "alg_bytes_per_launch": round(per, 1)}
     deg = g.degrees()
     keep = deg > 0
     relabel = torch.full((n,), -1, dtype=torch.int32, device=dev)
@@ -644,6 +663,7 @@ def run_vertex(args, P, W, torch, np):
                    "lambda": 3.0},
         "rebuild": {"vertices": n2, "edges": m_now, "ms": t_rb * 1e3, "edges_per_s": m_now / t_rb,
                     "invariants_hold": ok},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_vertex(st_edges_after_build(st), n, [b.cpu().numpy() for b in batches],

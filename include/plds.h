@@ -277,7 +277,8 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode);
 /* Time one kernel (0 = off, 1 = insertion scan (which also finishes the
  * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
  * preparation, 5 = the edge scan of plds_flips, 6 = the cooperative
- * insertion sweep, 7 = the relax kernel of plds_static_kcore).  Each launch of that kernel carries a HIP event pair that the
+ * insertion sweep, 7 = the relax kernel of plds_static_kcore, 8 = the
+ * application of a deletion list).  Each launch of that kernel carries a HIP event pair that the
  * runtime stamps at the dispatch's own start and end (hipExtLaunchKernel);
  * the cooperative sweep has events recorded around it on the stream.
  * While kind 1 or 4 is timed, insertion steps are launched one by one

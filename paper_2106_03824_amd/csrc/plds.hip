@@ -125,6 +125,7 @@ struct Ctl {
     int64_t sk_relaxed;   // count decrements of alive neighbours (sum of r over the rounds)
     // vertex deletion: incident edges counted, then gathered
     int64_t vd_deg, vd_n;
+    int32_t vd_ncl[4];    // the listed vertices by slab class
     int32_t viol_del0;    // the deletion sweep's first candidates (Invariant-2 violators)
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
@@ -2812,33 +2813,73 @@ __global__ void k_vd_deg(Dev d, const int32_t *vs, int64_t cnt) {
     if (threadIdx.x % kWave == 0 && sum) atomicAdd((unsigned long long *)&d.ctl->vd_deg, (unsigned long long)sum);
 }
 
-// Every edge of the listed vertices as a pair (v, w), a wavefront per vertex;
-// each wavefront appends a slab's 64 slots with one atomic.
-__global__ void k_vd_gather(Dev d, const int32_t *vs, int64_t cnt, int32_t *out, int64_t cap) {
-    const int lane = threadIdx.x % kWave;
-    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < cnt; i += nw) {
-        const int32_t v = vs[i];
-        const int32_t cv = d.cap[v];
-        const int32_t *sl = d.pool + d.off[v];
-        for (int32_t e0 = 0; e0 < cv; e0 += kWave) {
-            const int32_t e = e0 + lane;
-            const int32_t w = e < cv ? sl[e] : -1;
-            const uint64_t m = __ballot(w >= 0);
-            unsigned long long base = 0;
-            if (lane == 0 && m) base = atomicAdd((unsigned long long *)&d.ctl->vd_n, (unsigned long long)__popcll(m));
-            base = __shfl(base, 0, kWave);
-            const int64_t at = (int64_t)base + __popcll(m & ((1ull << lane) - 1));
-            if (w >= 0) {
-                if (at < cap) {
-                    out[2 * at] = v;
-                    out[2 * at + 1] = w;
-                } else {
-                    latch(d.ctl, kErrLevel);
-                }
+// The listed vertices by slab class (d.mv, d.mv1; counts vd_ncl), for a
+// list of at most n entries (repeats included), so that two class lists
+// sharing an array never meet.
+__global__ void k_vd_classify(Dev d, const int32_t *vs, int64_t cnt) {
+    __shared__ SlabQ q;
+    slabq_init(q);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t ib = (int64_t)blockIdx.x * blockDim.x; ib < cnt; ib += stride) {
+        const int64_t i = ib + threadIdx.x;
+        const int cls = i < cnt ? slab_class(d.cap[vs[i]]) : -1;
+        slabq_push(q, cls, i < cnt ? vs[i] : -1);
+        slabq_flush(q, blockDim.x, d.mv, d.mv1, d.ctl->vd_ncl, d.n, d.ctl);
+    }
+    slabq_flush(q, kSlabQ, d.mv, d.mv1, d.ctl->vd_ncl, d.n, d.ctl);
+}
+
+// Every edge of the listed vertices as a pair (v, w): the slabs are visited
+// by slab class (classified lists) or a wavefront per vertex (`vs`, when the
+// list is longer than n).  Each wavefront stages its pairs in LDS and appends
+// them with one atomic per kVdStage; same-address atomics serialise, so the
+// grid is kept to about a thousand wavefronts.
+constexpr int kVdStage = 256;
+constexpr int kVdGrid = 256;
+__global__ void __launch_bounds__(kBlock) k_vd_gather(Dev d, const int32_t *vs, int64_t cnt, int32_t *out,
+                                                      int64_t cap) {
+    __shared__ int32_t buf[kBlock / kWave][2 * (kVdStage + kWave)];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    int32_t *b = buf[wv];
+    int32_t nb = 0;   // wave-uniform
+    auto flush = [&]() {
+        __threadfence_block();   // the wavefront's staged pairs are visible to all its lanes
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long *)&d.ctl->vd_n, (unsigned long long)nb);
+        base = __shfl(base, 0, kWave);
+        for (int i = lane; i < 2 * nb; i += kWave)
+            if ((int64_t)base + i / 2 < cap) out[2 * base + i] = b[i];
+        if (lane == 0 && (int64_t)base + nb > cap) latch(d.ctl, kErrLevel);
+        nb = 0;
+    };
+    // one slot (w < 0: none) of v's slab; every lane of the wavefront calls it together
+    auto slot = [&](int32_t v, int2, int32_t w, int32_t) {
+        const uint64_t m = __ballot(w >= 0);
+        if (w >= 0) {
+            const int k = nb + __popcll(m & ((1ull << lane) - 1));
+            b[2 * k] = v;
+            b[2 * k + 1] = w;
+        }
+        nb += __popcll(m);
+        if (nb >= kVdStage) flush();
+    };
+    if (!vs) {
+        visit_slabs(
+            d, d.mv, d.mv1, d.ctl->vd_ncl, [](int32_t) { return make_int2(0, 0); }, [](int32_t) { return 0; },
+            slot);
+    } else {
+        const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+        for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < cnt; i += nw) {
+            const int32_t v = vs[i];
+            const int32_t cv = d.cap[v];
+            const int32_t *sl = d.pool + d.off[v];
+            for (int32_t e0 = 0; e0 < cv; e0 += kWave) {
+                const int32_t e = e0 + lane;
+                slot(v, make_int2(0, 0), e < cv ? sl[e] : -1, 0);
             }
         }
     }
+    if (nb) flush();
 }
 
 // A rebuild's edge list through the renumbering: an edge with a dropped end
@@ -3459,7 +3500,7 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
         }
         hipLaunchKernelGGL(k_apply_ins, dim3(grid_for(*applied)), dim3(kBlock), 0, s, d);
     } else {
-        hipLaunchKernelGGL(k_apply_del, dim3(grid_for(*applied)), dim3(kBlock), 0, s, d);
+        tlaunch(h, 8, k_apply_del, dim3(grid_for(*applied)), dim3(kBlock), 0, s, d);
     }
     HIPCHK(hipGetLastError());
     h->m += insert ? *applied : -*applied;
@@ -3980,6 +4021,7 @@ int run_update_body(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *d
         rc = sync_ctl(h, s);
         if (rc) return rc;
     }
+    take_timing(h, h->ev_used);   // launches timed since the last collection (complete by now)
     return check_err(h);
 }
 
@@ -4262,8 +4304,10 @@ int plds_delete_vertices(plds_t *h, const int32_t *vertices, int64_t count, void
     if (count == 0) return plds_update(h, nullptr, 0, nullptr, 0, stream);
     h->h_ctl->err = 0;
     h->h_ctl->vd_deg = h->h_ctl->vd_n = 0;
+    for (int c = 0; c < 4; c++) h->h_ctl->vd_ncl[c] = 0;
     HIPCHK(hipMemcpyAsync(&d.ctl->err, &h->h_ctl->err, sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(&d.ctl->vd_deg, &h->h_ctl->vd_deg, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.ctl->vd_ncl, h->h_ctl->vd_ncl, sizeof(h->h_ctl->vd_ncl), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_vd_deg, dim3(grid_for(count, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, vertices, count);
     HIPCHK(hipGetLastError());
     rc = sync_ctl(h, s);
@@ -4283,8 +4327,13 @@ int plds_delete_vertices(plds_t *h, const int32_t *vertices, int64_t count, void
         h->vd_cap = k;
     }
     if (k) {
-        hipLaunchKernelGGL(k_vd_gather, dim3(grid_for(count * kWave, kBlock, 2048)), dim3(kBlock), 0, s, d, vertices,
-                           count, h->vd_buf, k);
+        // sorted by slab class when the list fits the class lists (ids are in range by now)
+        const bool by_class = count <= h->n;
+        if (by_class)
+            hipLaunchKernelGGL(k_vd_classify, dim3(grid_for(count, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d,
+                               vertices, count);
+        hipLaunchKernelGGL(k_vd_gather, dim3(grid_for(count * kWave, kBlock, kVdGrid)), dim3(kBlock), 0, s, d,
+                           by_class ? nullptr : vertices, count, h->vd_buf, k);
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
@@ -4376,7 +4425,7 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode) {
 }
 
 int plds_set_timing(plds_t *h, int32_t kernel) {
-    if (!h || kernel < 0 || kernel > 7) return PLDS_EINVAL;
+    if (!h || kernel < 0 || kernel > 8) return PLDS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
     if (kernel && h->ev.empty()) {
         h->ev.assign(2 * kEvPairs, nullptr);

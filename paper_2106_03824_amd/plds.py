@@ -37,7 +37,8 @@ class plds_stats_t(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS[:-2]] + [("timed_ms", ctypes.c_double),
                                                                    ("alg_bytes_peel", ctypes.c_int64)]
 
-TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "flip_scan": 5, "ins_sweep": 6, "sk_relax": 7}
+TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "flip_scan": 5, "ins_sweep": 6, "sk_relax": 7,
+                 "apply_del": 8}
 
 
 _lib = None

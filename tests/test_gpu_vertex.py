@@ -62,6 +62,31 @@ def test_delete_vertices_matches_oracle():
     same_state(g, o)
 
 
+def test_delete_vertices_every_slab_class_and_long_list():
+    """Deleted vertices of every slab size (hubs of several thousand slots,
+    mid-size slabs, slabs of 8 and 16), and a list longer than n with
+    repeats (gathered a wavefront per listed vertex)."""
+    n = 2 ** 13
+    rng = np.random.default_rng(21)
+    e = [(h, v) for h in (0, 1) for v in range(2, n) if rng.random() < 0.8]
+    e += [(v, int(x)) for v in range(2, 30) for x in rng.integers(30, n, size=300)]
+    e += [(int(a), int(b)) for a, b in rng.integers(30, n, size=(4 * n, 2))]
+    e = np.array(e, dtype=np.int32)
+    say("delete vertices: slab classes")
+    g, o = lib().PLDS(n), O.Oracle(n)
+    assert g.insert(e) == 0 and o.insert(e) == 0
+    vs = np.concatenate([[0, 1], np.arange(2, 12), rng.integers(30, n, 400)]).astype(np.int32)
+    assert g.delete_vertices(vs) == 0
+    assert OV.delete_vertices(o, vs) == 0
+    same_state(g, o)
+    say("delete vertices: a list longer than n")
+    vs2 = rng.integers(0, n, 3 * n).astype(np.int32)
+    assert g.delete_vertices(vs2) == 0
+    assert OV.delete_vertices(o, vs2) == 0
+    same_state(g, o)
+    assert g.stats()["applied_del"] == o.stats()["applied_del"]
+
+
 def test_rebuild_grows_and_keeps_ids():
     n = 3000
     e = W.er(n, 10.0 / n, seed=2)
