@@ -2378,7 +2378,9 @@ __device__ void visit_slabs(const Dev &d, const int32_t *lo, const int32_t *hi, 
     const int lane = threadIdx.x % kWave;
     const int nw = gridDim.x * blockDim.x / kWave;
     const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int32_t nn = d.n, n0 = cnt[0], n1 = cnt[1], n2 = cnt[2], n3 = cnt[3];
+    // (the counts never exceed n by construction; clamped so that a list
+    // read from the back of its array stays inside it in any case)
+    const int32_t nn = d.n, n0 = min(cnt[0], nn), n1 = min(cnt[1], nn), n2 = min(cnt[2], nn), n3 = min(cnt[3], nn);
     // kSlabChunk * 64 slots of u's slab from slot e0
     auto chunk = [&](int32_t u, int2 hu, const int32_t *sl, int32_t cu, int32_t e0) {
         int32_t w[kSlabChunk];
