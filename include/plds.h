@@ -263,14 +263,17 @@ int plds_stats(const plds_t *h, plds_stats_t *out);
  * scanned), the movers landing at l. */
 int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
 
-/* How the insertion level loop runs: 0 = the whole loop in one cooperative
- * launch with grid barriers between its parts (when the device supports it,
- * else as 2); 1 (default) = one kernel per part, with climbing steps (a large
- * group of movers climbing level after level is kept flagged, and only the
- * vertices it leaves behind and the residents of the next two levels scan
- * their slabs); 2 = one kernel per part, every step scanning its movers'
- * slabs; 3 = as 1, with climbing steps for groups of any size (not only
- * large ones), which exercises them on small graphs.  Results are
+/* How the level loops run.  Insertions: 0 = the whole loop in one
+ * cooperative launch with grid barriers between its parts (when the device
+ * supports it, else as 2); 1 (default) = one kernel per part, with climbing
+ * steps (a large group of movers climbing level after level is kept flagged,
+ * and only the vertices it leaves behind and the residents of the next two
+ * levels scan their slabs); 2 = one kernel per part, every step scanning its
+ * movers' slabs; 3 = as 1, with climbing steps for groups of any size (not
+ * only large ones), which exercises them on small graphs.  Deletions: the
+ * steps run in one single-block kernel, a step with more than 2^14 pending
+ * vertices or 2^15 slab slots of movers by the grid kernels; in mode 2 every
+ * step (with any slab slots) goes to the grid kernels.  Results are
  * identical. */
 int plds_set_sweep_mode(plds_t *h, int32_t mode);
 
@@ -278,7 +281,7 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode);
  * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
  * preparation, 5 = the edge scan of plds_flips, 6 = the cooperative
  * insertion sweep, 7 = the relax kernel of plds_static_kcore, 8 = the
- * application of a deletion list).  Each launch of that kernel carries a HIP event pair that the
+ * application of a deletion list, 9 = the single-block deletion loop).  Each launch of that kernel carries a HIP event pair that the
  * runtime stamps at the dispatch's own start and end (hipExtLaunchKernel);
  * the cooperative sweep has events recorded around it on the stream.
  * While kind 1 or 4 is timed, insertion steps are launched one by one

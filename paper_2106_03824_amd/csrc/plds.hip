@@ -129,6 +129,9 @@ struct Ctl {
     int32_t viol_del0;    // the deletion sweep's first candidates (Invariant-2 violators)
     int32_t n_cand;       // initial candidates
     int32_t step_id;      // deletion step counter (stamps)
+    int32_t del_big;      // the current deletion step is run by the grid kernels (too large for one block)
+    int32_t n_big;        // violators with large slabs, listed for the block pass of the desire-levels
+    int32_t big_steps;    // deletion steps of the current sweep run by the grid kernels
     int32_t phys;         // level the movers of the current insertion step sit at
     int32_t jump;         // 1 if they land at l+1 from below l (a multi-level step)
     int64_t grow_req;     // slots requested by regrowth
@@ -183,6 +186,7 @@ struct Dev {
     // climbing steps
     int32_t climb_ok;                 // climbing steps allowed (plain handle, per-part kernels)
     int32_t climb_min;                // smallest group that enters a climbing step
+    int32_t loop_slots;               // most slab slots of a deletion step run by the single-block loop
     int32_t *lvb_start;               // [K+2] vertices with edges, bucketed by level at the sweep start
     int32_t *lvb_fill;                // [K+2]
     int32_t *lvb;                     // [n]
@@ -2005,53 +2009,173 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
 
 // ------------------------------------------------------ deletion sweep
 // Desire-level (Def. desire-level) of an Invariant-2 violator w at level lw:
-// the largest l' in [1, lw-1] with cnt(l'-1) >= dn_min[(l'-1)/L], where
+// the largest l' in [1, lw-1] with cnt(l'-1) >= dn_min[gn(l'-1)], where
 // cnt(j) = #neighbours at level >= j; 0 if there is none.  Such an l' also
 // satisfies Invariant 1 (the count one level up is below dn_min <= up_max).
-// One block per vertex: histogram of neighbour levels in LDS (bins 0..lw-1,
-// the top bin holding every level >= lw-1), then a suffix scan.
-__device__ int32_t block_dl(Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_t *seg, int32_t *red) {
-    int tid = threadIdx.x, nt = blockDim.x;
-    const GP pw = gp(d, w);
-    int32_t nb = lw;
-    for (int i = tid; i < nb; i += nt) hist[i] = 0;
-    __syncthreads();
-    int32_t cap = d.cap[w];
+//
+// cnt(j) never grows with j and dn_min[gn(j)] never shrinks, so the test
+// cnt(j) >= dn_min[gn(j)] holds on a prefix of [0, lw-2]: the answer is one
+// more than the last j of that prefix, found by binary search.  It holds at
+// j = 0 whenever w has a neighbour (dn_min[0] = 1), and fails above the
+// highest neighbour level.  Each probe counts the neighbours at level >= j,
+// so the work is O(deg(w) log lw), independent of how many levels lie below
+// w.  Neighbour levels are clamped to lw-1 (a probe never exceeds lw-2).
+
+constexpr int kDlRegs = 8;                       // slab slots per lane kept in registers
+constexpr int32_t kDlWaveCap = kDlRegs * kWave;  // slabs of up to 512 slots take one wavefront
+
+// One wavefront (every lane calls it; w is wave-uniform, cap = d.cap[w] <= kDlWaveCap).
+__device__ int32_t wave_dl(const Dev &d, int32_t w, int32_t lw, int32_t cap) {
+    const int lane = threadIdx.x % kWave;
+    const GP p = gp(d, w);
     const int32_t *s = d.pool + d.off[w];
-    for (int32_t e = tid; e < cap; e += nt) {
-        int32_t x = s[e];
-        if (x >= 0) atomicAdd(&hist[min(d.level[x], lw - 1)], 1);
+    const int nr = (cap + kWave - 1) / kWave;
+    int32_t x[kDlRegs], y[kDlRegs];
+#pragma unroll
+    for (int r = 0; r < kDlRegs; r++) {
+        const int32_t e = r * kWave + lane;
+        x[r] = (r < nr && e < cap) ? s[e] : -1;
     }
+    int32_t ymax = -1;
+#pragma unroll
+    for (int r = 0; r < kDlRegs; r++) {
+        y[r] = x[r] >= 0 ? min(d.level[x[r]], lw - 1) : -1;
+        ymax = max(ymax, y[r]);
+    }
+    ymax = wave_max(ymax);
+    int32_t lo = 0, hi = min(lw - 2, ymax);
+    if (hi < 0) return 0;   // no neighbour, or lw = 1
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        int32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < kDlRegs; r++)
+            if (r < nr) c += __popcll(__ballot(y[r] >= mid));
+        if (c >= d.dn_min[p.tab + mid / p.L]) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo + 1;
+}
+
+// Block-wide sums and maxima (every thread calls them; red holds one int per
+// wavefront of the block).
+__device__ __forceinline__ int32_t block_sum32(int32_t x, int32_t *red) {
+    x = wave_sum(x);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = x;
     __syncthreads();
-    int per = (nb + nt - 1) / nt, lo = min(nb, tid * per), hi = min(nb, lo + per);
-    int32_t sum = 0;
-    for (int i = lo; i < hi; i++) sum += hist[i];
-    seg[tid] = sum;
+    int32_t t = 0;
+    for (int i = 0; i < (int)blockDim.x / kWave; i++) t += red[i];
     __syncthreads();
-    if (tid == 0) {   // exclusive suffix sums of the segments
-        int32_t acc = 0;
-        for (int t = nt - 1; t >= 0; t--) {
-            int32_t x = seg[t];
-            seg[t] = acc;
-            acc += x;
+    return t;
+}
+__device__ __forceinline__ int32_t block_max32(int32_t x, int32_t *red) {
+    x = wave_max(x);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = x;
+    __syncthreads();
+    int32_t t = INT32_MIN;
+    for (int i = 0; i < (int)blockDim.x / kWave; i++) t = max(t, red[i]);
+    __syncthreads();
+    return t;
+}
+
+// The whole block, for a slab of any size (block-uniform call): a
+// segmented histogram of the neighbour levels in LDS.  A pass counts the
+// neighbours whose (clamped) level falls in a window of values [a, a+span),
+// in at most kDlBins bins of width W; suffix sums of the bins plus the
+// neighbours above the window give cnt() at every bin start, and the last
+// bin start where the test holds brackets the answer within W levels.  The
+// next pass refines that bin, until W = 1: one pass while lw <= nbins, two
+// up to nbins^2 levels.  hist: LDS [nbins]; sh: LDS of at least
+// blockDim/kWave + 2 ints.
+constexpr int32_t kDlBins = 2048;   // bins of the single-block deletion loop
+
+__device__ int32_t block_dl(const Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_t nbins, int32_t *sh) {
+    const int tid = threadIdx.x, nt = blockDim.x, nwv = blockDim.x / kWave;
+    if (lw < 2) return 0;   // block-uniform
+    const GP p = gp(d, w);
+    const int32_t cap = d.cap[w];
+    const int32_t *s = d.pool + d.off[w];
+    int32_t *sh_base = sh + nwv + 1;
+    // the first kDlRegs slots of each thread stay in registers (clamped
+    // levels) across the passes; the loads of a batch are issued together
+    int32_t y0[kDlRegs];
+    {
+        int32_t x[kDlRegs];
+#pragma unroll
+        for (int r = 0; r < kDlRegs; r++) {
+            const int32_t e = r * nt + tid;
+            x[r] = e < cap ? s[e] : -1;
         }
+#pragma unroll
+        for (int r = 0; r < kDlRegs; r++) y0[r] = x[r] >= 0 ? min(d.level[x[r]], lw - 1) : -1;
     }
-    __syncthreads();
-    int32_t best = -1, cnt = seg[tid];
-    for (int j = hi - 1; j >= lo; j--) {
-        cnt += hist[j];                       // cnt(j)
-        if (j <= lw - 2 && cnt >= dn_floor(d, pw, j + 1)) {
-            best = j;
-            break;
+    int32_t a = 0, span = lw, base = 0;
+    for (;;) {   // block-uniform
+        const int32_t nb = min(span, nbins);
+        const int32_t W = (span + nb - 1) / nb;
+        for (int i = tid; i < nb; i += nt) hist[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kDlRegs; r++) {
+            const int32_t y = y0[r] - a;
+            if (y0[r] >= 0 && y >= 0 && y < span) atomicAdd(&hist[y / W], 1);
         }
+        for (int32_t e0 = kDlRegs * nt; e0 < cap; e0 += kDlRegs * nt) {
+            int32_t x[kDlRegs];
+#pragma unroll
+            for (int r = 0; r < kDlRegs; r++) {
+                const int32_t e = e0 + r * nt + tid;
+                x[r] = e < cap ? s[e] : -1;
+            }
+#pragma unroll
+            for (int r = 0; r < kDlRegs; r++) {
+                if (x[r] < 0) continue;
+                const int32_t y = min(d.level[x[r]], lw - 1) - a;
+                if (y >= 0 && y < span) atomicAdd(&hist[y / W], 1);
+            }
+        }
+        __syncthreads();
+        // thread t owns the bins of segment nt-1-t, so that the exclusive
+        // prefix over threads counts the bins above its segment
+        const int32_t per = (nb + nt - 1) / nt;
+        const int32_t b0 = (nt - 1 - tid) * per, b1 = min(nb, b0 + per);
+        int32_t mine = 0;
+        for (int32_t b = b0; b < b1; b++) mine += hist[b];
+        int32_t tot;
+        int32_t cnt = block_excl(mine, &tot, sh) + base;
+        int32_t best = -1, above_best = 0;
+        for (int32_t b = b1 - 1; b >= b0; b--) {
+            const int32_t hb = hist[b];
+            cnt += hb;   // cnt(a + b*W)
+            const int32_t j = a + b * W;
+            if (j <= lw - 2 && cnt >= d.dn_min[p.tab + j / p.L]) {
+                best = b;
+                above_best = cnt - hb;
+                break;
+            }
+        }
+        const int32_t bmax = block_max32(best, sh);
+        if (bmax < 0) return 0;   // no neighbour (only possible in the first pass)
+        if (best == bmax) *sh_base = above_best;
+        __syncthreads();
+        base = *sh_base;
+        a += bmax * W;
+        __syncthreads();
+        if (W == 1) return a + 1;
+        span = W;
     }
-    int32_t wb = wave_max(best);
-    if (tid % kWave == 0) red[tid / kWave] = wb;
-    __syncthreads();
-    int32_t r = -1;
-    for (int i = 0; i < nt / kWave; i++) r = max(r, red[i]);
-    __syncthreads();
-    return r >= 0 ? r + 1 : 0;
+}
+
+__device__ __forceinline__ bool del_viol(const Dev &d, int32_t w, int32_t lw) {
+    return lw > 0 && d.ups[w] < dn_floor(d, gp(d, w), lw);
+}
+// A load that reads the device-coherent value (bypassing the compute unit's
+// L1): for counters that atomics of the same kernel have changed.
+__device__ __forceinline__ int32_t ld_dev(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool del_viol_dev(const Dev &d, int32_t w, int32_t lw) {
+    return lw > 0 && ld_dev(&d.ups[w]) < dn_floor(d, gp(d, w), lw);
 }
 
 // mode 0: seed from the endpoints of deleted edges (list = touch, pending
@@ -2086,31 +2210,69 @@ __global__ void k_del_cand(Dev d) {
 }
 
 // Desire-levels of the vertices of the recompute list that violate
-// Invariant 2, a block each (mode 0: the batch's candidates listed by
-// k_del_cand; mode 1: the neighbours a step's moves left violating).
-__global__ void k_dl(Dev d, int mode) {
-    extern __shared__ int32_t lds[];
-    int32_t *seg = lds, *red = lds + kBlock, *hist = lds + kBlock + 16;
+// Invariant 2 (mode 0: the batch's candidates listed by k_del_cand; mode 1:
+// the neighbours a step's moves left violating, when the step was too large
+// for the single-block loop).  A wavefront per vertex whose slab fits its
+// registers; then, in a second pass, a block per larger slab.
+__device__ __forceinline__ void dl_record(const Dev &d, Ctl *c, int32_t w, int32_t lw, int32_t dv, int32_t l,
+                                          int32_t *plist, int32_t *pn, int32_t *nm) {
+    if (dv <= l || dv >= lw) latch(c, kErrOrder);
+    if (d.dl[w] < 0) push(plist, pn, d.n, w, c);
+    d.dl[w] = dv;
+    atomicMin(nm, dv);
+}
+
+// A wavefront per listed vertex: violators whose slab fits the wavefront's
+// registers get their desire-level; larger ones are listed (the idle
+// cascade list casc1, counter n_big) for k_dl_big.
+__global__ void __launch_bounds__(kBlock) k_dl(Dev d, int mode) {
     Ctl *c = d.ctl;
-    int32_t cur = c->cur, tgt = mode == 0 ? cur : (cur ^ 1);
+    if (mode == 1 && (c->done || !c->del_big)) return;
+    const int32_t cur = c->cur, tgt = mode == 0 ? cur : (cur ^ 1);
     int32_t *plist = tgt ? d.p1 : d.p0;
-    int32_t cnt = c->n_rc;
-    const int32_t *list = d.rc;
-    int32_t l = mode == 0 ? -1 : c->l;
-    bool skip = mode == 1 && c->done;
+    const int32_t l = mode == 0 ? -1 : c->l;
+    const int lane = threadIdx.x % kWave;
     int32_t ncalc = 0;
-    for (int i = blockIdx.x; !skip && i < cnt; i += gridDim.x) {
-        int32_t w = list[i];
-        int32_t lw = d.level[w];
-        bool viol = lw > 0 && d.ups[w] < dn_floor(d, gp(d, w), lw);
-        if (!viol) continue;                  // block-uniform
-        int32_t dv = block_dl(d, w, lw, hist, seg, red);
+    const int32_t cnt = c->n_rc;
+    const int nw = gridDim.x * (kBlock / kWave);
+    for (int i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < cnt; i += nw) {   // wave-uniform
+        const int32_t w = d.rc[i];
+        const int32_t lw = d.level[w];
+        if (!del_viol(d, w, lw)) continue;
+        const int32_t cap = d.cap[w];
+        if (cap > kDlWaveCap) {
+            if (lane == 0) push(d.casc1, &c->n_big, d.n, w, c);
+            continue;
+        }
+        const int32_t dv = wave_dl(d, w, lw, cap);
         ncalc++;
+        if (lane == 0) dl_record(d, c, w, lw, dv, l, plist, &c->p_n[tgt], &c->nm);
+    }
+    if (lane == 0 && ncalc) atomicAdd((unsigned long long *)&c->dl_calcs, (unsigned long long)ncalc);
+}
+
+// A block of kBigBlock threads per listed violator with a large slab; its
+// histogram has one bin per level (min(K, kHistMax) bins of dynamic LDS), so
+// one pass over the slab usually suffices.
+constexpr int kBigBlock = 1024;
+constexpr int kBigGrid = 512;
+__global__ void __launch_bounds__(kBigBlock) k_dl_big(Dev d, int mode, int32_t nbins) {
+    extern __shared__ int32_t hist[];
+    __shared__ int32_t red[kBigBlock / kWave + 2];
+    Ctl *c = d.ctl;
+    if (mode == 1 && (c->done || !c->del_big)) return;
+    const int32_t cur = c->cur, tgt = mode == 0 ? cur : (cur ^ 1);
+    int32_t *plist = tgt ? d.p1 : d.p0;
+    const int32_t l = mode == 0 ? -1 : c->l;
+    const int32_t cnt = c->n_big;
+    int32_t ncalc = 0;
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {   // block-uniform
+        const int32_t w = d.casc1[i];
+        const int32_t lw = d.level[w];
+        const int32_t dv = block_dl(d, w, lw, hist, nbins, red);
         if (threadIdx.x == 0) {
-            if (dv <= l || dv >= lw) latch(c, kErrOrder);
-            if (d.dl[w] < 0) push(plist, &c->p_n[tgt], d.n, w, c);
-            d.dl[w] = dv;
-            atomicMin(&c->nm, dv);
+            ncalc++;
+            dl_record(d, c, w, lw, dv, l, plist, &c->p_n[tgt], &c->nm);
         }
     }
     if (threadIdx.x == 0 && ncalc) atomicAdd((unsigned long long *)&c->dl_calcs, (unsigned long long)ncalc);
@@ -2120,9 +2282,11 @@ __global__ void k_dl(Dev d, int mode) {
 // set the next level to the smallest pending desire-level.
 __global__ void k_del_next(Dev d, int mode) {
     Ctl *c = d.ctl;
-    if (mode == 1 && c->done) return;
+    if (mode == 1 && (c->done || !c->del_big)) return;
     if (mode == 1) {
         int32_t cur = c->cur;
+        c->del_big = 0;   // the next step goes back to the single-block loop
+        c->big_steps += 1;
         if (c->n_log < 4 * d.K) {
             int64_t *row = d.steplog + 4 * c->n_log++;
             row[0] = -1 - c->l;
@@ -2139,6 +2303,7 @@ __global__ void k_del_next(Dev d, int mode) {
         c->n_rc = 0;
         c->step_id += 1;
     }
+    c->n_big = 0;
     if (mode == 0) {
         c->n_rc = 0;   // the candidates' list has been read
         c->viol_del0 = c->p_n[c->cur];
@@ -2153,7 +2318,7 @@ __global__ void k_del_next(Dev d, int mode) {
 // vertices whose desire-level is l; the rest stay pending.
 __global__ void k_del_select(Dev d) {
     Ctl *c = d.ctl;
-    if (c->done) return;
+    if (c->done || !c->del_big) return;
     int32_t l = c->l, cur = c->cur, nxt = cur ^ 1, np = c->p_n[cur];
     const int32_t *P = cur ? d.p1 : d.p0;
     int32_t *Q = nxt ? d.p1 : d.p0;
@@ -2185,7 +2350,7 @@ __global__ void k_del_select(Dev d) {
 // counted on the way.
 __global__ void k_del_scan(Dev d) {
     Ctl *c = d.ctl;
-    if (c->done) return;
+    if (c->done || !c->del_big) return;
     int32_t l = c->l, nch = c->n_chunks, sid = c->step_id;
     int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     int nw = gridDim.x * blockDim.x / kWave;
@@ -2236,7 +2401,7 @@ __global__ void k_del_scan(Dev d) {
 // pending set.
 __global__ void k_del_fin(Dev d) {
     Ctl *c = d.ctl;
-    if (c->done) return;
+    if (c->done || !c->del_big) return;
     int32_t l = c->l, nmv = c->n_mv;
     int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmv; i += stride) {
@@ -2249,6 +2414,222 @@ __global__ void k_del_fin(Dev d) {
         d.stay[v] = 0;
         d.cnt2[v] = 0;
         d.dl[v] = -1;
+    }
+}
+
+// The deletion level loop of Algorithm 3 in one block, for steps that are
+// small (the usual case: a batch of deletions moves few vertices down, over
+// few levels, and each step of the grid kernels above would cost a chain of
+// five launches).  Each step is the same as select / scan / fin / k_dl /
+// k_del_next: the pending vertices whose desire-level is l move to l
+// together; their neighbours' up and up* counters drop; the neighbours left
+// violating Invariant 2 (and pending ones that lost a neighbour) get their
+// desire-levels recomputed; the next level is the smallest pending
+// desire-level.  A step whose pending list or movers' slabs exceed the
+// limits below is handed to the grid kernels (del_big), which run that one
+// step and hand the loop back.  Every step moves to a strictly higher level
+// (Lemma smaller-level), so at most K steps run; a desire-level that breaks
+// this latches kErrOrder and ends the loop.
+constexpr int kLoopBlock = 1024;
+constexpr int32_t kLoopPending = 2048;   // most pending vertices of a step run here
+constexpr int32_t kLoopSlots = 4096;     // most slab slots of a step's movers run here (d.loop_slots;
+                                         // 0 in sweep mode 2, which sends every step to the grid kernels)
+
+__global__ void __launch_bounds__(kLoopBlock) k_del_loop(Dev d) {
+    __shared__ int32_t red[kLoopBlock / kWave + 2];
+    __shared__ int32_t hist[kDlBins];
+    __shared__ int64_t red64[kLoopBlock / kWave];
+    __shared__ int32_t s_stop, s_l, s_cur, s_np, s_nmv, s_nq, s_nm, s_nrc, s_nbig, s_nsmall, s_calc, s_sid;
+    __shared__ unsigned long long s_scanned;
+    Ctl *c = d.ctl;
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    constexpr int nw = kLoopBlock / kWave;
+    if (tid == 0) {
+        s_stop = c->done || c->del_big || (ld_dev(&c->err) & kErrOrder);
+        s_l = c->l;
+        s_cur = c->cur;
+        s_np = c->p_n[c->cur];
+    }
+    __syncthreads();
+    for (int32_t steps = 0; !s_stop; steps++) {
+        const int32_t l = s_l, cur = s_cur, np = s_np;
+        const int32_t *P = cur ? d.p1 : d.p0;
+        int32_t *Q = cur ? d.p0 : d.p1;
+        // size of the step
+        int32_t nm = 0;
+        int64_t slots = 0;
+        if (np <= kLoopPending)
+            for (int i = tid; i < np; i += kLoopBlock) {
+                const int32_t v = P[i];
+                if (d.dl[v] == l) {
+                    nm++;
+                    slots += d.cap[v];
+                }
+            }
+        nm = block_sum32(nm, red);
+        slots = block_sum64(slots, red64);
+        if (np > kLoopPending || slots > d.loop_slots || steps > d.K) {
+            if (tid == 0) {
+                if (steps > d.K) latch(c, kErrOrder);   // cannot happen with exact desire-levels
+                else c->del_big = 1;
+            }
+            break;   // block-uniform
+        }
+        if (tid == 0) {
+            s_nmv = 0;
+            s_nq = c->p_n[cur ^ 1];
+            s_nm = kInf;
+            s_nrc = 0;
+            s_nbig = 0;
+            s_nsmall = 0;
+            s_calc = 0;
+            s_scanned = 0;
+            s_sid = c->step_id;
+        }
+        __syncthreads();
+        // select: movers to d.mv, the rest stay pending in Q
+        for (int i = tid; i < np; i += kLoopBlock) {
+            const int32_t v = P[i], dv = d.dl[v];
+            if (dv == l) {
+                d.mv[atomicAdd(&s_nmv, 1)] = v;
+            } else {
+                if (dv < l) latch(c, kErrOrder);
+                atomicMin(&s_nm, dv);
+                Q[atomicAdd(&s_nq, 1)] = v;
+            }
+        }
+        __syncthreads();
+        // scan: a wavefront per mover
+        const int32_t nmv = s_nmv, sid = s_sid;
+        for (int mi = wid; mi < nmv; mi += nw) {
+            const int32_t v = d.mv[mi];
+            const int32_t cap = d.cap[v], pv = d.level[v];
+            const int32_t *sl = d.pool + d.off[v];
+            int32_t cu = 0, cus = 0;
+            for (int32_t e0 = 0; e0 < cap; e0 += kWave) {
+                const int32_t e = e0 + lane;
+                const int32_t w = e < cap ? sl[e] : -1;
+                bool fresh = false;
+                if (w >= 0) {
+                    const int32_t dw = d.dl[w];
+                    if (dw == l) {
+                        cu++;
+                        cus++;
+                    } else {
+                        const int32_t lw = d.level[w];
+                        cu += lw >= l;
+                        cus += lw >= l - 1;
+                        bool again = dw >= 0;
+                        if (lw > l && lw <= pv) atomicSub(&d.up[w], 1);
+                        if (lw > l + 1 && lw <= pv + 1) {
+                            const int32_t old = atomicSub(&d.ups[w], 1);
+                            if (old == dn_floor(d, gp(d, w), lw)) again = true;
+                        }
+                        fresh = again && atomicExch(&d.rcstamp[w], sid) != sid;
+                    }
+                }
+                const uint64_t mask = __ballot(fresh);
+                if (mask) {
+                    int32_t base = 0;
+                    const int leader = __ffsll((unsigned long long)mask) - 1;
+                    if (lane == leader) base = atomicAdd(&s_nrc, __popcll(mask));
+                    base = __shfl(base, leader, kWave);
+                    if (fresh) d.rc[base + __popcll(mask & ((1ull << lane) - 1))] = w;
+                }
+            }
+            cu = wave_sum(cu);
+            cus = wave_sum(cus);
+            if (lane == 0) {
+                d.stay[v] = cu;
+                d.cnt2[v] = cus;
+                atomicAdd(&s_scanned, (unsigned long long)cap);
+            }
+        }
+        __syncthreads();
+        // fin: the movers take level l with their recounted degrees
+        for (int i = tid; i < nmv; i += kLoopBlock) {
+            const int32_t v = d.mv[i];
+            atomicSub(&d.occ[d.level[v]], 1);
+            atomicAdd(&d.occ[l], 1);
+            d.level[v] = l;
+            d.up[v] = d.stay[v];
+            d.ups[v] = d.cnt2[v];
+            d.stay[v] = 0;
+            d.cnt2[v] = 0;
+            d.dl[v] = -1;
+        }
+        __syncthreads();
+        // desire-levels of the recompute list: its violators are listed, a
+        // thread per entry, into the idle cascade lists (slabs that fit a
+        // wavefront's registers from the front of casc0, larger ones into
+        // casc1); then a wavefront per small slab and the whole block per
+        // larger one
+        const int32_t nrc = s_nrc;
+        for (int i = tid; i < nrc; i += kLoopBlock) {
+            const int32_t w = d.rc[i];
+            const int32_t lw = d.level[w];
+            if (!del_viol_dev(d, w, lw)) continue;
+            if (d.cap[w] > kDlWaveCap) d.casc1[atomicAdd(&s_nbig, 1)] = w;
+            else d.casc0[atomicAdd(&s_nsmall, 1)] = w;
+        }
+        __syncthreads();
+        const int32_t nsmall = s_nsmall;
+        for (int i = wid; i < nsmall; i += nw) {
+            const int32_t w = d.casc0[i];
+            const int32_t lw = d.level[w];
+            const int32_t dv = wave_dl(d, w, lw, d.cap[w]);
+            if (lane == 0) {
+                atomicAdd(&s_calc, 1);
+                if (dv <= l || dv >= lw) latch(c, kErrOrder);
+                if (d.dl[w] < 0) Q[atomicAdd(&s_nq, 1)] = w;
+                d.dl[w] = dv;
+                atomicMin(&s_nm, dv);
+            }
+        }
+        __syncthreads();
+        const int32_t nbig = s_nbig;
+        for (int i = 0; i < nbig; i++) {   // block-uniform
+            const int32_t w = d.casc1[i];
+            const int32_t lw = d.level[w];
+            const int32_t dv = block_dl(d, w, lw, hist, kDlBins, red);
+            if (tid == 0) {
+                s_calc++;
+                if (dv <= l || dv >= lw) latch(c, kErrOrder);
+                if (d.dl[w] < 0) Q[s_nq++] = w;
+                d.dl[w] = dv;
+                s_nm = min(s_nm, dv);
+            }
+        }
+        __syncthreads();
+        // close the step (as k_del_next)
+        if (tid == 0) {
+            if (c->n_log < 4 * d.K) {
+                int64_t *row = d.steplog + 4 * c->n_log++;
+                row[0] = -1 - l;
+                row[1] = -1;
+                row[2] = nmv;
+                row[3] = c->scanned + (int64_t)s_scanned;
+            }
+            c->scanned += (int64_t)s_scanned;
+            c->dl_calcs += s_calc;
+            c->sweeps += 1;
+            c->moves += nmv;
+            c->p_n[cur] = 0;
+            c->p_n[cur ^ 1] = s_nq;
+            c->cur = cur ^ 1;
+            c->n_mv = 0;
+            c->n_chunks = 0;
+            c->n_rc = 0;
+            c->step_id += 1;
+            const int32_t nxt = s_nm;
+            if (nxt == kInf) c->done = 1;
+            else c->l = nxt;
+            s_l = nxt;
+            s_cur = cur ^ 1;
+            s_np = s_nq;
+            s_stop = c->done || (ld_dev(&c->err) & kErrOrder);
+        }
+        __syncthreads();
     }
 }
 
@@ -3149,7 +3530,8 @@ struct plds {
     hipGraph_t del_graph = nullptr;
     hipGraphExec_t del_exec = nullptr;
     Dev del_graph_dev{};
-    int64_t del_steps_hint = 0;   // steps of the last deletion sweep
+    int64_t del_steps_hint = 0;   // steps of the last deletion sweep run by the grid kernels
+    int32_t dl_nbins = 0;         // bins argument of the step graph's large-slab desire-level kernel
     // orientation tracking: the last update call's starting levels and its
     // applied updates (pairs (min, max))
     int32_t lpg = 0;              // levels_per_group as given at create
@@ -3411,6 +3793,9 @@ int ctl_reset_batch(plds *h, hipStream_t s) {
     c->n_sl[0] = c->n_sl[1] = 0;
     c->n_cw[0] = c->n_cw[1] = 0;
     c->step_dec[0] = c->step_dec[1] = 0;
+    c->del_big = 0;
+    c->n_big = 0;
+    c->big_steps = 0;
     c->sum_up = 0;
     c->sweeps = c->moves = c->scanned = c->dl_calcs = 0;
     c->alg_U = c->alg_up1 = 0;
@@ -3550,10 +3935,14 @@ int ins_graph(plds *h) {
 
 constexpr int kDelGraphSteps = 4;
 
-// The deletion step sequence (select, scan, fin, desire-levels, next) x
-// kDelGraphSteps as one graph of kernel nodes, rebuilt when the device
-// buffers move.
-int del_graph(plds *h, size_t lds) {
+// bins of the large-slab desire-level histogram: one per level when the
+// handle has at most kHistMax levels
+int32_t dl_bins(const plds *h) { return std::max<int32_t>(std::min<int32_t>(h->K, kHistMax), 64); }
+
+// The deletion steps too large for the single-block loop, as one graph of
+// kernel nodes: (select, scan, fin, desire-levels (two phases), next, loop) x
+// kDelGraphSteps; rebuilt when the device buffers move.
+int del_graph(plds *h) {
     if (h->del_exec && !memcmp(&h->del_graph_dev, &h->d, sizeof(Dev))) return 0;
     if (h->del_exec) (void)hipGraphExecDestroy(h->del_exec);
     if (h->del_graph) (void)hipGraphDestroy(h->del_graph);
@@ -3563,26 +3952,31 @@ int del_graph(plds *h, size_t lds) {
     if (hipGraphCreate(&h->del_graph, 0) != hipSuccess) return PLDS_EHIP;
     Dev *dv = &h->del_graph_dev;
     void *a0[] = {(void *)dv};
-    void *a1[] = {(void *)dv, (void *)&h->par[1]};   // mode 1
+    void *a1[] = {(void *)dv, (void *)&h->par[1]};                          // mode 1
+    h->dl_nbins = dl_bins(h);
+    void *ab[] = {(void *)dv, (void *)&h->par[1], (void *)&h->dl_nbins};   // mode 1, bins
+    const unsigned blds = (unsigned)h->dl_nbins * sizeof(int32_t);
     struct K {
         const void *f;
-        int grid;
-        size_t lds;
+        int grid, block;
+        unsigned lds;
         void **args;
-    } ks[5] = {{(const void *)k_del_select, kSweepGrid / 4, 0, a0},
-               {(const void *)k_del_scan, kSweepGrid, 0, a0},
-               {(const void *)k_del_fin, kSweepGrid / 4, 0, a0},
-               {(const void *)k_dl, kDlGrid, lds, a1},
-               {(const void *)k_del_next, 1, 0, a1}};
+    } ks[7] = {{(const void *)k_del_select, kSweepGrid / 4, kBlock, 0, a0},
+               {(const void *)k_del_scan, kSweepGrid, kBlock, 0, a0},
+               {(const void *)k_del_fin, kSweepGrid / 4, kBlock, 0, a0},
+               {(const void *)k_dl, kDlGrid, kBlock, 0, a1},
+               {(const void *)k_dl_big, kBigGrid, kBigBlock, blds, ab},
+               {(const void *)k_del_next, 1, 1, 0, a1},
+               {(const void *)k_del_loop, 1, kLoopBlock, 0, a0}};
     hipGraphNode_t prev = nullptr;
     for (int i = 0; i < kDelGraphSteps; i++) {
-        for (int k = 0; k < 5; k++) {
+        for (int k = 0; k < 7; k++) {
             hipGraphNode_t node;
             hipKernelNodeParams p{};
             p.func = const_cast<void *>(ks[k].f);
             p.gridDim = dim3(ks[k].grid);
-            p.blockDim = dim3(k == 4 ? 1 : kBlock);
-            p.sharedMemBytes = (unsigned)ks[k].lds;
+            p.blockDim = dim3(ks[k].block);
+            p.sharedMemBytes = ks[k].lds;
             p.kernelParams = ks[k].args;
             p.extra = nullptr;
             if (hipGraphAddKernelNode(&node, h->del_graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
@@ -3723,36 +4117,35 @@ int insertion_sweep(plds *h, hipStream_t s) {
 
 int deletion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
-    size_t lds = (size_t)(kBlock + 16 + h->K + 1) * sizeof(int32_t);
-    if (lds > 64 * 1024 &&
-        hipFuncSetAttribute((const void *)k_dl, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return PLDS_EINVAL;
+    d.loop_slots = h->sweep_mode == 2 ? 0 : kLoopSlots;
     hipLaunchKernelGGL(k_del_cand, dim3(grid_for(h->h_ctl->n_touch, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
-    tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 0);
+    const int32_t nbins = dl_bins(h);
+    tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), 0, s, d, 0);
+    hipLaunchKernelGGL(k_dl_big, dim3(kBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t), s, d, 0, nbins);
     hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 0);
+    // the level loop in one block; it stops at a step too large for it
+    tlaunch(h, 9, k_del_loop, dim3(1), dim3(kLoopBlock), 0, s, d);
     HIPCHK(hipGetLastError());
-    int rc;
-    // timed step kernels are launched one by one, in runs of 4, 8, ..., after
-    // a wait for the candidates; else the step graph follows at once (its
-    // steps return at once if there are no candidates), as many times before
-    // the first wait as the last sweep took steps (rounded down to whole
-    // graphs)
-    const bool use_graph = h->timed_kind != 2 && h->timed_kind != 3;
-    if (!use_graph) {
-        rc = sync_ctl(h, s);
-        if (rc) return rc;
-        take_timing(h, h->ev_used);
-    }
+    int rc = sync_ctl(h, s);
+    if (rc) return rc;
+    take_timing(h, h->ev_used);
+    // Large steps: the grid kernels run the step, then the single-block loop
+    // goes on; a step graph holds kDelGraphSteps such pairs (the kernels of
+    // a pair not needed return at once).  Timed step kernels are launched one
+    // by one.
+    const bool use_graph = h->timed_kind != 2 && h->timed_kind != 3 && h->timed_kind != 9;
     int run = 4;
-    int64_t first = std::min<int64_t>(std::max<int64_t>(h->del_steps_hint / kDelGraphSteps, 1), 8);
     int64_t steps = 0;
+    // before the next wait, as many step graphs as the last sweep had large
+    // steps (at most 8; steps issued after the sweep's end return at once)
+    int64_t first = std::min<int64_t>(std::max<int64_t>((h->del_steps_hint + kDelGraphSteps - 1) / kDelGraphSteps, 1), 8);
     while (!h->h_ctl->done && !h->h_ctl->err) {
         if (steps > (int64_t)h->K + 1) {
             h->broken = true;
             return PLDS_ESTATE;
         }
         if (use_graph) {
-            rc = del_graph(h, lds);
+            rc = del_graph(h);
             if (rc) return rc;
             for (int64_t i = 0; i < first; i++) HIPCHK(hipGraphLaunch(h->del_exec, s));
             steps += first * kDelGraphSteps;
@@ -3763,19 +4156,22 @@ int deletion_sweep(plds *h, hipStream_t s) {
                 hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
                 tlaunch(h, 2, k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_del_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-                tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), lds, s, d, 1);
+                tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), 0, s, d, 1);
+                hipLaunchKernelGGL(k_dl_big, dim3(kBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t), s, d, 1,
+                                   nbins);
                 hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 1);
+                tlaunch(h, 9, k_del_loop, dim3(1), dim3(kLoopBlock), 0, s, d);
             }
+            run = std::min(run * 2, 128);
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
         take_timing(h, h->ev_used);
-        run = std::min(run * 2, 128);
     }
     Ctl *c = h->h_ctl;
     h->stats.viol_del0 = c->viol_del0;
-    h->del_steps_hint = c->sweeps;
+    h->del_steps_hint = c->big_steps;
     h->stats.sweeps_del += c->sweeps;
     h->stats.moves_down += c->moves;
     h->stats.slots_scanned += c->scanned;
@@ -4427,7 +4823,7 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode) {
 }
 
 int plds_set_timing(plds_t *h, int32_t kernel) {
-    if (!h || kernel < 0 || kernel > 8) return PLDS_EINVAL;
+    if (!h || kernel < 0 || kernel > 9) return PLDS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
     if (kernel && h->ev.empty()) {
         h->ev.assign(2 * kEvPairs, nullptr);

@@ -38,7 +38,7 @@ class plds_stats_t(ctypes.Structure):
                                                                    ("alg_bytes_peel", ctypes.c_int64)]
 
 TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "flip_scan": 5, "ins_sweep": 6, "sk_relax": 7,
-                 "apply_del": 8}
+                 "apply_del": 8, "del_loop": 9}
 
 
 _lib = None

@@ -7,13 +7,18 @@ batches, workload 2): the 16 insertion batches of the build, then rounds of
 the build (int16) and, for every batch, a checksum of the levels and the
 sweep/move counts, plus the oracle's single-core time per batch.
 
+With ``resume R`` it starts from the stored post-build state (checked
+against the stored digest of the last build batch) instead of rebuilding,
+and writes the build batches' records back unchanged followed by R rounds;
+rounds already in the stored trace must come out identical.
+
 With the argument ``sizes`` it instead starts from the stored post-build
 state (the build's edges and the levels above) and applies the batch sizes
 10^4 and 10^5: insertions, then deletions, then mixed batches, with update
 seeds 1000*2 + 100 + j for j = 100, 101, ...; the result goes to
 rmat20_oracle_sizes.json.
 
-    python tests/golden/make_rmat20_oracle.py [rounds | sizes]
+    python tests/golden/make_rmat20_oracle.py [rounds | resume rounds | sizes]
 """
 import hashlib
 import json
@@ -80,6 +85,48 @@ def main(rounds=2):
     assert o.check() == 0
 
 
+def resume(rounds):
+    st = W.RmatStream(SCALE, 16 * 2 ** SCALE, seed=1, build_batches=16, cfg=2)
+    old = json.load(open(OUT_JSON))
+    builds = [b for b in old["batches"] if b["kind"].startswith("build")]
+    assert len(builds) == len(st.build)
+    o = O.Oracle(st.n, 0.4, 3.0)
+    lv0 = np.load(OUT_NPZ)["levels"].astype(np.int32)
+    assert o.load_state(np.concatenate(st.build), lv0) == 0
+    assert digest(o.levels()) == builds[-1]["sha"], "stored post-build levels do not match the trace"
+    known = {b["kind"]: b for b in old["batches"]}
+    trace = {"workload": old["workload"], "delta": 0.4, "lambda": 3.0, "batches": list(builds)}
+
+    def record(kind, rc, dt):
+        s = o.stats()
+        item = {"kind": kind, "rc": rc, "seconds": round(dt, 3), "sha": digest(o.levels()),
+                **{k: s[k] for k in ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up",
+                                     "moves_down", "viol_ins0", "viol_del0")}}
+        if kind in known:
+            ref = {k: v for k, v in known[kind].items() if k != "seconds"}
+            assert ref == {k: v for k, v in item.items() if k != "seconds"}, (kind, ref, item)
+        trace["batches"].append(item)
+        print(json.dumps(item), flush=True)
+        tmp = OUT_JSON + ".tmp"
+        json.dump(trace, open(tmp, "w"), indent=1)
+        os.replace(tmp, OUT_JSON)
+
+    for r in range(rounds):
+        ins = st.insert_batch(BATCH)
+        t = time.perf_counter()
+        rc = o.insert(ins)
+        record(f"ins{r}", rc, time.perf_counter() - t)
+        dele = st.delete_batch(BATCH)
+        t = time.perf_counter()
+        rc = o.delete(dele)
+        record(f"del{r}", rc, time.perf_counter() - t)
+        mi, md = st.mixed_batch(BATCH)
+        t = time.perf_counter()
+        rc = o.update(mi, md)
+        record(f"mix{r}", rc, time.perf_counter() - t)
+    assert o.check() == 0
+
+
 def sizes():
     st = W.RmatStream(SCALE, 16 * 2 ** SCALE, seed=1, build_batches=16, cfg=2)
     st.j = SIZES_J0
@@ -113,5 +160,7 @@ def sizes():
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "sizes":
         sizes()
+    elif len(sys.argv) > 1 and sys.argv[1] == "resume":
+        resume(int(sys.argv[2]))
     else:
         main(int(sys.argv[1]) if len(sys.argv) > 1 else 2)
