@@ -215,6 +215,23 @@ int plds_densest_value(plds_t *h, int32_t graph, double *out, void *stream);
  * exceed 4096 buckets).  Returns after the work on `stream` is complete. */
 int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream);
 
+/* plds_static_kcore for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result as plds_static_kcore, but its scratch arrays
+ * (the peeling counts, buckets and round counters of every vertex, and the
+ * bucket table) live in one array of about 24 MiB per device, defined by the
+ * library and held until the process ends, instead of memory allocated on
+ * the handle's first call; the call makes no device or host allocation.
+ * Handles of at most PLDS_NOALLOC_MAX_N vertices (PLDS_EINVAL beyond).
+ * Every call on a device shares that device's array and leaves its last
+ * contents there (the call clears what must start at zero): calls that
+ * overlap on one device, on any streams or handles, race and must not be
+ * issued.  PLDS_EHIP if the array's device address could not be looked up
+ * when the handle was created.  Returns after the work on `stream` is
+ * complete. */
+#define PLDS_NOALLOC_MAX_N (1 << 21)
+int plds_static_kcore_noalloc(plds_t *h, double eps, double *est_out, void *stream);
+
 /* Vertex updates (section on vertex insertions and deletions).
  *
  * plds_delete_vertices: every edge incident to one of the `count` vertices of

@@ -25,6 +25,7 @@
 #include <cstring>
 #include <type_traits>
 #include <new>
+#include <mutex>
 #include <vector>
 
 #include "../../include/plds.h"
@@ -2999,6 +3000,21 @@ __device__ void sk_flush_hist(const SK &k, int32_t *h) {
         if (h[b]) atomicAdd(&k.cnt[b], h[b]);
 }
 
+// Powers of 1+eps (pw[b] = pw[b-1] * (1+eps) in double, from pw[0] = 1, the
+// same repeated multiplication as the host's count of them) and cleared
+// bucket counts.  One block.
+__global__ void k_sk_setup(SK k) {
+    double *pw = const_cast<double *>(k.pw);
+    if (threadIdx.x == 0) {
+        double x = 1.0;
+        for (int32_t b = 0; b < k.nbk; b++) {
+            if (b > 0) x *= 1.0 + k.eps;
+            pw[b] = x;
+        }
+    }
+    for (int i = threadIdx.x; i < kSkBuckets; i += blockDim.x) k.cnt[i] = 0;
+}
+
 __global__ void k_sk_init(Dev d, SK k) {
     extern __shared__ int32_t hist[];   // [nbk]
     for (int b = threadIdx.x; b < k.nbk; b += blockDim.x) hist[b] = 0;
@@ -3486,6 +3502,16 @@ static Tables make_tables(int64_t n, double delta, double lambda, int32_t lpg) {
     }
     return T;
 }
+// Scratch memory of the allocation-free entry points (callers that cannot
+// allocate device memory): one array per device, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel (in host code
+// the name is only a stand-in for the symbol); it uses the device address
+// looked up once per device by scratch_lookup().
+constexpr size_t kScratchPw = (size_t)kSkBuckets * sizeof(double);    // powers of 1+eps
+constexpr size_t kScratchCnt = (size_t)kSkBuckets * sizeof(int32_t);  // bucket counts
+constexpr size_t kScratchBytes = kScratchPw + kScratchCnt + (size_t)3 * PLDS_NOALLOC_MAX_N * sizeof(int32_t);
+static __device__ __align__(256) int32_t scratch[kScratchBytes / sizeof(int32_t)];
+
 struct plds {
     int64_t n = 0, m = 0;
     double delta = 0, lambda = 0;
@@ -3559,6 +3585,27 @@ namespace {
             return PLDS_EHIP;          \
         }                              \
     } while (0)
+
+// Device address of each device's scratch array, looked up once per device
+// (with that device current) when a handle is created there.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+void scratch_lookup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[dev] = p;
+    else (void)hipGetLastError();
+}
+
+void *scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
 
 template <class T>
 int dalloc(T **p, int64_t count) {
@@ -4179,6 +4226,64 @@ int deletion_sweep(plds *h, hipStream_t s) {
     return check_err(h);
 }
 
+// Checks of a static k-core call; *nbk receives the number of powers of
+// 1+eps up to the first one past n (plus one), *R the peels per threshold,
+// ceil(log_{1+delta} n) with delta = 2/eps.
+int static_kcore_args(const plds *h, double eps, const double *est_out, int32_t *nbk, int32_t *R) {
+    if (!est_out || !(eps > 0) || !std::isfinite(eps) || h->d.ng != 1) return PLDS_EINVAL;
+    int32_t k = 1;
+    for (double x = 1.0; x < (double)h->n; x *= 1.0 + eps) {
+        if (k >= kSkBuckets) return PLDS_EINVAL;   // eps too small for the bucket table
+        k++;
+    }
+    if (k + 1 > kSkBuckets) return PLDS_EINVAL;
+    *nbk = k + 1;
+    int32_t r = 0;
+    for (double x = 1.0; x < (double)h->n; x *= 1.0 + 2.0 / eps) r++;
+    *R = r;
+    return PLDS_OK;
+}
+
+// Algorithm 6 with the scratch arrays of k (allocates nothing).
+int static_kcore_run(plds *h, const SK &k, hipStream_t s) {
+    Dev &d = h->d;
+    hipLaunchKernelGGL(k_sk_setup, dim3(1), dim3(kBlock), 0, s, k);
+    h->h_ctl->sk_alive = 0;
+    h->h_ctl->sk_relaxed = 0;
+    HIPCHK(hipMemcpyAsync(&d.ctl->sk_alive, &h->h_ctl->sk_alive, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const size_t hist = (size_t)k.nbk * sizeof(int32_t);
+    hipLaunchKernelGGL(k_sk_init, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
+    hipLaunchKernelGGL(k_sk_first, dim3(1), dim3(kBlock), 0, s, d, k);
+    HIPCHK(hipGetLastError());
+    int rc = sync_ctl(h, s);
+    if (rc) return rc;
+    int run = 8;
+    int64_t rounds = 0;
+    while (!h->h_ctl->sk_done && !h->h_ctl->err) {
+        if (rounds > h->n + 1) {   // every round peels at least one vertex
+            h->broken = true;
+            return PLDS_ESTATE;
+        }
+        for (int i = 0; i < run; i++) {
+            hipLaunchKernelGGL(k_sk_peel, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, k);
+            tlaunch(h, 7, k_sk_relax, dim3(grid_for((int64_t)h->n * kWave, kBlock, 2048)), dim3(kBlock), 0, s, d, k);
+            hipLaunchKernelGGL(k_sk_fix, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
+            hipLaunchKernelGGL(k_sk_next, dim3(1), dim3(kBlock), 0, s, d, k);
+        }
+        rounds += run;
+        HIPCHK(hipGetLastError());
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+        take_timing(h, h->ev_used);
+        run = std::min(run * 2, 256);
+    }
+    // the relax kernel's algorithmic bytes: every vertex's adjacency is read
+    // once (4-byte id and 4-byte bucket per slot of its 2m), plus an 8-byte
+    // count update per alive neighbour of a peeled vertex
+    h->stats.alg_bytes_peel += 16 * h->m + 8 * h->h_ctl->sk_relaxed;
+    return check_err(h);
+}
+
 int guard(const plds *h) {
     if (!h) return PLDS_EINVAL;
     if (h->broken) return PLDS_ESTATE;
@@ -4229,6 +4334,7 @@ int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double l
         delete h;
         return PLDS_EHIP;
     }
+    scratch_lookup(h->device);
     {   // scan blocks: at most one resident round (a scan launched with more
         // blocks than the device holds at once runs its latency chain once
         // per round of blocks), and at most kScanPerCU per compute unit
@@ -4631,20 +4737,11 @@ int plds_densest_value(plds_t *h, int32_t graph, double *out, void *stream) {
 int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
     int rc = guard(h);
     if (rc) return rc;
-    if (!est_out || !(eps > 0) || !std::isfinite(eps) || h->d.ng != 1) return PLDS_EINVAL;
+    int32_t nbk = 0, R = 0;
+    rc = static_kcore_args(h, eps, est_out, &nbk, &R);
+    if (rc) return rc;
     hipStream_t s = S(stream);
     Dev &d = h->d;
-    // (1+eps)^b by repeated multiplication, up to the first power >= n (>= any degree + 1)
-    std::vector<double> pw(1, 1.0);
-    while (pw.back() < (double)h->n) {
-        if ((int)pw.size() >= kSkBuckets) return PLDS_EINVAL;   // eps too small for the bucket table
-        pw.push_back(pw.back() * (1.0 + eps));
-    }
-    pw.push_back(pw.back() * (1.0 + eps));
-    if ((int)pw.size() > kSkBuckets) return PLDS_EINVAL;
-    // peels per threshold: ceil(log_{1+delta} n), delta = 2/eps
-    int32_t R = 0;
-    for (double x = 1.0; x < (double)h->n; x *= 1.0 + 2.0 / eps) R++;
     if (!h->sk_C) {
         if (dalloc(&h->sk_C, h->n) || dalloc(&h->sk_B, h->n) || dalloc(&h->sk_r, h->n) ||
             dalloc(&h->sk_cnt, kSkBuckets) || dalloc(&h->sk_pw, kSkBuckets)) {
@@ -4654,43 +4751,27 @@ int plds_static_kcore(plds_t *h, double eps, double *est_out, void *stream) {
     }
     // the peeled and touched lists use arrays of n entries that are idle
     // outside update calls
-    SK k{h->sk_C, h->sk_B, h->sk_r, h->sk_cnt, d.mv, d.casc0, d.mv1, h->sk_pw, est_out, (int32_t)pw.size(), R, eps};
-    HIPCHK(hipMemcpyAsync(h->sk_pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(h->sk_cnt, 0, kSkBuckets * sizeof(int32_t), s));
-    h->h_ctl->sk_alive = 0;
-    h->h_ctl->sk_relaxed = 0;
-    HIPCHK(hipMemcpyAsync(&d.ctl->sk_alive, &h->h_ctl->sk_alive, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    const size_t hist = (size_t)k.nbk * sizeof(int32_t);
-    hipLaunchKernelGGL(k_sk_init, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
-    hipLaunchKernelGGL(k_sk_first, dim3(1), dim3(kBlock), 0, s, d, k);
-    HIPCHK(hipGetLastError());
-    rc = sync_ctl(h, s);
+    SK k{h->sk_C, h->sk_B, h->sk_r, h->sk_cnt, d.mv, d.casc0, d.mv1, h->sk_pw, est_out, nbk, R, eps};
+    return static_kcore_run(h, k, s);
+}
+
+int plds_static_kcore_noalloc(plds_t *h, double eps, double *est_out, void *stream) {
+    int rc = guard(h);
     if (rc) return rc;
-    int run = 8;
-    int64_t rounds = 0;
-    while (!h->h_ctl->sk_done && !h->h_ctl->err) {
-        if (rounds > h->n + 1) {   // every round peels at least one vertex
-            h->broken = true;
-            return PLDS_ESTATE;
-        }
-        for (int i = 0; i < run; i++) {
-            hipLaunchKernelGGL(k_sk_peel, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d, k);
-            tlaunch(h, 7, k_sk_relax, dim3(grid_for((int64_t)h->n * kWave, kBlock, 2048)), dim3(kBlock), 0, s, d, k);
-            hipLaunchKernelGGL(k_sk_fix, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d, k);
-            hipLaunchKernelGGL(k_sk_next, dim3(1), dim3(kBlock), 0, s, d, k);
-        }
-        rounds += run;
-        HIPCHK(hipGetLastError());
-        rc = sync_ctl(h, s);
-        if (rc) return rc;
-        take_timing(h, h->ev_used);
-        run = std::min(run * 2, 256);
-    }
-    // the relax kernel's algorithmic bytes: every vertex's adjacency is read
-    // once (4-byte id and 4-byte bucket per slot of its 2m), plus an 8-byte
-    // count update per alive neighbour of a peeled vertex
-    h->stats.alg_bytes_peel += 16 * h->m + 8 * h->h_ctl->sk_relaxed;
-    return check_err(h);
+    int32_t nbk = 0, R = 0;
+    rc = static_kcore_args(h, eps, est_out, &nbk, &R);
+    if (rc) return rc;
+    if (h->n > PLDS_NOALLOC_MAX_N) return PLDS_EINVAL;
+    char *base = (char *)scratch_ptr(h->device);
+    if (!base) return PLDS_EHIP;   // the symbol lookup at create failed
+    // layout of the scratch array: powers, bucket counts, then C, B, r
+    double *pw = (double *)base;
+    int32_t *cnt = (int32_t *)(base + kScratchPw);
+    int32_t *C = (int32_t *)(base + kScratchPw + kScratchCnt);
+    int32_t *B = C + PLDS_NOALLOC_MAX_N, *r = B + PLDS_NOALLOC_MAX_N;
+    Dev &d = h->d;
+    SK k{C, B, r, cnt, d.mv, d.casc0, d.mv1, pw, est_out, nbk, R, eps};
+    return static_kcore_run(h, k, S(stream));
 }
 
 int plds_delete_vertices(plds_t *h, const int32_t *vertices, int64_t count, void *stream) {

@@ -13,6 +13,11 @@ LIB_PATH = os.path.join(HERE, "libplds.so")
 
 PLDS_OK, PLDS_EINVAL, PLDS_ERANGE, PLDS_ENOMEM, PLDS_EHIP, PLDS_ESTATE = 0, -1, -2, -3, -4, -5
 PLDS_LPG_OPT = -1   # levels per group of the PLDSOpt variant: ceil(log_{1+delta} n / 50)
+PLDS_NOALLOC_MAX_N = 1 << 21   # largest handle of plds_static_kcore_noalloc (include/plds.h)
+
+
+def lib_max_noalloc_n():
+    return PLDS_NOALLOC_MAX_N
 
 
 class PLDSError(RuntimeError):
@@ -83,6 +88,7 @@ def lib():
                                             _VP]
         L.plds_densest_value.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP]
         L.plds_static_kcore.argtypes = [_VP, ctypes.c_double, _VP, _VP]
+        L.plds_static_kcore_noalloc.argtypes = [_VP, ctypes.c_double, _VP, _VP]
         L.plds_delete_vertices.argtypes = [_VP, _VP, _I64, _VP]
         L.plds_rebuild.argtypes = [_VP, _I64, _VP, ctypes.POINTER(_VP), _VP]
         L.plds_strerror.restype = ctypes.c_char_p
@@ -96,7 +102,7 @@ EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
            "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror",
            "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value",
-           "plds_static_kcore", "plds_delete_vertices", "plds_rebuild")
+           "plds_static_kcore", "plds_static_kcore_noalloc", "plds_delete_vertices", "plds_rebuild")
 
 
 def strerror(code):
@@ -250,6 +256,13 @@ def plds_densest_value(h, graph=0, stream=None):
 
 def plds_static_kcore(h, eps, out, stream=None):
     return _chk(lib().plds_static_kcore(h, float(eps), _ptr(out), _stream(stream)), "plds_static_kcore")
+
+
+def plds_static_kcore_noalloc(h, eps, out, stream=None):
+    """As plds_static_kcore, with the library's fixed per-device scratch array
+    instead of memory allocated on first use (n <= PLDS_NOALLOC_MAX_N)."""
+    return _chk(lib().plds_static_kcore_noalloc(h, float(eps), _ptr(out), _stream(stream)),
+                "plds_static_kcore_noalloc")
 
 
 def plds_delete_vertices(h, vertices, stream=None, check=True):
