@@ -288,11 +288,23 @@ int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
  * levels scan their slabs); 2 = one kernel per part, every step scanning its
  * movers' slabs; 3 = as 1, with climbing steps for groups of any size (not
  * only large ones), which exercises them on small graphs.  Deletions: the
- * steps run in one single-block kernel, a step with more than 2^14 pending
- * vertices or 2^15 slab slots of movers by the grid kernels; in mode 2 every
+ * steps run in one single-block kernel, a step with more than 2^11 pending
+ * vertices or 2^12 slab slots of movers by the grid kernels; in mode 2 every
  * step (with any slab slots) goes to the grid kernels.  Results are
- * identical. */
+ * identical.  Mode 4 tests the bounded waits of mode 0: the grid barrier's
+ * abort flag is raised before the cooperative launch, every block leaves at
+ * its first barrier, and the insertion call returns PLDS_ESTATE (the handle
+ * is then unusable).  A barrier wait that gives up in mode 0 ends the same
+ * way. */
 int plds_set_sweep_mode(plds_t *h, int32_t mode);
+
+/* Failure injection, for tests of error handling: after `after` more device
+ * allocations by the library on the calling thread, the next one fails (the
+ * call that makes it returns PLDS_ENOMEM), then allocations succeed again;
+ * after < 0 switches it off.  An allocation that fails before a batch
+ * changes anything leaves the state unchanged; one that fails while a batch
+ * is being applied leaves the handle unusable (later calls: PLDS_ESTATE). */
+int plds_inject_alloc_failure(int64_t after);
 
 /* Time one kernel (0 = off, 1 = insertion scan (which also finishes the
  * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step

@@ -3607,9 +3607,14 @@ void *scratch_ptr(int dev) {
     return g_scratch[dev];
 }
 
+// Failure injection (plds_inject_alloc_failure): allocations left on this
+// thread before one fails, -1 = off.
+thread_local int64_t t_alloc_fail_after = -1;
+
 template <class T>
 int dalloc(T **p, int64_t count) {
     *p = nullptr;
+    if (t_alloc_fail_after >= 0 && t_alloc_fail_after-- == 0) return PLDS_ENOMEM;
     if (count <= 0) count = 1;
     if (hipMalloc((void **)p, (size_t)count * sizeof(T)) != hipSuccess) {
         *p = nullptr;
@@ -3858,7 +3863,7 @@ int ctl_reset_batch(plds *h, hipStream_t s) {
 
 int check_err(plds *h) {
     int32_t e = h->h_ctl->err;
-    if (e & (kErrFull | kErrLevel | kErrOrder)) {
+    if (e & (kErrFull | kErrLevel | kErrOrder | kErrHang)) {
         h->broken = true;
         return PLDS_ESTATE;
     }
@@ -3916,15 +3921,24 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
         }
     }
     *applied = h->h_ctl->n_valid;
+    // From here on the dedupe pass has counted this list's edges per
+    // endpoint (addc) and listed the endpoints: a failure leaves the handle
+    // unusable rather than half-applied.
     if (h->track) {
         rc = track_list(h, insert, *applied, s);
-        if (rc) return rc;
+        if (rc) {
+            h->broken = true;
+            return rc;
+        }
     }
     if (insert) {
         if (h->h_ctl->n_grow > 0) {
             int64_t req = h->h_ctl->grow_req;
             rc = ensure_pool(h, s, req);
-            if (rc) return rc;
+            if (rc) {
+                h->broken = true;
+                return rc;
+            }
             HIPCHK(hipMemsetAsync(d.pool + h->pool_top, 0xff, (size_t)req * sizeof(int32_t), s));
             hipLaunchKernelGGL(k_grow_alloc, dim3(grid_for(h->h_ctl->n_grow)), dim3(kBlock), 0, s, d);
             // a wavefront per slab (at least 256 blocks, for the pieces of large slabs)
@@ -4072,7 +4086,8 @@ int insertion_sweep(plds *h, hipStream_t s) {
     // candidates too: the buckets and the first step graphs follow the
     // seeding without a wait (the steps of a sweep without candidates return
     // at once).  Otherwise, and for the cooperative or timed forms, wait.
-    const bool eager = h->sweep_mode != 0 && h->timed_kind != 1 && h->timed_kind != 4 && h->ins_steps_hint >= 32;
+    const bool eager = h->sweep_mode != 0 && h->sweep_mode != 4 && h->timed_kind != 1 && h->timed_kind != 4 &&
+                       h->ins_steps_hint >= 32;
     int rc = PLDS_OK;
     if (!eager) {
         rc = sync_ctl(h, s);
@@ -4087,8 +4102,12 @@ int insertion_sweep(plds *h, hipStream_t s) {
         hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(h->n, kBlock, kApplyGrid)), dim3(kBlock), lds, s, d);
         HIPCHK(hipGetLastError());
     }
-    if (!h->h_ctl->done && h->sweep_mode == 0 && coop_blocks(h) > 0) {
+    if (!h->h_ctl->done && (h->sweep_mode == 0 || h->sweep_mode == 4) && coop_blocks(h) > 0) {
         HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(Bar), s));
+        if (h->sweep_mode == 4) {   // every block leaves at its first barrier
+            static const int one = 1;
+            HIPCHK(hipMemcpyAsync(&h->bar->abort, &one, sizeof(int), hipMemcpyHostToDevice, s));
+        }
         Bar *bar = h->bar;
         void *args[] = {(void *)&d, (void *)&bar};
         tstart(h, 6, s);
@@ -4898,8 +4917,13 @@ int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *p
 }
 
 int plds_set_sweep_mode(plds_t *h, int32_t mode) {
-    if (!h || mode < 0 || mode > 3) return PLDS_EINVAL;
+    if (!h || mode < 0 || mode > 4) return PLDS_EINVAL;
     h->sweep_mode = mode;
+    return PLDS_OK;
+}
+
+int plds_inject_alloc_failure(int64_t after) {
+    t_alloc_fail_after = after < 0 ? -1 : after;
     return PLDS_OK;
 }
 

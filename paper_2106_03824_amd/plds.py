@@ -89,6 +89,7 @@ def lib():
         L.plds_densest_value.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _VP]
         L.plds_static_kcore.argtypes = [_VP, ctypes.c_double, _VP, _VP]
         L.plds_static_kcore_noalloc.argtypes = [_VP, ctypes.c_double, _VP, _VP]
+        L.plds_inject_alloc_failure.argtypes = [_I64]
         L.plds_delete_vertices.argtypes = [_VP, _VP, _I64, _VP]
         L.plds_rebuild.argtypes = [_VP, _I64, _VP, ctypes.POINTER(_VP), _VP]
         L.plds_strerror.restype = ctypes.c_char_p
@@ -102,7 +103,8 @@ EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi",
            "plds_batch_delete", "plds_coreness", "plds_levels", "plds_degrees", "plds_info", "plds_thresholds",
            "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror",
            "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value",
-           "plds_static_kcore", "plds_static_kcore_noalloc", "plds_delete_vertices", "plds_rebuild")
+           "plds_static_kcore", "plds_static_kcore_noalloc", "plds_delete_vertices", "plds_rebuild",
+           "plds_inject_alloc_failure")
 
 
 def strerror(code):
@@ -256,6 +258,12 @@ def plds_densest_value(h, graph=0, stream=None):
 
 def plds_static_kcore(h, eps, out, stream=None):
     return _chk(lib().plds_static_kcore(h, float(eps), _ptr(out), _stream(stream)), "plds_static_kcore")
+
+
+def plds_inject_alloc_failure(after):
+    """Testing aid: the library's allocation after `after` more on this
+    thread fails (after < 0: off)."""
+    return _chk(lib().plds_inject_alloc_failure(int(after)), "plds_inject_alloc_failure")
 
 
 def plds_static_kcore_noalloc(h, eps, out, stream=None):

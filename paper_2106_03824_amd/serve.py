@@ -14,7 +14,10 @@ each graph alone, in arrival order:
 
 Admission control: a graph is admitted only when its estimated HBM
 footprint fits in the remaining budget.  Until then its requests wait.
-Retiring a graph frees its footprint and lets waiting graphs in.
+Retiring a graph frees its footprint and lets waiting graphs in.  An
+admission that fails (the library refused to create the handle or to load
+the initial edges) frees the footprint and leaves nothing resident; every
+later request of that graph fails at once with the same error.
 
 The server does no arithmetic of the method; it only orders calls into the
 library (plds.py / libplds.so).
@@ -60,6 +63,7 @@ class Server:
         self.delta, self.lam = delta, lam
         self.handles = {}                                   # graph -> PLDS
         self.foot = {}                                      # graph -> admitted footprint
+        self.failed = {}                                    # graph -> error of its failed admission
         self.queues = collections.defaultdict(collections.deque)
         self.busy = set()
         self.cv = threading.Condition()
@@ -98,7 +102,7 @@ class Server:
             n, edges = req.payload
             need = footprint_bytes(n, len(edges))
             return self.used + need <= self.budget or not self.handles and not self.busy
-        return req.graph in self.handles
+        return req.graph in self.handles or req.graph in self.failed
 
     def _pick(self):
         best = None
@@ -145,6 +149,8 @@ class Server:
                 self.inflight -= 1
                 if req.kind == "retire" or (req.kind == "admit" and req.error is not None):
                     self.used -= self.foot.pop(req.graph, 0)
+                if req.kind == "admit" and req.error is not None:
+                    self.failed[req.graph] = req.error
                 self.cv.notify_all()
 
     def _dev(self, a, stream):
@@ -157,13 +163,20 @@ class Server:
 
     def _run(self, req, stream):
         torch = self.torch
+        if req.graph in self.failed and req.kind != "admit":
+            raise RuntimeError(f"graph {req.graph} was not admitted: {self.failed[req.graph]!r}")
         if req.kind == "admit":
             n, edges = req.payload
+            self.failed.pop(req.graph, None)
             h = P.PLDS(n, self.delta, self.lam, 0, len(edges))
+            try:
+                if len(edges):
+                    P.plds_update(h.h, self._dev(edges, stream), None, stream=stream)
+                req.result = {"m": h.info()["m"]}
+            except Exception:
+                h.close()
+                raise
             self.handles[req.graph] = h
-            if len(edges):
-                P.plds_update(h.h, self._dev(edges, stream), None, stream=stream)
-            req.result = {"m": h.info()["m"]}
         elif req.kind == "update":
             ins, dele = req.payload
             h = self.handles[req.graph]

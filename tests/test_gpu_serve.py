@@ -124,3 +124,42 @@ def test_serving_admission_waits_for_budget():
     replay(reqs, budget_bytes=2 * biggest, workers=4, arrival=True)
     replay(alone, budget_bytes=64 << 30, workers=1, arrival=False)
     same(results(reqs), results(alone))
+
+
+def test_failed_admission_drains(monkeypatch):
+    """A graph whose handle cannot be created (the library's ENOMEM, forced
+    here) frees its footprint; its later requests fail with the admission's
+    error, the loop drains, and the other graphs are served as alone."""
+    from paper_2106_03824_amd import plds as P
+    from paper_2106_03824_amd import serve as S
+    say("serve: failed admission")
+    real = P.PLDS
+
+    class Refused(real):
+        def __init__(self, n, *a, **k):
+            if n == 777:
+                raise P.PLDSError(P.PLDS_ENOMEM, "plds_create")
+            super().__init__(n, *a, **k)
+
+    monkeypatch.setattr(S.P, "PLDS", Refused)
+    n = 2 ** 10
+    e = W.rmat(10, 8 * n, seed=5)
+    reqs = [S.Request(0, "a", "admit", 0.0, (n, e)), S.Request(1, "bad", "admit", 0.0, (777, e[:10])),
+            S.Request(2, "bad", "update", 0.0, (e[:5], None)), S.Request(3, "bad", "query", 0.0,
+                                                                      np.arange(5, dtype=np.int32)),
+            S.Request(4, "a", "query", 0.0, np.arange(50, dtype=np.int32)), S.Request(5, "bad", "retire", 0.0),
+            S.Request(6, "a", "retire", 0.0)]
+    srv = S.Server(budget_bytes=1 << 40, workers=2)
+    try:
+        srv.serve(reqs, arrival=False)
+        assert srv.used == 0 and not srv.handles
+    finally:
+        srv.close()
+    assert isinstance(reqs[1].error, P.PLDSError)
+    for r in reqs[2:4] + [reqs[5]]:
+        assert r.error is not None and "not admitted" in str(r.error)
+    assert reqs[0].error is None and reqs[4].error is None and reqs[6].error is None
+    o = O.Oracle(n, 0.4, 3.0)
+    assert o.update(e, None) == 0
+    assert np.array_equal(reqs[4].result.view(np.int64), o.coreness(np.arange(50, dtype=np.int32)).view(np.int64))
+    assert np.array_equal(reqs[6].result["levels"], o.levels())
