@@ -1,32 +1,32 @@
 #!/usr/bin/env python3
 """Edge updates/s of the batch-dynamic PLDS on one MI355X.
 
-Workload: an R-MAT graph of scale 20 (2^20 vertices, 16*2^20 unique edges,
-a=0.57 b=0.19 c=0.19, seed 1), delta=0.4, lambda=3, built by 16 insertion
-batches (not timed).  One step applies three batches of 10^6 updates each
-through the C ABI: new uniform pairs (insertions), sampled existing edges
-(deletions), and a mixed batch of half each.  Batches are generated on the
-host and copied to HBM before the timed region; the value is the number of
-applied updates over the wall time of the K timed steps.
+Default workload (configuration 3): an R-MAT graph of scale 24 (2^24
+vertices, 16*2^24 unique edges, a=0.57 b=0.19 c=0.19, seed 1), delta=0.4,
+lambda=3, in the order of a seeded random permutation (seed 3001).  All but
+a held-out tail of the permutation is streamed in as insertion batches of
+10^6 (the build, not timed; its rate is reported, and its first batches are
+checked against the stored oracle trace of the stream).  One step applies
+three batches of 10^6 updates each through the C ABI: the next 10^6 tail
+edges (insertions), 10^6 edges sampled without replacement from the built
+graph (deletions), and a mixed batch of half each.  Batches are in HBM
+before the timed region; the value is the number of applied updates over the
+wall time of the K timed steps.
 
-Also reported: the insertion-scan kernel against the HBM roofline (its
+Beside it: configuration 2 (the RMAT-20 stream: 16 build batches, then
+rounds of 10^6 new uniform pairs, sampled deletions and mixed batches, every
+batch checked against the stored oracle trace of the stream; --no-rmat20
+leaves it out), the insertion-scan kernel against the HBM roofline (its
 launches timed with HIP events inside the library, on the call's stream;
 HBM traffic per launch from the committed counter summary under profiles/
-when it matches the current kernel source),
-parity of the GPU levels with the stored oracle trace of this stream, and the
-CPU oracle (one core) timed on a bounded sample of the same stream (one
-deletion and one mixed batch of 1e6 from the post-build state).
+when it matches the current kernel source), and the CPU oracle (one core)
+timed on a bounded sample of the same RMAT-24 stream.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-
-With --scale 24 (or any scale other than 20) it runs the large streamed
-workload instead: an R-MAT graph of that scale with 16*2^scale unique edges
-(seed 1), streamed as insertion batches of --batch edges in a seeded random
-permutation (seed 3001), then two deletion batches of --batch sampled
-existing edges and one mixed batch; every batch is timed and the value is all
-applied updates over the wall time of the whole stream.
-
-    python bench.py --scale 24 [--batch 1000000]
+    python bench.py --workload rmat20      # configuration 2 alone
+    python bench.py --workload stream [--scale 24] [--batch 1000000]
+                       # the whole graph streamed in insertion batches, then
+                       # two deletion batches and one mixed batch, all timed
 
 With --batched it runs the batched form instead: 256 independent graphs of
 uneven size (128 Erdos-Renyi G(n, p) with n log-uniform in [2^10, 2^16] and
@@ -66,6 +66,7 @@ METRIC = "edge updates/sec (ins, del) at 1e6 batch"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 2 << 30
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_ins_scan_rmat20_hbm_counters.txt")
+PROFILE_SUMMARY_24 = os.path.join(ROOT, "profiles", "k_ins_scan_rmat24_hbm_counters.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_03824_amd", "csrc", "plds.hip")
 
 
@@ -73,13 +74,14 @@ def source_digest():
     return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(summary=None):
     """HBM bytes per k_ins_scan launch from the committed counter summary, if
     it was taken on the current kernel source; else None."""
-    if not os.path.exists(PROFILE_SUMMARY):
+    summary = summary or PROFILE_SUMMARY
+    if not os.path.exists(summary):
         return None
     vals = {}
-    for line in open(PROFILE_SUMMARY):
+    for line in open(summary):
         if ":" in line and not line.startswith(" "):
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
@@ -251,7 +253,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "rmat20", "stream"],
+                    help="rmat24 (default): the RMAT-24 stream and timed rounds of ins/del/mix (configuration 3), "
+                         "with the RMAT-20 stream (configuration 2) reported beside it; rmat20: that stream alone; "
+                         "stream: the whole RMAT graph of --scale streamed in insertion batches, then deletions")
+    ap.add_argument("--scale", type=int, default=24, help="scale of the rmat24 and stream workloads")
+    ap.add_argument("--no-rmat20", action="store_true", help="leave the RMAT-20 stream out of the default run")
     ap.add_argument("--batch", type=int, default=10 ** 6)
     ap.add_argument("--kernel", default="ins_scan", help="kernel timed for the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -306,9 +313,21 @@ def main():
         return run_static(args, P, W, torch, np)
     if args.vertex:
         return run_vertex(args, P, W, torch, np)
-    if args.scale != 20:
+    if args.workload == "stream":
         return run_stream(args, P, W, torch, np)
-    scale, B = args.scale, args.batch
+    if args.opt or args.workload == "rmat20":
+        out = run_rmat20(args, P, W, torch, np, args.steps, args.warmup)
+        print(json.dumps(out), flush=True)
+        return
+    return run_rmat24(args, P, W, torch, np)
+
+
+def run_rmat20(args, P, W, torch, np, steps, warmup):
+    """Configuration 2: the RMAT-20 stream (16 build batches, then rounds of
+    1e6 insertions, deletions and mixed updates), checked against the stored
+    oracle trace; returns the JSON object."""
+    dev = torch.device("cuda", 0)
+    scale, B = 20, 10 ** 6
     m0 = 16 * 2 ** scale
     log("generating R-MAT", scale, m0)
     st = W.RmatStream(scale, m0, seed=1, build_batches=16, cfg=2)
@@ -347,7 +366,7 @@ def main():
     t_build = time.perf_counter() - t_build
     log(f"build: {build_updates} edges in {t_build:.2f}s")
 
-    rounds = args.warmup + args.steps
+    rounds = warmup + steps
     batches = []
     for r in range(rounds):
         ins = st.insert_batch(B)
@@ -364,8 +383,8 @@ def main():
     tot = {"updates": 0, "alg_bytes": 0, "timed_ms": 0.0, "launches": 0, "sweeps": 0, "moves": 0}
     snaps = []          # (batch index, device copy of the levels, stats) for the parity check after timing
     for r in range(rounds):
-        timed = r >= args.warmup
-        if timed and r == args.warmup:
+        timed = r >= warmup
+        if timed and r == warmup:
             P.plds_set_timing(g.h, args.kernel)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -412,8 +431,8 @@ def main():
                 "alg_bytes_per_launch": round(per_launch, 1)}
     lat_ms = sorted(x * 1e3 for x in lat)
     out = {
-        "metric": METRIC, "value": value, "unit": "edge updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": value, "unit": "edge updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"rmat{scale}-ef16-build16-then-ins/del/mix-{B}" + ("-pldsopt" if args.opt else ""),
                    "n": n, "m0": m0, "delta": 0.4, "lambda": 3.0, "levels_per_group": g.L, "batch": B,
@@ -421,7 +440,7 @@ def main():
         "rates": {k: (v[0] / v[1] if v[1] else None) for k, v in per_kind.items()},
         "batch_latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1,
                                                                               int(0.99 * len(lat_ms)))]},
-        "sweeps_per_step": tot["sweeps"] / args.steps, "moves_per_step": tot["moves"] / args.steps,
+        "sweeps_per_step": tot["sweeps"] / steps, "moves_per_step": tot["moves"] / steps,
         "build_updates_per_s": build_updates / t_build,
         "roofline": roof,
         "parity_vs_oracle_trace": parity if trace is not None else None,
@@ -430,8 +449,200 @@ def main():
         out["invariants_hold"] = g.check() == 0   # no stored oracle trace for this level structure
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline_opt(st, n)
-    elif not args.no_cpu_baseline:
+    elif not args.no_cpu_baseline and args.workload == "rmat20":
         out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, args.cpu_seconds)
+    g.close()
+    return out
+
+
+RMAT24_TRACE = os.path.join(ROOT, "tests", "golden", "rmat24_oracle_trace.json")
+PERM_SEED_24 = 3001   # permutation of the RMAT-24 stream (as in tests/golden/make_rmat24_oracle.py)
+
+
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
+
+
+def cpu_baseline_rmat24(perm, n, seconds):
+    """The oracle (one core) on the same RMAT-24 stream, from its start (the
+    post-build state of 2.3e8 edges is out of its reach in the time given):
+    the stream's first edges as insertion batches of 1e5 until half the
+    budget is spent, then one deletion batch of 1e5 edges sampled from those
+    and one mixed batch (5e4 next stream edges, 5e4 sampled)."""
+    import numpy as np
+    import oracle as O
+    from paper_2106_03824_amd import workloads as W
+    o = O.Oracle(n, 0.4, 3.0)
+    C = 10 ** 5
+    u_ins = off = 0
+    t_ins = 0.0
+    while t_ins < seconds / 2 and off + C <= len(perm) // 2:
+        t = time.perf_counter()
+        assert o.insert(perm[off:off + C]) == 0
+        t_ins += time.perf_counter() - t
+        u_ins += o.stats()["applied_ins"]
+        off += C
+    dele = W.sample_edges(perm[:off], C, 3200)
+    t = time.perf_counter()
+    assert o.delete(dele) == 0
+    t_del = time.perf_counter() - t
+    u_del = o.stats()["applied_del"]
+    rest = o.edges()
+    mi, md = perm[off:off + C // 2], W.sample_edges(rest, C // 2, 3201)
+    t = time.perf_counter()
+    assert o.update(mi, md) == 0
+    t_mix = time.perf_counter() - t
+    s = o.stats()
+    u_mix = s["applied_ins"] + s["applied_del"]
+    total = t_ins + t_del + t_mix
+    out = {"value": (u_ins + u_del + u_mix) / total, "unit": "edge updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"oracle (one core, single-threaded) on the RMAT-24 stream from its start: the first {off} "
+                     f"permuted edges as insertion batches of 1e5 ({t_ins:.1f}s), one 1e5 deletion batch sampled "
+                     f"from them ({t_del:.2f}s) and one 1e5 mixed batch ({t_mix:.2f}s); the GPU's timed batches "
+                     f"run against the 2.3e8-edge graph, which the oracle cannot reach in this budget",
+           "rates": {"ins": u_ins / t_ins, "del": u_del / t_del, "mix": u_mix / t_mix}, "seconds": round(total, 2)}
+    out.update(cpu_info())
+    return out
+
+
+def run_rmat24(args, P, W, torch, np):
+    """Configuration 3: R-MAT of scale 24 (16*2^24 unique edges, seed 1) in the
+    order of a seeded random permutation.  All but a held-out tail of the
+    permutation is streamed in as insertion batches of 1e6 (the build; its
+    first batches are checked against the stored oracle trace of the stream),
+    then each of the W + K rounds applies 1e6 insertions (the next tail
+    edges), 1e6 deletions (sampled without replacement from the built graph)
+    and a mixed batch (5e5 tail edges, 5e5 sampled deletions)."""
+    scale, B = args.scale, args.batch
+    n, m0 = 2 ** scale, 16 * 2 ** scale
+    R = args.warmup + args.steps
+    per_round_ins = B + (B - B // 2)
+    hold = R * per_round_ins
+    if hold >= m0 // 2:
+        raise SystemExit("too many rounds for the graph: the held-out tail would exceed half of it")
+    t = time.perf_counter()
+    e = W.rmat(scale, m0, seed=1)
+    perm = W.permute_edges(e, PERM_SEED_24)
+    del e
+    nb = m0 - hold
+    dels = W.sample_edges(perm[:nb], R * (B + B // 2), PERM_SEED_24 + 99)
+    log(f"R-MAT {scale}: {m0} edges, build {nb}, held out {hold}, in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda", 0)
+    perm_d = torch.from_numpy(perm).to(dev)
+    dels_d = torch.from_numpy(dels).to(dev)
+    trace = None
+    if scale == 24 and B == 10 ** 6 and os.path.exists(RMAT24_TRACE):
+        trace = json.load(open(RMAT24_TRACE))["batches"]
+    g = P.PLDS(n, 0.4, 3.0, 0, 2 * m0)
+    parity = {"batches_checked": 0, "mismatches": 0, "trace_batches": len(trace) if trace else 0}
+    torch.cuda.synchronize()
+    t_build = time.perf_counter()
+    build_updates, build_sweeps = 0, []
+    for i, off in enumerate(range(0, nb, B)):
+        P.plds_update(g.h, perm_d[off:min(off + B, nb)], None)
+        s = g.stats()
+        build_updates += s["applied_ins"]
+        build_sweeps.append(s["sweeps_ins"])
+        if trace is not None and i < len(trace):
+            ref = trace[i]
+            ok = digest(g.levels().cpu().numpy()) == ref["sha"] and all(
+                s[k] == ref[k] for k in ("applied_ins", "sweeps_ins", "moves_up", "viol_ins0"))
+            parity["batches_checked"] += 1
+            parity["mismatches"] += 0 if ok else 1
+            if not ok:
+                log("PARITY MISMATCH at stream batch", i)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t_build
+    log(f"build: {build_updates} edges in {t_build:.2f}s ({parity['batches_checked']} batches checked)")
+
+    def rnd(r):
+        a = nb + r * per_round_ins
+        d = r * (B + B // 2)
+        return [("ins", perm_d[a:a + B], None), ("del", None, dels_d[d:d + B]),
+                ("mix", perm_d[a + B:a + per_round_ins], dels_d[d + B:d + B + B // 2])]
+
+    per_kind = {"ins": [0, 0.0], "del": [0, 0.0], "mix": [0, 0.0]}
+    lat = []
+    tot = {"updates": 0, "alg_bytes": 0, "timed_ms": 0.0, "launches": 0, "sweeps": 0, "moves": 0, "syncs": 0,
+           "calls": 0}
+    t0 = None
+    for r in range(R):
+        timed = r >= args.warmup
+        if timed and r == args.warmup:
+            P.plds_set_timing(g.h, args.kernel)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        for kind, ins, dele in rnd(r):
+            tb = time.perf_counter()
+            P.plds_update(g.h, ins, dele)
+            dt = time.perf_counter() - tb
+            s = g.stats()
+            if timed:
+                u = s["applied_ins"] + s["applied_del"]
+                per_kind[kind][0] += u
+                per_kind[kind][1] += dt
+                lat.append(dt)
+                tot["updates"] += u
+                tot["alg_bytes"] += s["alg_bytes_up"]
+                tot["timed_ms"] += s["timed_ms"]
+                tot["launches"] += s["timed_launches"]
+                tot["sweeps"] += s["sweeps_ins"] + s["sweeps_del"]
+                tot["moves"] += s["moves_up"] + s["moves_down"]
+                tot["syncs"] += s["host_syncs"]
+                tot["calls"] += 1
+                log(f"round {r} {kind}: {u} updates in {dt * 1e3:.2f} ms, sweeps {s['sweeps_ins'] + s['sweeps_del']}, "
+                    f"host syncs {s['host_syncs']}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    P.plds_set_timing(g.h, 0)
+    value = tot["updates"] / wall
+    log(f"timed: {tot['updates']} updates in {wall:.3f}s -> {value:.3e}/s")
+    check = g.check()
+    info = g.info()
+    g.close()
+    del perm_d, dels_d
+    torch.cuda.empty_cache()
+    roof = roofline(tot, args.kernel)
+    if roof is not None and args.kernel == "ins_scan":
+        roof["traffic"] = measured_traffic(PROFILE_SUMMARY_24)
+    lat_ms = sorted(x * 1e3 for x in lat)
+    out = {
+        "metric": METRIC, "value": value, "unit": "edge updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"rmat{scale}-ef16-stream{B}-then-ins/del/mix-{B}", "n": n, "m0": m0,
+                   "built_edges": nb, "delta": 0.4, "lambda": 3.0, "levels_per_group": info["L"], "K": info["K"],
+                   "batch": B,
+                   "step": "1 insertion (held-out stream edges) + 1 deletion (sampled) + 1 mixed batch"},
+        "rates": {k: (v[0] / v[1] if v[1] else None) for k, v in per_kind.items()},
+        "batch_latency_ms": {"p50": lat_ms[len(lat_ms) // 2],
+                             "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
+        "sweeps_per_step": tot["sweeps"] / args.steps, "moves_per_step": tot["moves"] / args.steps,
+        "host_syncs_per_call": tot["syncs"] / max(tot["calls"], 1),
+        "build": {"edges": build_updates, "seconds": round(t_build, 3), "updates_per_s": build_updates / t_build,
+                  "batches": len(build_sweeps), "sweeps_per_batch": float(np.mean(build_sweeps)),
+                  "parity_vs_oracle_trace": parity},
+        "roofline": roof,
+        "device_check": check,
+    }
+    if not args.no_rmat20:
+        r20 = run_rmat20(args, P, W, torch, np, min(args.steps, 20), min(args.warmup, 5))
+        out["rmat20"] = {k: r20[k] for k in ("value", "steps", "warmup", "ms_per_step", "rates", "batch_latency_ms",
+                                             "sweeps_per_step", "roofline", "parity_vs_oracle_trace", "config")}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_rmat24(perm, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
