@@ -21,6 +21,16 @@ of the section disagree; this reading reproduces the worked example):
   ceil(log_{1+delta} n) peels were made in it (delta = 2/eps);
 * a vertex peeled from bucket b gets the estimate (1+eps)^b (the worked
   example's estimates 2 and 4 for buckets 1 and 2 at eps = 1).
+
+Pins (tests/test_oracle_static.py): the worked example, closed forms, the
+approximation bound, and hand-derived graphs on which the peel cap, the
+clamp of new buckets to t and the `<=` of the continuation test each change
+an estimate.  The floor ceil((1+eps)^(t-1)) is kept as the listing states
+it, but it never changes a bucket under this reading: a threshold t is
+always the bucket of some integer count C0 (a smallest bucket, and buckets
+are b(C) or earlier thresholds), so ceil((1+eps)^(t-1)) <= C0 <= (1+eps)^t
+and a count at or below the floor is clamped to t anyway.  That step alone
+is parity unpinned: no input can show it.
 """
 import numpy as np
 

@@ -91,3 +91,18 @@ def test_after_updates_and_errors():
     say("static empty graph")
     z = lib().PLDS(100)
     assert (z.static_kcore(1.0).cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("name,n,E,eps", [
+    ("peel cap and clamp", 6, [(0, 1), (2, 3), (2, 4), (3, 5), (4, 5), (3, 1), (4, 1), (5, 1)], 1.0),
+    ("clamp", 8, [(0, 1), (1, 2), (0, 2), (2, 3)] + [(a, b) for a in range(3, 8) for b in range(a + 1, 8)], 1.0),
+    ("continuation at equality", 5, [(0, 1), (2, 4), (3, 4), (2, 1), (3, 1), (4, 1)], 0.6180339887498949),
+])
+def test_rule_pins(name, n, E, eps):
+    """The hand-derived graphs that pin the peel cap, the clamp to the
+    threshold and the continuation test's equality case (see
+    tests/test_oracle_static.py), on the GPU."""
+    say("static rule pin", name)
+    g = lib().PLDS(n)
+    assert g.insert(E) == 0
+    assert same(g.static_kcore(eps).cpu().numpy(), SKO.static_approx_kcore(n, E, eps))
