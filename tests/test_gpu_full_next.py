@@ -1,10 +1,25 @@
 """The orientation outputs, the static k-core and vertex deletions at the
 benchmark's full size: the RMAT-20 graph after the stream's 16 build
-batches, and 1e6-update batches.  The oracle is too slow at this size (its
-static run takes about 50 s, its F and J minutes per batch), so the outputs
-are checked exactly by an independent vectorized recomputation from the
-dumped edges and levels, and by the approximation bound against exact
-peeling."""
+batches, and 1e6-update batches, each pinned to the oracle:
+
+* static k-core: the SHA-256 of the oracle's estimates of this graph
+  (tests/golden/rmat20_static_oracle.json, written by make_rmat20_static.py
+  from the oracle alone), plus the approximation bound against exact
+  peeling;
+* vertex deletions: the oracle loaded with its own stored post-build state
+  (tests/golden/rmat20_oracle_levels.npz) deletes the same vertices, and
+  levels and degrees must be identical;
+* flips F and oriented updates J of the stream's first insertion and mixed
+  batches: the levels before and after each call are the oracle's (the
+  stored post-build levels, then levels whose SHA-256 equals the oracle
+  trace's for that batch) and the edge sets are the stream's own (never
+  dumped from the library); F and J are recomputed from them by a
+  vectorized form of Algorithm 5's definitions (the oracle's own F and J
+  take it minutes per batch at this size).
+"""
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -12,7 +27,10 @@ import pytest
 
 import oracle as O
 import oracle.static_kcore as SKO
+import oracle.vertex as OV
 from paper_2106_03824_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -74,6 +92,9 @@ def test_static_kcore_full_size(stream):
     est = g.static_kcore(eps).cpu().numpy()
     again = g.static_kcore(eps).cpu().numpy()
     assert np.array_equal(est.view(np.int64), again.view(np.int64))
+    ref = json.load(open(os.path.join(GOLDEN, "rmat20_static_oracle.json")))["estimates"][repr(eps)]
+    assert hashlib.sha256(np.ascontiguousarray(est, dtype=np.float64).tobytes()).hexdigest()[:32] == ref["sha"]
+    assert int((est > 0).sum()) == ref["nonzero"]
     core = O.exact_coreness(stream.n, e)
     nz = core > 0
     assert ((est == 0) == ~nz).all()
@@ -84,24 +105,33 @@ def test_static_kcore_full_size(stream):
     assert r.max() <= (2 + eps) * (1 + eps) * (1 + 1e-12)
 
 
-def test_flips_and_oriented_updates_full_size(stream):
-    g = built(stream)
+def _digest(levels):
+    return hashlib.sha256(np.ascontiguousarray(levels, dtype=np.int32).tobytes()).hexdigest()[:32]
+
+
+def test_flips_and_oriented_updates_full_size():
+    st = W.RmatStream(20, 16 * 2 ** 20, seed=1, build_batches=16, cfg=2)
+    trace = {b["kind"]: b for b in json.load(open(os.path.join(GOLDEN, "rmat20_oracle_trace.json")))["batches"]}
+    g = built(st)
+    lv_oracle = np.load(os.path.join(GOLDEN, "rmat20_oracle_levels.npz"))["levels"].astype(np.int64)
+    assert np.array_equal(g.levels().cpu().numpy(), lv_oracle)
     g.track_orientation(True)
     B = 10 ** 6
-    for kind in ("ins", "mix"):
-        cur, _ = g.dump()
-        cur = cur.cpu().numpy()
-        if kind == "ins":
-            ins, dele = W.new_pairs(stream.n, cur, B, 7001), None
-        else:   # drawn from the graph after the insertion batch
-            ins, dele = W.new_pairs(stream.n, cur, B // 2, 7002), W.sample_edges(cur, B // 2, 7003)
+    lv0 = lv_oracle
+    for kind in ("ins0", "del0", "mix0"):
+        k0 = st.cur.copy()                       # the stream's edge set before the call
+        if kind == "ins0":
+            ins, dele = st.insert_batch(B), None
+        elif kind == "del0":
+            ins, dele = None, st.delete_batch(B)
+        else:
+            ins, dele = st.mixed_batch(B)
+        k1 = st.cur                              # and after it
         say("full size: flips after", kind)
-        e0, lv0 = g.dump()
-        e0, lv0 = e0.cpu().numpy(), lv0.cpu().numpy().astype(np.int64)
         assert g.update(ins, dele) == 0
-        e1, lv1 = g.dump()
-        e1, lv1 = e1.cpu().numpy(), lv1.cpu().numpy().astype(np.int64)
-        k0, k1 = np.unique(keys(e0)), np.unique(keys(e1))
+        lv1 = g.levels().cpu().numpy()
+        assert _digest(lv1) == trace[kind]["sha"], "levels differ from the oracle's"
+        lv1 = lv1.astype(np.int64)
         common = np.intersect1d(k0, k1, assume_unique=True)
         before, after = oriented(lv0, common), oriented(lv1, common)
         want_f = before[(before != after).any(axis=1)]
@@ -117,6 +147,7 @@ def test_flips_and_oriented_updates_full_size(stream):
         ji, jd = g.oriented_updates()
         assert np.array_equal(rows_sorted(ji.cpu().numpy()), rows_sorted(oriented(lv1, a_ins)))
         assert np.array_equal(rows_sorted(jd.cpu().numpy()), rows_sorted(oriented(lv0, a_del)))
+        lv0 = lv1
 
 
 def test_vertex_deletions_full_size(stream):
@@ -135,3 +166,13 @@ def test_vertex_deletions_full_size(stream):
     assert g.info()["m"] == int((~inc).sum())
     assert (g.degrees().cpu().numpy()[vs] == 0).all()
     assert g.check() == 0
+    say("full size: vertex deletions on the oracle")
+    o = O.Oracle(stream.n, 0.4, 3.0)
+    lv_oracle = np.load(os.path.join(GOLDEN, "rmat20_oracle_levels.npz"))["levels"].astype(np.int32)
+    assert o.load_state(np.concatenate(stream.build), lv_oracle) == 0
+    assert OV.delete_vertices(o, vs) == 0
+    assert np.array_equal(g.levels().cpu().numpy(), o.levels())
+    assert np.array_equal(g.degrees().cpu().numpy(), o.degrees())
+    sg, so = g.stats(), o.stats()
+    for k in ("applied_del", "sweeps_del", "moves_down", "viol_del0"):
+        assert sg[k] == so[k], (k, sg[k], so[k])

@@ -4,9 +4,15 @@ workload of the benchmark, run through the C ABI exactly as bench.py
 seeded random permutation, then two deletion batches of 10^6 sampled edges
 and one mixed batch.
 
-The oracle replays of this stream would take hours, so parity at this size is
-by properties that hold for every correct run, checked on the CPU from the
-generated edge lists (never from edges the library reports):
+Bit-exact parity: the stream's first batches (as many as the stored oracle
+trace tests/golden/rmat24_oracle_trace.json holds, written by
+make_rmat24_oracle.py from the oracle alone, at one to five minutes of
+oracle time per batch) must leave levels with the same SHA-256 as the
+oracle's, with the same applied, sweep, move and violator counts.
+
+The oracle would take days for the whole stream, so beyond the trace parity
+is by properties that hold for every correct run, checked on the CPU from
+the generated edge lists (never from edges the library reports):
 
   * Invariant 1 (up(v) <= floor((2+3/lambda)(1+delta)^g)) and Invariant 2
     (up*(v) >= ceil((1+delta)^g) at level > 0) at every vertex, with up and
@@ -17,6 +23,9 @@ generated edge lists (never from edges the library reports):
     its level, and lies within the factor (2+3/lambda)(1+delta) = 4.2 of the
     exact coreness from the oracle's bucket peeling (Lemma decomp-bound).
 """
+import hashlib
+import json
+import os
 import sys
 import time
 
@@ -29,6 +38,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 SCALE, B = 24, 10 ** 6
+TRACE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat24_oracle_trace.json")
+
+
+def digest(levels):
+    return hashlib.sha256(np.ascontiguousarray(levels, dtype=np.int32).tobytes()).hexdigest()[:32]
 
 
 def say(*a):
@@ -76,10 +90,20 @@ def test_rmat24_stream_properties():
     dev = torch.device("cuda", 0)
     perm_d = torch.from_numpy(perm).to(dev)
     del perm
+    trace = json.load(open(TRACE))["batches"] if os.path.exists(TRACE) else []
+    say(f"rmat24 oracle trace: {len(trace)} batches")
     for i in range(0, m0, B):
+        bi = i // B
         if i % (64 * B) == 0:
-            say("rmat24 build batch", i // B)
+            say("rmat24 build batch", bi)
         assert P.plds_batch_insert(g.h, perm_d[i:i + B]) == 0
+        if bi < len(trace):
+            ref, s = trace[bi], g.stats()
+            assert ref["kind"] == f"stream{bi}"
+            assert digest(g.levels().cpu().numpy()) == ref["sha"], f"levels differ from the oracle after batch {bi}"
+            for k in ("applied_ins", "sweeps_ins", "moves_up", "viol_ins0"):
+                assert s[k] == ref[k], (bi, k, s[k], ref[k])
+    assert len(trace) >= 25
     del perm_d
     say("rmat24 build done: invariants")
     check_invariants(n, e, g.levels().cpu().numpy(), up_max, dn_min, L)
