@@ -84,11 +84,11 @@ def built(st):
     return g
 
 
-def test_static_kcore_full_size(stream):
+@pytest.mark.parametrize("eps", [0.5, 1.0, 0.1])
+def test_static_kcore_full_size(stream, eps):
     g = built(stream)
     e = np.concatenate(stream.build)
-    eps = 0.5
-    say("full size: static k-core eps 0.5")
+    say("full size: static k-core eps", eps)
     est = g.static_kcore(eps).cpu().numpy()
     again = g.static_kcore(eps).cpu().numpy()
     assert np.array_equal(est.view(np.int64), again.view(np.int64))
