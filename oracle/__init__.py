@@ -33,6 +33,9 @@ def lib():
         L = ctypes.CDLL(path)
         L.ora_create.restype = ctypes.c_void_p
         L.ora_create.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
+        L.ora_create_ex.restype = ctypes.c_void_p
+        L.ora_create_ex.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.c_int32]
         L.ora_destroy.argtypes = [ctypes.c_void_p]
         L.ora_info.argtypes = [ctypes.c_void_p, _I64P]
         L.ora_tables.argtypes = [ctypes.c_void_p, _I32P, _I32P, _F64P]
@@ -65,11 +68,16 @@ def _p(a, t):
 
 class Oracle:
     """Sequential PLDS.  mode 0 keeps counters (Algorithms 2-3 as printed),
-    mode 1 rescans every vertex at every level (slow cross-check)."""
+    mode 1 rescans every vertex at every level (slow cross-check).  coeff > 0
+    (at least 1) replaces the Invariant-1 coefficient 2 + 3/lambda (the
+    experiments' heuristic parameters use 1.1); jump=True moves insertion
+    violators straight to their desire-level (the implementation's
+    procedure) instead of one level at a time."""
 
-    def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, mode=0):
+    def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, mode=0, coeff=0.0, jump=False):
         self._destroy = lib().ora_destroy        # bound now: module globals may be gone at exit
-        self._h = lib().ora_create(int(n), float(delta), float(lam), int(levels_per_group), int(mode))
+        self._h = lib().ora_create_ex(int(n), float(delta), float(lam), int(levels_per_group), int(mode),
+                                      float(coeff), int(bool(jump)))
         if not self._h:
             raise ValueError("ora_create rejected its arguments")
         info = self.info()

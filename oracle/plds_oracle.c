@@ -71,6 +71,8 @@ typedef struct {
 struct ora {
     int64_t n, m;
     double delta, lambda;
+    double coeff;           /* Invariant 1 coefficient: 2 + 3/lambda, or the caller's */
+    int32_t jump;           /* insertions move violators to their desire-level at once */
     int32_t t, L, G, K, mode;
     int32_t *up_max, *dn_min;
     double *pow_tab;
@@ -132,7 +134,7 @@ static void build_tables(ora_t *o, int32_t levels_per_group) {
     o->up_max = (int32_t *)malloc((size_t)o->G * sizeof(int32_t));
     o->dn_min = (int32_t *)malloc((size_t)o->G * sizeof(int32_t));
     o->pow_tab = (double *)malloc((size_t)o->G * sizeof(double));
-    double coeff = 2.0 + 3.0 / o->lambda;       /* Invariant 1 coefficient */
+    double coeff = o->coeff;                    /* Invariant 1 coefficient */
     double x = 1.0;
     for (int32_t g = 0; g < o->G; g++) {
         if (g > 0) x *= 1.0 + o->delta;
@@ -146,14 +148,25 @@ static void build_tables(ora_t *o, int32_t levels_per_group) {
 
 static inline int32_t gn(const ora_t *o, int32_t lvl) { return lvl / o->L; }
 
-ora_t *ora_create(int64_t n, double delta, double lambda, int32_t levels_per_group, int32_t mode) {
+/* coeff > 0 replaces the Invariant-1 coefficient 2 + 3/lambda (the
+ * experiments' heuristic parameters use 1.1); it must be at least 1, so that
+ * floor(coeff x) >= ceil(x) - 1 for every x >= 1 and an integer count below
+ * the Invariant-2 floor never exceeds the Invariant-1 cap.  jump != 0 selects
+ * the implementation's insertion procedure (PLDS implementation details):
+ * violators move straight to their desire-level instead of one level at a
+ * time. */
+ora_t *ora_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int32_t mode, double coeff,
+                     int32_t jump) {
     if (n < 1 || n > INT32_MAX || !(delta > 0) || !(lambda > 0) || (mode != 0 && mode != 1))
         return NULL;
+    if (coeff > 0 && coeff < 1.0) return NULL;
     ora_t *o = (ora_t *)calloc(1, sizeof(ora_t));
     if (!o) return NULL;
     o->n = n;
     o->delta = delta;
     o->lambda = lambda;
+    o->coeff = coeff > 0 ? coeff : 2.0 + 3.0 / lambda;
+    o->jump = jump != 0;
     o->mode = mode;
     build_tables(o, levels_per_group);
     o->adj = (int32_t **)calloc((size_t)n, sizeof(int32_t *));
@@ -178,6 +191,10 @@ ora_t *ora_create(int64_t n, double delta, double lambda, int32_t levels_per_gro
         o->qlev[i] = -1;
     }
     return o;
+}
+
+ora_t *ora_create(int64_t n, double delta, double lambda, int32_t levels_per_group, int32_t mode) {
+    return ora_create_ex(n, delta, lambda, levels_per_group, mode, 0.0, 0);
 }
 
 void ora_destroy(ora_t *o) {
@@ -509,6 +526,135 @@ static void insert_phase_scan(ora_t *o) {
     }
 }
 
+/* Upward desire-level (Def. desire-level, for an Invariant-1 violator): the
+ * level closest to level(v) at which both invariants hold.  Below level(v)
+ * Invariant 1 keeps failing (the count of neighbours at or above a level only
+ * grows downwards, the cap only shrinks), so the search runs upwards from
+ * level(v)+1 and takes the first level where both hold; up(v) and up*(v) are
+ * counted from the neighbours' current levels. */
+static int32_t up_desire_level(ora_t *o, int32_t v) {
+    int32_t lv = o->level[v];
+    int32_t *h = o->hist;
+    for (int32_t j = 0; j <= o->K; j++) h[j] = 0;
+    for (int32_t i = 0; i < o->deg[v]; i++) h[o->level[o->adj[v][i]]]++;
+    o->stats[6]++;
+    o->stats[9] += o->deg[v];
+    int32_t cnt_ge = 0;                          /* cnt(j) = #neighbours at level >= j */
+    for (int32_t j = o->K - 1; j > lv; j--) cnt_ge += h[j];
+    /* cnt_ge = cnt(lv+1); walk j = lv+1, lv+2, ... keeping cnt(j) and cnt(j-1) */
+    for (int32_t j = lv + 1; j < o->K; j++) {
+        int32_t cnt_prev = cnt_ge + h[j - 1];    /* cnt(j-1) */
+        int ok1 = cnt_ge <= o->up_max[gn(o, j)];
+        int ok2 = cnt_prev >= o->dn_min[gn(o, j - 1)];
+        if (ok1 && ok2) return j;
+        cnt_ge -= h[j];                          /* cnt(j+1) */
+    }
+    fail(o, A_T1_LEVEL_RANGE);                   /* no level above satisfies both */
+    return lv;
+}
+
+/* The implementation's insertion procedure (PLDS implementation details:
+ * a filter and sort computes the desire-level of the vertices that move up),
+ * counter mode.  Levels are processed from the lowest one holding an
+ * Invariant-1 violator: the set S_l of violators at l is fixed, the
+ * desire-level of each is computed from the levels before any of them moves,
+ * and all of S_l move to their desire-levels together; the neighbours that
+ * start to violate (at levels above l) and the movers that still violate at
+ * their new level are processed when the loop reaches their level. */
+static void insert_phase_jump(ora_t *o, const uint64_t *keys, int64_t k) {
+    for (int64_t i = 0; i < k; i++)
+        edge_counters(o, (int32_t)(keys[i] >> 32), (int32_t)(keys[i] & 0xffffffffu), +1);
+    for (int64_t i = 0; i < k; i++) {
+        int32_t ends[2] = {(int32_t)(keys[i] >> 32), (int32_t)(keys[i] & 0xffffffffu)};
+        for (int e = 0; e < 2; e++) {
+            int32_t x = ends[e];
+            if (viol2(o, x)) fail(o, A_T2_INV2_INSERT);
+            if (viol1(o, x) && o->qlev[x] != o->level[x]) {
+                o->qlev[x] = o->level[x];
+                queue(o, o->level[x], x);
+                o->stats[12]++;
+            }
+        }
+    }
+    for (int32_t l = 0; l < o->K; l++) {
+        vec_t *b = &o->bucket[l];
+        if (b->n == 0) continue;
+        o->movers.n = 0;
+        for (int64_t i = 0; i < b->n; i++) {
+            int32_t v = b->a[i];
+            o->qlev[v] = -1;
+            if (o->level[v] == l && !o->inset[v] && viol1(o, v)) {
+                o->inset[v] = 1;
+                vec_push(&o->movers, v);
+            }
+        }
+        b->n = 0;
+        if (o->movers.n == 0) continue;
+        o->stats[2]++;
+        o->stats[4] += o->movers.n;
+        /* desire-levels of all movers from the levels before the round */
+        for (int64_t i = 0; i < o->movers.n; i++) {
+            int32_t v = o->movers.a[i];
+            o->dl[v] = up_desire_level(o, v);
+            if (o->dl[v] <= l) fail(o, A_T4_MOVE_UP);
+        }
+        /* neighbours that stay see each mover go from l to its desire-level */
+        for (int64_t i = 0; i < o->movers.n; i++) {
+            int32_t v = o->movers.a[i];
+            o->stats[7] += o->deg[v];
+            o->stats[8] += o->up[v];
+            for (int32_t j = 0; j < o->deg[v]; j++) {
+                int32_t w = o->adj[v][j];
+                if (!o->inset[w]) adjust(o, w, l, o->dl[v]);
+            }
+        }
+        for (int64_t i = 0; i < o->movers.n; i++) {
+            int32_t v = o->movers.a[i];
+            o->level[v] = o->dl[v];
+            o->dl[v] = -1;
+        }
+        for (int64_t i = 0; i < o->movers.n; i++) recount(o, o->movers.a[i]);
+        for (int64_t i = 0; i < o->movers.n; i++) {
+            int32_t v = o->movers.a[i];
+            for (int32_t j = -1; j < o->deg[v]; j++) {
+                int32_t x = j < 0 ? v : o->adj[v][j];
+                if (viol2(o, x)) fail(o, A_T2_INV2_INSERT);
+                if (!viol1(o, x)) continue;
+                if (o->level[x] <= l) fail(o, A_T4_MOVE_UP);
+                if (o->qlev[x] != o->level[x]) {
+                    o->qlev[x] = o->level[x];
+                    queue(o, o->level[x], x);
+                }
+            }
+        }
+        for (int64_t i = 0; i < o->movers.n; i++) o->inset[o->movers.a[i]] = 0;
+    }
+}
+
+/* The same, full-scan mode: every level, every vertex, degrees recounted;
+ * S_l = all vertices of level l violating Invariant 1. */
+static void insert_phase_jump_scan(ora_t *o) {
+    for (int32_t l = 0; l < o->K; l++) {
+        o->movers.n = 0;
+        for (int32_t v = 0; v < (int32_t)o->n; v++) {
+            if (o->level[v] < l && viol1(o, v)) fail(o, A_T4_MOVE_UP);
+            if (o->level[v] == l && viol1(o, v)) vec_push(&o->movers, v);
+        }
+        if (o->movers.n == 0) continue;
+        o->stats[2]++;
+        o->stats[4] += o->movers.n;
+        for (int64_t i = 0; i < o->movers.n; i++) {
+            int32_t v = o->movers.a[i];
+            o->stats[7] += o->deg[v];
+            o->stats[8] += count_up(o, v);
+            o->old[v] = up_desire_level(o, v);
+        }
+        for (int64_t i = 0; i < o->movers.n; i++) o->level[o->movers.a[i]] = o->old[o->movers.a[i]];
+        for (int32_t v = 0; v < (int32_t)o->n; v++)
+            if (viol2(o, v)) fail(o, A_T2_INV2_INSERT);
+    }
+}
+
 /* ------------------------------------------------------------ deletions */
 /* Algorithm 3 (RebalanceDeletions), counter mode.  Invariant-2 violators get
  * their desire-level; for l = 0,1,... every pending vertex whose
@@ -642,8 +788,14 @@ int ora_update(ora_t *o, const int32_t *ins, int64_t n_ins, const int32_t *del, 
     o->stats[0] = w;
     rc = adj_apply(o, keys, w, 1);
     if (rc == 0 && w > 0) {
-        if (o->mode == 0) insert_phase_counters(o, keys, w);
-        else insert_phase_scan(o);
+        if (o->jump) {
+            if (o->mode == 0) insert_phase_jump(o, keys, w);
+            else insert_phase_jump_scan(o);
+        } else if (o->mode == 0) {
+            insert_phase_counters(o, keys, w);
+        } else {
+            insert_phase_scan(o);
+        }
     }
 
     /* deletions: unique, then keep edges present (after the insertions) */

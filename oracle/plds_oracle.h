@@ -34,6 +34,12 @@ typedef struct ora ora_t;
  * experiments' PLDSOpt variant, ceil(log_{1+delta} n / 50); 0 (or any other
  * value <= 0) the default 4*ceil(log_{1+delta} n). */
 ora_t *ora_create(int64_t n, double delta, double lambda, int32_t levels_per_group, int32_t mode);
+/* As ora_create; coeff > 0 (at least 1) replaces the Invariant-1 coefficient
+ * 2 + 3/lambda (the experiments' heuristic parameters use 1.1), jump != 0
+ * moves insertion violators straight to their desire-level (PLDS
+ * implementation details) instead of one level at a time. */
+ora_t *ora_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int32_t mode, double coeff,
+                     int32_t jump);
 void ora_destroy(ora_t *o);
 
 /* out[0..7] = n, m, t = ceil(log_{1+delta} n), L, G, K, mode, 0 */

@@ -8,12 +8,19 @@ level 0..K-1 and moves every Invariant-2 violator whose desire-level equals
 that level (Algorithm 3); the desire-level is taken literally from its
 definition, by trying every level 0..K-1 and keeping the closest one at which
 both invariants hold.
+
+Options: a coefficient of Invariant 1 in place of 2 + 3/lambda (the
+experiments' heuristic parameters use 1.1, taken as the exact rational of its
+decimal text), and the implementation's insertion procedure (jump=True): at
+every level 0..K-1 the vertices of that level violating Invariant 1 each take
+their desire-level (the literal search above, made before any of them moves)
+and all of them move there together.
 """
 from fractions import Fraction
 import math
 
 
-def exact_params(n, delta, lam, levels_per_group=0):
+def exact_params(n, delta, lam, levels_per_group=0, coeff=None):
     """t = least integer with (1+delta)^t >= n; L = 4t (or the override);
     G = t+1 groups; K = G*L levels (Section "Detailed PLDS Algorithm")."""
     delta, lam = Fraction(delta), Fraction(lam)
@@ -23,16 +30,17 @@ def exact_params(n, delta, lam, levels_per_group=0):
         t += 1
     L = levels_per_group if levels_per_group > 0 else max(1, 4 * t)
     G = t + 1
-    coeff = 2 + 3 / lam
+    coeff = 2 + 3 / lam if coeff is None else Fraction(str(coeff))
     up_max = [math.floor(coeff * (1 + delta) ** g) for g in range(G)]
     dn_min = [math.ceil((1 + delta) ** g) for g in range(G)]
     return dict(t=t, L=L, G=G, K=G * L, up_max=up_max, dn_min=dn_min, delta=delta, lam=lam)
 
 
 class BrutePLDS:
-    def __init__(self, n, delta=Fraction(2, 5), lam=Fraction(3), levels_per_group=0):
+    def __init__(self, n, delta=Fraction(2, 5), lam=Fraction(3), levels_per_group=0, coeff=None, jump=False):
         self.n = n
-        p = exact_params(n, delta, lam, levels_per_group)
+        self.jump = jump
+        p = exact_params(n, delta, lam, levels_per_group, coeff)
         self.__dict__.update(p)
         self.adj = [set() for _ in range(n)]
         self.level = [0] * n
@@ -77,8 +85,10 @@ class BrutePLDS:
                 S = [v for v in range(self.n) if self.level[v] == l and not self.inv1_ok(v, l)]
                 if S:
                     self.sweeps_ins += 1
+                    target = {v: (self.desire_level(v) if self.jump else l + 1) for v in S}
+                    assert all(t > l for t in target.values())
                     for v in S:
-                        self.level[v] = l + 1
+                        self.level[v] = target[v]
         removed = False
         for (a, b) in dele:
             if a != b and b in self.adj[a]:
