@@ -94,6 +94,32 @@ int plds_create(int64_t n, double delta, double lambda, plds_t **out);
 int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int64_t edge_capacity_hint,
                    plds_t **out);
 
+/* Options of plds_create_opts (zero-initialise, then set what differs):
+ *   levels_per_group, edge_capacity_hint: as plds_create_ex;
+ *   up_coeff: 0 for the Invariant-1 coefficient 2 + 3/lambda of the
+ *     analysis, or a value >= 1 that replaces it (the experiments'
+ *     heuristic parameters use 1.1; the approximation guarantee then no
+ *     longer holds).  Any value >= 1 keeps floor(c x) >= ceil(x) - 1, which
+ *     the desire-level search relies on; smaller values are PLDS_EINVAL;
+ *   up_jump: 0 for Algorithm 2 (violators move up one level per sweep);
+ *     1 for the procedure of the PLDS implementation details: at each level
+ *     holding Invariant-1 violators (lowest first) every violator takes its
+ *     desire-level (Def. desire-level: the closest level where both
+ *     invariants hold, here the first level above it where Invariant 1
+ *     holds), computed from the levels before any of them moves, and all of
+ *     them move there together.  Each such level counts as one sweep
+ *     (sweeps_ins) and each mover as one move (moves_up).  Deletions follow
+ *     Algorithm 3 either way. */
+typedef struct {
+    int32_t levels_per_group;
+    int32_t up_jump;
+    int64_t edge_capacity_hint;
+    double up_coeff;
+    int64_t reserved[4];
+} plds_options_t;
+
+int plds_create_opts(int64_t n, double delta, double lambda, const plds_options_t *opts, plds_t **out);
+
 int plds_destroy(plds_t *h);
 
 /* Batched form: one handle holding `ngraphs` independent graphs, graph g
@@ -310,7 +336,8 @@ int plds_inject_alloc_failure(int64_t after);
  * movers), 2 = deletion scan, 3 = desire-level, 4 = insertion step
  * preparation, 5 = the edge scan of plds_flips, 6 = the cooperative
  * insertion sweep, 7 = the relax kernel of plds_static_kcore, 8 = the
- * application of a deletion list, 9 = the single-block deletion loop).  Each launch of that kernel carries a HIP event pair that the
+ * application of a deletion list, 9 = the single-block deletion loop,
+ * 10 = the edge scan of a round of jumps of a handle made with up_jump).  Each launch of that kernel carries a HIP event pair that the
  * runtime stamps at the dispatch's own start and end (hipExtLaunchKernel);
  * the cooperative sweep has events recorded around it on the stream.
  * While kind 1 or 4 is timed, insertion steps are launched one by one

@@ -2025,8 +2025,22 @@ __global__ void __launch_bounds__(kBlock) k_ins_sweep(Dev d, Bar *bar) {
 constexpr int kDlRegs = 8;                       // slab slots per lane kept in registers
 constexpr int32_t kDlWaveCap = kDlRegs * kWave;  // slabs of up to 512 slots take one wavefront
 
+// Both searches below find the last j of a window [lo, hi] where the count
+// cnt(j) of w's neighbours at level >= j reaches a per-group threshold:
+// dn_min (the desire-level of a deletion) or up_max + 1 (the first level
+// above an insertion violator where Invariant 1 holds is one more).  The
+// test holds on a prefix of the window (cnt never grows with j, the
+// thresholds never shrink); the result is lo - 1 if it fails at lo.
+// Neighbour levels are clamped to `clamp` (>= hi).
+struct Srch {
+    int32_t lo, hi, clamp, up;   // up = 0: dn_min[g], 1: up_max[g] + 1
+};
+__device__ __forceinline__ int32_t srch_thr(const Dev &d, GP p, const Srch &q, int32_t j) {
+    return q.up ? d.up_max[p.tab + j / p.L] + 1 : d.dn_min[p.tab + j / p.L];
+}
+
 // One wavefront (every lane calls it; w is wave-uniform, cap = d.cap[w] <= kDlWaveCap).
-__device__ int32_t wave_dl(const Dev &d, int32_t w, int32_t lw, int32_t cap) {
+__device__ int32_t wave_srch(const Dev &d, int32_t w, int32_t cap, const Srch &q) {
     const int lane = threadIdx.x % kWave;
     const GP p = gp(d, w);
     const int32_t *s = d.pool + d.off[w];
@@ -2040,22 +2054,27 @@ __device__ int32_t wave_dl(const Dev &d, int32_t w, int32_t lw, int32_t cap) {
     int32_t ymax = -1;
 #pragma unroll
     for (int r = 0; r < kDlRegs; r++) {
-        y[r] = x[r] >= 0 ? min(d.level[x[r]], lw - 1) : -1;
+        y[r] = x[r] >= 0 ? min(d.level[x[r]], q.clamp) : -1;
         ymax = max(ymax, y[r]);
     }
     ymax = wave_max(ymax);
-    int32_t lo = 0, hi = min(lw - 2, ymax);
-    if (hi < 0) return 0;   // no neighbour, or lw = 1
+    int32_t lo = q.lo - 1, hi = min(q.hi, ymax);   // answer in [lo, hi]; lo = "fails at q.lo"
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
         int32_t c = 0;
 #pragma unroll
         for (int r = 0; r < kDlRegs; r++)
             if (r < nr) c += __popcll(__ballot(y[r] >= mid));
-        if (c >= d.dn_min[p.tab + mid / p.L]) lo = mid;
+        if (c >= srch_thr(d, p, q, mid)) lo = mid;
         else hi = mid - 1;
     }
-    return lo + 1;
+    return lo;
+}
+
+// Desire-level of an Invariant-2 violator at level lw (largest l' in
+// [1, lw-1] with cnt(l'-1) >= dn_min[gn(l'-1)], else 0).
+__device__ __forceinline__ int32_t wave_dl(const Dev &d, int32_t w, int32_t lw, int32_t cap) {
+    return wave_srch(d, w, cap, Srch{0, lw - 2, max(lw - 1, 0), 0}) + 1;
 }
 
 // Block-wide sums and maxima (every thread calls them; red holds one int per
@@ -2090,9 +2109,9 @@ __device__ __forceinline__ int32_t block_max32(int32_t x, int32_t *red) {
 // blockDim/kWave + 2 ints.
 constexpr int32_t kDlBins = 2048;   // bins of the single-block deletion loop
 
-__device__ int32_t block_dl(const Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_t nbins, int32_t *sh) {
+__device__ int32_t block_srch(const Dev &d, int32_t w, const Srch &q, int32_t *hist, int32_t nbins, int32_t *sh) {
     const int tid = threadIdx.x, nt = blockDim.x, nwv = blockDim.x / kWave;
-    if (lw < 2) return 0;   // block-uniform
+    if (q.hi < q.lo) return q.lo - 1;   // block-uniform
     const GP p = gp(d, w);
     const int32_t cap = d.cap[w];
     const int32_t *s = d.pool + d.off[w];
@@ -2108,9 +2127,11 @@ __device__ int32_t block_dl(const Dev &d, int32_t w, int32_t lw, int32_t *hist, 
             x[r] = e < cap ? s[e] : -1;
         }
 #pragma unroll
-        for (int r = 0; r < kDlRegs; r++) y0[r] = x[r] >= 0 ? min(d.level[x[r]], lw - 1) : -1;
+        for (int r = 0; r < kDlRegs; r++) y0[r] = x[r] >= 0 ? min(d.level[x[r]], q.clamp) : -1;
     }
-    int32_t a = 0, span = lw, base = 0;
+    // window of values [a, a+span): below q.lo nothing matters, above the
+    // clamp nothing exists
+    int32_t a = q.lo, span = q.clamp + 1 - q.lo, base = 0;
     for (;;) {   // block-uniform
         const int32_t nb = min(span, nbins);
         const int32_t W = (span + nb - 1) / nb;
@@ -2131,7 +2152,7 @@ __device__ int32_t block_dl(const Dev &d, int32_t w, int32_t lw, int32_t *hist, 
 #pragma unroll
             for (int r = 0; r < kDlRegs; r++) {
                 if (x[r] < 0) continue;
-                const int32_t y = min(d.level[x[r]], lw - 1) - a;
+                const int32_t y = min(d.level[x[r]], q.clamp) - a;
                 if (y >= 0 && y < span) atomicAdd(&hist[y / W], 1);
             }
         }
@@ -2149,22 +2170,27 @@ __device__ int32_t block_dl(const Dev &d, int32_t w, int32_t lw, int32_t *hist, 
             const int32_t hb = hist[b];
             cnt += hb;   // cnt(a + b*W)
             const int32_t j = a + b * W;
-            if (j <= lw - 2 && cnt >= d.dn_min[p.tab + j / p.L]) {
+            if (j <= q.hi && cnt >= srch_thr(d, p, q, j)) {
                 best = b;
                 above_best = cnt - hb;
                 break;
             }
         }
         const int32_t bmax = block_max32(best, sh);
-        if (bmax < 0) return 0;   // no neighbour (only possible in the first pass)
+        if (bmax < 0) return q.lo - 1;   // the test fails at q.lo (only possible in the first pass)
         if (best == bmax) *sh_base = above_best;
         __syncthreads();
         base = *sh_base;
         a += bmax * W;
         __syncthreads();
-        if (W == 1) return a + 1;
+        if (W == 1) return a;
         span = W;
     }
+}
+
+__device__ __forceinline__ int32_t block_dl(const Dev &d, int32_t w, int32_t lw, int32_t *hist, int32_t nbins,
+                                            int32_t *sh) {
+    return block_srch(d, w, Srch{0, lw - 2, max(lw - 1, 0), 0}, hist, nbins, sh) + 1;
 }
 
 __device__ __forceinline__ bool del_viol(const Dev &d, int32_t w, int32_t lw) {
@@ -2632,6 +2658,234 @@ __global__ void __launch_bounds__(kLoopBlock) k_del_loop(Dev d) {
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------- insertions with jumps
+// The implementation's insertion procedure (PLDS implementation details):
+// levels are processed upwards from the lowest one holding an Invariant-1
+// violator; the violators S_l of level l each take their desire-level (the
+// first level above l where Invariant 1 holds, counted from the levels
+// before any of them moves; Invariant 2 then holds there too, since the
+// count one level down exceeds the cap, which is at least the floor less
+// one), and all of S_l move there together.  A neighbour w that stays
+// gains an up-neighbour for a mover v going from l to t_v if l < level(w)
+// <= t_v, and an up*-neighbour if l+1 < level(w) <= t_v+1; one whose count
+// crosses its cap becomes pending at its level; a mover that still violates
+// at t_v (co-movers landed above it) becomes pending at t_v.  Pending
+// vertices sit in the ping-pong lists p0/p1 (idle during insertions), the
+// round's movers' targets in dl[] (-1 elsewhere).
+
+// Initial pending list: the violators among the touched endpoints (listed
+// by k_ins_seed in cand).
+__global__ void k_jmp_init(Dev d) {
+    Ctl *c = d.ctl;
+    const int32_t nc = c->n_cand;
+    int32_t *P = c->cur ? d.p1 : d.p0;
+    int32_t best = kInf;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += gridDim.x * blockDim.x) {
+        const int32_t v = d.cand[i];
+        P[i] = v;
+        best = min(best, d.level[v]);
+    }
+    best = -wave_max(-best);
+    if (threadIdx.x % kWave == 0 && best < kInf) atomicMin(&c->nm, best);
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->p_n[c->cur] = nc;
+}
+
+// Round at level l, part 1: movers (pending at l) to mv with their slab
+// chunks; the rest stay pending.
+__global__ void k_jmp_select(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    const int32_t l = c->l, cur = c->cur, nxt = cur ^ 1, np = c->p_n[cur];
+    const int32_t *P = cur ? d.p1 : d.p0;
+    int32_t *Q = nxt ? d.p1 : d.p0;
+    const int lane = threadIdx.x % kWave;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < np; i0 += stride) {
+        const int i = i0 + lane;
+        int32_t v = -1, lv = -1;
+        if (i < np) {
+            v = P[i];
+            lv = d.level[v];
+            if (lv < l) latch(c, kErrOrder);
+            else if (lv > l) atomicMin(&c->nm, lv);
+        }
+        const bool mover = i < np && lv == l;
+        wpush(d.mv, &c->n_mv, d.n, mover, v, c);
+        wpush(Q, &c->p_n[nxt], d.n, i < np && lv > l, v, c);
+        add_chunks_w(d, mover ? v : -1);
+    }
+}
+
+// Part 2: each mover's desire-level into dl[]: a wavefront per slab that fits
+// its registers, the rest listed (casc1, n_big) for k_jmp_dl_big.
+__global__ void __launch_bounds__(kBlock) k_jmp_dl(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    const int32_t l = c->l, nmv = c->n_mv;
+    const int lane = threadIdx.x % kWave;
+    const int nw = gridDim.x * (kBlock / kWave);
+    for (int i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < nmv; i += nw) {   // wave-uniform
+        const int32_t v = d.mv[i];
+        const int32_t cap = d.cap[v];
+        if (cap > kDlWaveCap) {
+            if (lane == 0) push(d.casc1, &c->n_big, d.n, v, c);
+            continue;
+        }
+        const int32_t t = wave_srch(d, v, cap, Srch{l, d.K - 2, d.K - 1, 1}) + 1;
+        if (lane == 0) {
+            if (t <= l) latch(c, kErrOrder);
+            d.dl[v] = t;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBigBlock) k_jmp_dl_big(Dev d, int32_t nbins) {
+    extern __shared__ int32_t hist[];
+    __shared__ int32_t red[kBigBlock / kWave + 2];
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    const int32_t l = c->l, cnt = c->n_big;
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {   // block-uniform
+        const int32_t v = d.casc1[i];
+        const int32_t t = block_srch(d, v, Srch{l, d.K - 2, d.K - 1, 1}, hist, nbins, red) + 1;
+        if (threadIdx.x == 0) {
+            if (t <= l) latch(c, kErrOrder);
+            d.dl[v] = t;
+        }
+    }
+}
+
+// Part 3: every mover v (l -> t = dl[v]) scans its slab by chunks.  A
+// co-mover w counts at its own target dl[w]; another w keeps its level lw,
+// gains an up-neighbour if l < lw <= t (the one whose count reaches cap + 1
+// makes it pending) and an up*-neighbour if l+1 < lw <= t+1.  v's own up and
+// up* at t are counted on the way (stay, cnt2).
+__global__ void k_jmp_scan(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    const int32_t l = c->l, nch = c->n_chunks, nxt = c->cur ^ 1;
+    int32_t *Q = nxt ? d.p1 : d.p0;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    const int nw = gridDim.x * blockDim.x / kWave;
+    int32_t scanned = 0, bumps = 0, best = kInf;
+    for (int ci = wid; ci < nch; ci += nw) {
+        const int64_t desc = d.chunks[ci];
+        const int32_t v = (int32_t)(desc >> 32), k = (int32_t)(desc & 0xffffffff);
+        const int32_t cap = d.cap[v], t = d.dl[v];
+        const int32_t *sl = d.pool + d.off[v];
+        const int32_t lo = k * kChunk, hi = min(lo + kChunk, cap);
+        int32_t cu = 0, cus = 0;
+        for (int32_t e0 = lo; e0 < hi; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            const int32_t w = e < hi ? sl[e] : -1;
+            bool pend = false;
+            if (w >= 0) {
+                const int32_t tw = d.dl[w];
+                const int32_t lw = tw >= 0 ? tw : d.level[w];   // a co-mover counts at its target
+                cu += lw >= t;
+                cus += lw >= t - 1;
+                if (tw < 0) {
+                    if (lw > l && lw <= t) {
+                        const int32_t old = atomicAdd(&d.up[w], 1);
+                        bumps++;
+                        if (old == up_cap(d, gp(d, w), lw)) {
+                            pend = true;
+                            best = min(best, lw);
+                        }
+                    }
+                    if (lw > l + 1 && lw <= t + 1) {
+                        atomicAdd(&d.ups[w], 1);
+                        bumps++;
+                    }
+                }
+            }
+            wpush(Q, &c->p_n[nxt], d.n, pend, w, c);
+        }
+        scanned += hi - lo;
+        cu = wave_sum(cu);
+        cus = wave_sum(cus);
+        if (lane == 0) {
+            if (cu) atomicAdd(&d.stay[v], cu);
+            if (cus) atomicAdd(&d.cnt2[v], cus);
+        }
+    }
+    best = -wave_max(-best);
+    bumps = wave_sum(bumps);
+    if (lane == 0) {
+        if (best < kInf) atomicMin(&c->nm, best);
+        if (scanned) atomicAdd((unsigned long long *)&c->scanned, (unsigned long long)scanned);
+        if (bumps) atomicAdd((unsigned long long *)&c->alg_up1, (unsigned long long)bumps);
+    }
+}
+
+// Part 4: movers take their targets with their recounted degrees; one that
+// still violates becomes pending at its new level.
+__global__ void k_jmp_fin(Dev d) {
+    Ctl *c = d.ctl;
+    if (c->done) return;
+    const int32_t nmv = c->n_mv, nxt = c->cur ^ 1;
+    int32_t *Q = nxt ? d.p1 : d.p0;
+    const int lane = threadIdx.x % kWave;
+    const int stride = gridDim.x * blockDim.x;
+    int32_t best = kInf, top = 0;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < nmv; i0 += stride) {
+        const int i = i0 + lane;
+        bool pend = false;
+        int32_t v = -1;
+        if (i < nmv) {
+            v = d.mv[i];
+            const int32_t t = d.dl[v];
+            atomicSub(&d.occ[d.level[v]], 1);
+            atomicAdd(&d.occ[t], 1);
+            d.level[v] = t;
+            d.up[v] = d.stay[v];
+            d.ups[v] = d.cnt2[v];
+            d.stay[v] = 0;
+            d.cnt2[v] = 0;
+            d.dl[v] = -1;
+            top = max(top, t);
+            if (d.up[v] > up_cap(d, gp(d, v), t)) {
+                pend = true;
+                best = min(best, t);
+            }
+        }
+        wpush(Q, &c->p_n[nxt], d.n, pend, v, c);
+    }
+    best = -wave_max(-best);
+    top = wave_max(top);
+    if (lane == 0) {
+        if (best < kInf) atomicMin(&c->nm, best);
+        if (top) atomicMax((unsigned long long *)&c->top, (unsigned long long)top);
+    }
+}
+
+// One thread: close a round (mode 1) or the seeding (mode 0), and take the
+// lowest pending level next.
+__global__ void k_jmp_next(Dev d, int mode) {
+    Ctl *c = d.ctl;
+    if (mode == 1 && c->done) return;
+    if (mode == 1) {
+        if (c->n_log < 4 * d.K) {
+            int64_t *row = d.steplog + 4 * c->n_log++;
+            row[0] = c->l;
+            row[1] = c->l;
+            row[2] = c->n_mv;
+            row[3] = (int64_t)c->n_chunks + ((int64_t)3 << 48);   // kind 3: a round of jumps
+        }
+        c->sweeps += 1;
+        c->moves += c->n_mv;
+        c->p_n[c->cur] = 0;
+        c->cur ^= 1;
+        c->n_mv = 0;
+        c->n_chunks = 0;
+    }
+    c->n_big = 0;
+    const int32_t nm = c->nm;
+    c->nm = kInf;
+    if (nm == kInf) c->done = 1;
+    else c->l = nm;
 }
 
 // ------------------------------------------------------------- queries
@@ -3479,7 +3733,7 @@ struct Tables {
     std::vector<double> pw;
 };
 
-static Tables make_tables(int64_t n, double delta, double lambda, int32_t lpg) {
+static Tables make_tables(int64_t n, double delta, double lambda, int32_t lpg, double up_coeff) {
     Tables T;
     double p = 1.0;
     while (p < (double)n) {
@@ -3492,7 +3746,7 @@ static Tables make_tables(int64_t n, double delta, double lambda, int32_t lpg) {
     T.up.assign(T.G + 1, INT32_MAX);
     T.dn.assign(T.G + 1, INT32_MAX);
     T.pw.assign(T.G + 1, 0.0);
-    double coeff = 2.0 + 3.0 / lambda, x = 1.0;
+    double coeff = up_coeff > 0 ? up_coeff : 2.0 + 3.0 / lambda, x = 1.0;
     for (int32_t g = 0; g < T.G; g++) {
         if (g > 0) x *= 1.0 + delta;
         T.pw[g] = x;
@@ -3557,10 +3811,17 @@ struct plds {
     hipGraphExec_t del_exec = nullptr;
     Dev del_graph_dev{};
     int64_t del_steps_hint = 0;   // steps of the last deletion sweep run by the grid kernels
+    // the rounds of the jump procedure as a prebuilt graph
+    hipGraph_t jmp_graph = nullptr;
+    hipGraphExec_t jmp_exec = nullptr;
+    Dev jmp_graph_dev{};
+    int64_t jmp_steps_hint = 0;
     int32_t dl_nbins = 0;         // bins argument of the step graph's large-slab desire-level kernel
     // orientation tracking: the last update call's starting levels and its
     // applied updates (pairs (min, max))
     int32_t lpg = 0;              // levels_per_group as given at create
+    double up_coeff = 0;          // Invariant-1 coefficient given at create (0: 2 + 3/lambda)
+    int32_t up_jump = 0;          // insertions move violators straight to their desire-level
     int32_t *vd_buf = nullptr;    // incident edges of deleted vertices
     int64_t vd_cap = 0;
     // static approximate k-core scratch (allocated on first use)
@@ -3645,7 +3906,7 @@ void build_tables(plds *h, int32_t lpg) {
     h->h_pow.clear();
     h->t = h->L = h->G = h->K = 0;
     for (size_t g = 0; g < h->gn.size(); g++) {
-        Tables T = make_tables(h->gn[g], h->delta, h->lambda, lpg);
+        Tables T = make_tables(h->gn[g], h->delta, h->lambda, lpg, h->up_coeff);
         h->gtab.push_back((int32_t)h->h_up_max.size());
         h->h_up_max.insert(h->h_up_max.end(), T.up.begin(), T.up.end());
         h->h_dn_min.insert(h->h_dn_min.end(), T.dn.begin(), T.dn.end());
@@ -3685,6 +3946,10 @@ void free_all(plds *h) {
     if (h->del_graph) (void)hipGraphDestroy(h->del_graph);
     h->del_exec = nullptr;
     h->del_graph = nullptr;
+    if (h->jmp_exec) (void)hipGraphExecDestroy(h->jmp_exec);
+    if (h->jmp_graph) (void)hipGraphDestroy(h->jmp_graph);
+    h->jmp_exec = nullptr;
+    h->jmp_graph = nullptr;
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     h->ev.clear();
@@ -4181,6 +4446,111 @@ int insertion_sweep(plds *h, hipStream_t s) {
     return check_err(h);
 }
 
+constexpr int kJmpGraphSteps = 4;
+
+// Rounds of the jump procedure as one graph of kernel nodes: (select,
+// desire-levels (two kernels), scan, fin, next) x kJmpGraphSteps; rebuilt
+// when the device buffers move.
+int jmp_graph(plds *h) {
+    if (h->jmp_exec && !memcmp(&h->jmp_graph_dev, &h->d, sizeof(Dev))) return 0;
+    if (h->jmp_exec) (void)hipGraphExecDestroy(h->jmp_exec);
+    if (h->jmp_graph) (void)hipGraphDestroy(h->jmp_graph);
+    h->jmp_exec = nullptr;
+    h->jmp_graph = nullptr;
+    h->jmp_graph_dev = h->d;
+    if (hipGraphCreate(&h->jmp_graph, 0) != hipSuccess) return PLDS_EHIP;
+    Dev *dv = &h->jmp_graph_dev;
+    h->dl_nbins = dl_bins(h);
+    void *a0[] = {(void *)dv};
+    void *a1[] = {(void *)dv, (void *)&h->par[1]};
+    void *ab[] = {(void *)dv, (void *)&h->dl_nbins};
+    const unsigned blds = (unsigned)h->dl_nbins * sizeof(int32_t);
+    struct K {
+        const void *f;
+        int grid, block;
+        unsigned lds;
+        void **args;
+    } ks[6] = {{(const void *)k_jmp_select, kSweepGrid / 4, kBlock, 0, a0},
+               {(const void *)k_jmp_dl, kDlGrid, kBlock, 0, a0},
+               {(const void *)k_jmp_dl_big, kBigGrid, kBigBlock, blds, ab},
+               {(const void *)k_jmp_scan, kSweepGrid, kBlock, 0, a0},
+               {(const void *)k_jmp_fin, kSweepGrid / 4, kBlock, 0, a0},
+               {(const void *)k_jmp_next, 1, 1, 0, a1}};
+    hipGraphNode_t prev = nullptr;
+    for (int i = 0; i < kJmpGraphSteps; i++) {
+        for (int k = 0; k < 6; k++) {
+            hipGraphNode_t node;
+            hipKernelNodeParams p{};
+            p.func = const_cast<void *>(ks[k].f);
+            p.gridDim = dim3(ks[k].grid);
+            p.blockDim = dim3(ks[k].block);
+            p.sharedMemBytes = ks[k].lds;
+            p.kernelParams = ks[k].args;
+            p.extra = nullptr;
+            if (hipGraphAddKernelNode(&node, h->jmp_graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+                return PLDS_EHIP;
+            prev = node;
+        }
+    }
+    if (hipGraphInstantiate(&h->jmp_exec, h->jmp_graph, nullptr, nullptr, 0) != hipSuccess) return PLDS_EHIP;
+    return 0;
+}
+
+// The insertion rebalance with desire-level jumps (handles created with
+// up_jump): seed the pending list with the batch's violating endpoints,
+// then run rounds until no vertex is pending.
+int jump_sweep(plds *h, hipStream_t s) {
+    Dev &d = h->d;
+    const int nt = h->h_ctl->n_touch;
+    HIPCHK(hipMemsetAsync(d.lvl_cnt, 0, (size_t)(h->K + 1) * sizeof(int32_t), s));
+    const size_t hist = (size_t)(h->K <= kHistMax ? h->K : 0) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_ins_seed, dim3(grid_for(nt, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d);
+    hipLaunchKernelGGL(k_jmp_init, dim3(kListGrid), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_jmp_next, dim3(1), dim3(1), 0, s, d, 0);
+    HIPCHK(hipGetLastError());
+    const bool timed = h->timed_kind != 0;
+    int64_t first = std::min<int64_t>(std::max<int64_t>(h->jmp_steps_hint / kJmpGraphSteps, 1), 8);
+    int64_t steps = 0;
+    int rc = PLDS_OK;
+    const int32_t nbins = dl_bins(h);
+    do {
+        if (steps > (int64_t)h->K + 1) {   // every round moves to a higher level
+            h->broken = true;
+            return PLDS_ESTATE;
+        }
+        if (!timed) {
+            rc = jmp_graph(h);
+            if (rc) return rc;
+            for (int64_t i = 0; i < first; i++) HIPCHK(hipGraphLaunch(h->jmp_exec, s));
+        } else {
+            for (int64_t i = 0; i < first * kJmpGraphSteps; i++) {
+                hipLaunchKernelGGL(k_jmp_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+                hipLaunchKernelGGL(k_jmp_dl, dim3(kDlGrid), dim3(kBlock), 0, s, d);
+                hipLaunchKernelGGL(k_jmp_dl_big, dim3(kBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t), s,
+                                   d, nbins);
+                tlaunch(h, 10, k_jmp_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
+                hipLaunchKernelGGL(k_jmp_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
+                hipLaunchKernelGGL(k_jmp_next, dim3(1), dim3(1), 0, s, d, 1);
+            }
+        }
+        steps += first * kJmpGraphSteps;
+        first = 1;
+        HIPCHK(hipGetLastError());
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+        take_timing(h, h->ev_used);
+    } while (!h->h_ctl->done && !h->h_ctl->err);
+    Ctl *c = h->h_ctl;
+    h->stats.viol_ins0 = c->n_cand;
+    h->jmp_steps_hint = c->sweeps + 1;
+    h->stats.sweeps_ins += c->sweeps;
+    h->stats.moves_up += c->moves;
+    h->stats.alg_bytes_up += 8 * c->scanned + 8 * c->alg_up1 + 4 * c->moves;
+    h->stats.slots_scanned += c->scanned;
+    h->stats.top_level = std::max(h->stats.top_level, c->top);
+    return check_err(h);
+}
+
 int deletion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
     d.loop_slots = h->sweep_mode == 2 ? 0 : kLoopSlots;
@@ -4326,13 +4696,18 @@ const char *plds_strerror(int code) {
     }
 }
 
-int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double lambda, int32_t levels_per_group,
-                      int64_t edge_capacity_hint, plds_t **out) {
+}  // extern "C"
+
+namespace {
+
+int create_impl(int32_t ngraphs, const int64_t *ns, double delta, double lambda, int32_t levels_per_group,
+                int64_t edge_capacity_hint, double up_coeff, int32_t up_jump, plds_t **out) {
     if (!out) return PLDS_EINVAL;
     *out = nullptr;
     if (ngraphs < 1 || !ns || !(delta > 0) || !(lambda > 0) || !std::isfinite(delta) || !std::isfinite(lambda) ||
         (levels_per_group < 0 && levels_per_group != PLDS_LPG_OPT) || edge_capacity_hint < 0)
         return PLDS_EINVAL;
+    if (up_coeff != 0 && !(up_coeff >= 1.0 && std::isfinite(up_coeff))) return PLDS_EINVAL;
     int64_t n = 0;
     for (int32_t g = 0; g < ngraphs; g++) {
         if (ns[g] < 1 || ns[g] > INT32_MAX) return PLDS_EINVAL;
@@ -4345,6 +4720,8 @@ int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double l
     h->delta = delta;
     h->lambda = lambda;
     h->lpg = levels_per_group;
+    h->up_coeff = up_coeff;
+    h->up_jump = up_jump ? 1 : 0;
     for (int32_t g = 0, b = 0; g < ngraphs; b += (int32_t)ns[g], g++) {
         h->gbase.push_back(b);
         h->gn.push_back(ns[g]);
@@ -4455,6 +4832,22 @@ int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double l
     return PLDS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int plds_create_multi(int32_t ngraphs, const int64_t *ns, double delta, double lambda, int32_t levels_per_group,
+                      int64_t edge_capacity_hint, plds_t **out) {
+    return create_impl(ngraphs, ns, delta, lambda, levels_per_group, edge_capacity_hint, 0.0, 0, out);
+}
+
+int plds_create_opts(int64_t n, double delta, double lambda, const plds_options_t *opts, plds_t **out) {
+    if (out) *out = nullptr;
+    if (!opts || n < 1 || n > INT32_MAX) return PLDS_EINVAL;
+    return create_impl(1, &n, delta, lambda, opts->levels_per_group, opts->edge_capacity_hint, opts->up_coeff,
+                       opts->up_jump, out);
+}
+
 int plds_create_ex(int64_t n, double delta, double lambda, int32_t levels_per_group, int64_t edge_capacity_hint,
                    plds_t **out) {
     if (n < 1 || n > INT32_MAX) {
@@ -4523,7 +4916,7 @@ int run_update_body(plds *h, const int32_t *ins, int64_t n_ins, const int32_t *d
         h->stats.applied_ins = applied;
         synced = false;
         if (applied) {
-            rc = insertion_sweep(h, s);
+            rc = h->up_jump ? jump_sweep(h, s) : insertion_sweep(h, s);
             if (rc) return rc;
             synced = true;
         }
@@ -4859,7 +5252,7 @@ int plds_rebuild(plds_t *h, int64_t new_n, const int32_t *relabel, plds_t **out,
         if (hipGetLastError() != hipSuccess) rc = PLDS_EHIP;
     }
     plds_t *nh = nullptr;
-    if (!rc) rc = plds_create_multi(1, &new_n, h->delta, h->lambda, h->lpg, 2 * m, &nh);
+    if (!rc) rc = create_impl(1, &new_n, h->delta, h->lambda, h->lpg, 2 * m, h->up_coeff, h->up_jump, &nh);
     if (!rc) {
         nh->sweep_mode = h->sweep_mode;
         if (m) rc = plds_update(nh, e, m, nullptr, 0, stream);   // Algorithm 2 on every edge
@@ -4928,7 +5321,7 @@ int plds_inject_alloc_failure(int64_t after) {
 }
 
 int plds_set_timing(plds_t *h, int32_t kernel) {
-    if (!h || kernel < 0 || kernel > 9) return PLDS_EINVAL;
+    if (!h || kernel < 0 || kernel > 10) return PLDS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
     if (kernel && h->ev.empty()) {
         h->ev.assign(2 * kEvPairs, nullptr);

@@ -26,6 +26,12 @@ class PLDSError(RuntimeError):
         super().__init__(f"{where}: {strerror(code)} ({code})")
 
 
+class plds_options_t(ctypes.Structure):
+    _fields_ = [("levels_per_group", ctypes.c_int32), ("up_jump", ctypes.c_int32),
+                ("edge_capacity_hint", ctypes.c_int64), ("up_coeff", ctypes.c_double),
+                ("reserved", ctypes.c_int64 * 4)]
+
+
 class plds_info_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("t", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("G", ctypes.c_int32), ("K", ctypes.c_int32), ("delta", ctypes.c_double),
@@ -43,7 +49,7 @@ class plds_stats_t(ctypes.Structure):
                                                                    ("alg_bytes_peel", ctypes.c_int64)]
 
 TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "flip_scan": 5, "ins_sweep": 6, "sk_relax": 7,
-                 "apply_del": 8, "del_loop": 9}
+                 "apply_del": 8, "del_loop": 9, "jmp_scan": 10}
 
 
 _lib = None
@@ -60,6 +66,8 @@ def lib():
         L.plds_create.argtypes = [_I64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_VP)]
         L.plds_create_ex.argtypes = [_I64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _I64,
                                      ctypes.POINTER(_VP)]
+        L.plds_create_opts.argtypes = [_I64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(plds_options_t),
+                                       ctypes.POINTER(_VP)]
         L.plds_destroy.argtypes = [_VP]
         L.plds_create_multi.argtypes = [ctypes.c_int32, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _I64,
                                         ctypes.POINTER(_VP)]
@@ -104,7 +112,7 @@ EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi",
            "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror",
            "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value",
            "plds_static_kcore", "plds_static_kcore_noalloc", "plds_delete_vertices", "plds_rebuild",
-           "plds_inject_alloc_failure")
+           "plds_inject_alloc_failure", "plds_create_opts")
 
 
 def strerror(code):
@@ -146,6 +154,16 @@ def _edges_arg(e):
 def plds_create(n, delta, lam):
     h = _VP()
     _chk(lib().plds_create(int(n), float(delta), float(lam), ctypes.byref(h)), "plds_create")
+    return h
+
+
+def plds_create_opts(n, delta, lam, levels_per_group=0, edge_capacity_hint=0, up_coeff=0.0, up_jump=False):
+    o = plds_options_t()
+    o.levels_per_group, o.up_jump = int(levels_per_group), int(bool(up_jump))
+    o.edge_capacity_hint, o.up_coeff = int(edge_capacity_hint), float(up_coeff)
+    h = _VP()
+    _chk(lib().plds_create_opts(int(n), float(delta), float(lam), ctypes.byref(o), ctypes.byref(h)),
+         "plds_create_opts")
     return h
 
 
@@ -358,9 +376,14 @@ def plds_sync(h, stream=None):
 class PLDS:
     """Owning wrapper: one handle on the current device."""
 
-    def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, edge_capacity_hint=0, _handle=None):
-        self.h = _handle if _handle is not None else plds_create_ex(n, delta, lam, levels_per_group,
-                                                                    edge_capacity_hint)
+    def __init__(self, n, delta=0.4, lam=3.0, levels_per_group=0, edge_capacity_hint=0, _handle=None,
+                 up_coeff=0.0, up_jump=False):
+        if _handle is not None:
+            self.h = _handle
+        elif up_coeff or up_jump:
+            self.h = plds_create_opts(n, delta, lam, levels_per_group, edge_capacity_hint, up_coeff, up_jump)
+        else:
+            self.h = plds_create_ex(n, delta, lam, levels_per_group, edge_capacity_hint)
         info = plds_info(self.h)
         self.n, self.L, self.G, self.K, self.t = info["n"], info["L"], info["G"], info["K"], info["t"]
 
