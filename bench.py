@@ -151,19 +151,27 @@ def _baseline(value, unit, t_work, sample, **extra):
     return out
 
 
-def cpu_baseline_opt(st, n):
-    """The oracle at PLDSOpt levels (one core) over the first 8 build batches
-    of the same RMAT-20 stream (8e6 insertions into the growing graph)."""
+def cpu_baseline_opt(st, n, lpg=-1, coeff=0.0, jump=False, seconds=20.0):
+    """The oracle in the same variant (PLDSOpt levels, coefficient, jumps;
+    one core) on the start of the same RMAT-20 stream: its build edges in
+    insertion batches of 1e5 until `seconds` have passed (a build batch of
+    1e6 takes the oracle minutes at the default level structure)."""
     import oracle as O
-    o = O.Oracle(n, 0.4, 3.0, -1)
-    u, t = 0, time.perf_counter()
-    for b in st.build[:8]:
-        assert o.insert(b) == 0
+    o = O.Oracle(n, 0.4, 3.0, lpg, coeff=coeff, jump=jump)
+    e = st.build[0]
+    C = 10 ** 5
+    u, dt, off = 0, 0.0, 0
+    while dt < seconds and off + C <= len(e):
+        t = time.perf_counter()
+        assert o.insert(e[off:off + C]) == 0
+        dt += time.perf_counter() - t
         u += o.stats()["applied_ins"]
-    dt = time.perf_counter() - t
+        off += C
+        log(f"cpu baseline: {off} edges in {dt:.1f}s")
     return _baseline(u / dt, "edge updates/s", dt,
-                     "oracle at PLDSOpt levels (one core), the stream's first 8 build batches of 1e6 insertions "
-                     "(the oracle has no stored post-build state at this level structure)")
+                     f"oracle (one core) in the same variant (levels per group {lpg}, coefficient "
+                     f"{coeff or '2+3/lambda'}, jumps {bool(jump)}), the stream's first {off} build edges as "
+                     f"insertion batches of 1e5 (the oracle has no stored post-build state for the variants)")
 
 
 def cpu_baseline_static(eps):
@@ -270,6 +278,11 @@ def main():
     ap.add_argument("--opt", action="store_true",
                     help="the default RMAT-20 stream with the PLDSOpt level structure (ceil(log_{1+delta} n / 50) "
                          "levels per group)")
+    ap.add_argument("--jump", action="store_true",
+                    help="the RMAT-20 stream with the implementation's insertion procedure (upward desire-level jumps)")
+    ap.add_argument("--coeff", type=float, default=0.0,
+                    help="the RMAT-20 stream with this Invariant-1 coefficient in place of 2+3/lambda (1.1: the "
+                         "paper's heuristic parameters)")
     ap.add_argument("--static", action="store_true",
                     help="the static approximate k-core (Algorithm 6) of the RMAT-20 graph after the build")
     ap.add_argument("--static-eps", type=float, nargs="+", default=[0.5, 1.0, 0.1])
@@ -315,7 +328,7 @@ def main():
         return run_vertex(args, P, W, torch, np)
     if args.workload == "stream":
         return run_stream(args, P, W, torch, np)
-    if args.opt or args.workload == "rmat20":
+    if args.opt or args.jump or args.coeff or args.workload == "rmat20":
         out = run_rmat20(args, P, W, torch, np, args.steps, args.warmup)
         print(json.dumps(out), flush=True)
         return
@@ -333,9 +346,11 @@ def run_rmat20(args, P, W, torch, np, steps, warmup):
     st = W.RmatStream(scale, m0, seed=1, build_batches=16, cfg=2)
     n = st.n
     lpg = P.PLDS_LPG_OPT if args.opt else 0
-    g = P.PLDS(n, 0.4, 3.0, lpg, 2 * m0)
+    variant = args.opt or args.jump or args.coeff
+    kernel = "jmp_scan" if args.jump and args.kernel == "ins_scan" else args.kernel
+    g = P.PLDS(n, 0.4, 3.0, lpg, 2 * m0, up_coeff=args.coeff, up_jump=args.jump)
     # the stored oracle trace is of the paper's level structure
-    trace = json.load(open(TRACE)) if (scale == 20 and B == 10 ** 6 and not args.opt and os.path.exists(TRACE)) \
+    trace = json.load(open(TRACE)) if (scale == 20 and B == 10 ** 6 and not variant and os.path.exists(TRACE)) \
         else None
     parity = {"batches_checked": 0, "mismatches": 0}
 
@@ -385,7 +400,7 @@ def run_rmat20(args, P, W, torch, np, steps, warmup):
     for r in range(rounds):
         timed = r >= warmup
         if timed and r == warmup:
-            P.plds_set_timing(g.h, args.kernel)
+            P.plds_set_timing(g.h, kernel)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         for kind, ins, dele in batches[r]:
@@ -426,7 +441,8 @@ def run_rmat20(args, P, W, torch, np, steps, warmup):
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic() if args.kernel == "ins_scan" else None, "kernel": "k_" + args.kernel,
+                "traffic": measured_traffic() if kernel == "ins_scan" and not variant else None,
+                "kernel": "k_" + kernel,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "launches": tot["launches"],
                 "alg_bytes_per_launch": round(per_launch, 1)}
     lat_ms = sorted(x * 1e3 for x in lat)
@@ -434,7 +450,8 @@ def run_rmat20(args, P, W, torch, np, steps, warmup):
         "metric": METRIC, "value": value, "unit": "edge updates/s", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"rmat{scale}-ef16-build16-then-ins/del/mix-{B}" + ("-pldsopt" if args.opt else ""),
+        "config": {"workload": f"rmat{scale}-ef16-build16-then-ins/del/mix-{B}" + ("-pldsopt" if args.opt else "")
+                   + ("-jump" if args.jump else "") + (f"-coeff{args.coeff}" if args.coeff else ""),
                    "n": n, "m0": m0, "delta": 0.4, "lambda": 3.0, "levels_per_group": g.L, "batch": B,
                    "step": "1 insertion + 1 deletion + 1 mixed batch"},
         "rates": {k: (v[0] / v[1] if v[1] else None) for k, v in per_kind.items()},
@@ -445,10 +462,10 @@ def run_rmat20(args, P, W, torch, np, steps, warmup):
         "roofline": roof,
         "parity_vs_oracle_trace": parity if trace is not None else None,
     }
-    if args.opt:
-        out["invariants_hold"] = g.check() == 0   # no stored oracle trace for this level structure
+    if variant:
+        out["invariants_hold"] = g.check() == 0   # no stored oracle trace for these variants
         if not args.no_cpu_baseline:
-            out["cpu_baseline"] = cpu_baseline_opt(st, n)
+            out["cpu_baseline"] = cpu_baseline_opt(st, n, lpg, args.coeff, args.jump)
     elif not args.no_cpu_baseline and args.workload == "rmat20":
         out["cpu_baseline"] = cpu_baseline(st_edges_after_build(st), n, args.cpu_seconds)
     g.close()

@@ -296,6 +296,20 @@ __device__ __forceinline__ int32_t wadd_key(int32_t *arr, int32_t key) {
     return res;
 }
 
+// Every active lane calls it; lanes with key >= 0 add `delta` to arr[key],
+// with one atomic per distinct key of the wavefront.
+__device__ __forceinline__ void wave_add_key(int32_t *arr, int32_t key, int32_t delta) {
+    uint64_t todo = __ballot(key >= 0);
+    const int lane = __lane_id();
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t k = __shfl(key, leader, kWave);
+        const uint64_t same = __ballot(key == k) & todo;
+        if (lane == leader) atomicAdd(&arr[k], delta * __popcll(same));
+        todo &= ~same;
+    }
+}
+
 // exclusive prefix sum over the wavefront; *total receives the sum
 __device__ __forceinline__ int32_t wave_excl(int32_t x, int32_t *total) {
     int lane = __lane_id();
@@ -2077,6 +2091,29 @@ __device__ __forceinline__ int32_t wave_dl(const Dev &d, int32_t w, int32_t lw, 
     return wave_srch(d, w, cap, Srch{0, lw - 2, max(lw - 1, 0), 0}) + 1;
 }
 
+// One global atomic per block for a running minimum, maximum or sum that
+// every thread contributes to (every thread of the block calls it; block-
+// uniform control flow).  Same-address device atomics serialise, so a
+// contribution per lane or per wavefront would queue thousands of them.
+__device__ __forceinline__ void block_min_to(int32_t x, int32_t *dst) {
+    __shared__ int32_t acc;
+    if (threadIdx.x == 0) acc = kInf;
+    __syncthreads();
+    x = -wave_max(-x);
+    if (threadIdx.x % kWave == 0 && x < kInf) atomicMin(&acc, x);
+    __syncthreads();
+    if (threadIdx.x == 0 && acc < kInf) atomicMin(dst, acc);
+}
+__device__ __forceinline__ void block_add64_to(int64_t x, unsigned long long *dst) {
+    __shared__ unsigned long long acc;
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    x = wave_sum64(x);
+    if (threadIdx.x % kWave == 0 && x) atomicAdd(&acc, (unsigned long long)x);
+    __syncthreads();
+    if (threadIdx.x == 0 && acc) atomicAdd(dst, acc);
+}
+
 // Block-wide sums and maxima (every thread calls them; red holds one int per
 // wavefront of the block).
 __device__ __forceinline__ int32_t block_sum32(int32_t x, int32_t *red) {
@@ -2241,48 +2278,67 @@ __global__ void k_del_cand(Dev d) {
 // the neighbours a step's moves left violating, when the step was too large
 // for the single-block loop).  A wavefront per vertex whose slab fits its
 // registers; then, in a second pass, a block per larger slab.
-__device__ __forceinline__ void dl_record(const Dev &d, Ctl *c, int32_t w, int32_t lw, int32_t dv, int32_t l,
-                                          int32_t *plist, int32_t *pn, int32_t *nm) {
+__device__ __forceinline__ bool dl_record(const Dev &d, Ctl *c, int32_t w, int32_t lw, int32_t dv, int32_t l) {
     if (dv <= l || dv >= lw) latch(c, kErrOrder);
-    if (d.dl[w] < 0) push(plist, pn, d.n, w, c);
+    const bool fresh = d.dl[w] < 0;   // not pending yet
     d.dl[w] = dv;
-    atomicMin(nm, dv);
+    return fresh;
 }
 
 // A wavefront per listed vertex: violators whose slab fits the wavefront's
 // registers get their desire-level; larger ones are listed (the idle
-// cascade list casc1, counter n_big) for k_dl_big.
+// cascade list casc1, counter n_big) for k_dl_big.  The iterations are
+// block-uniform so that new pending vertices are staged in LDS and appended
+// with one atomic per block, and the running minimum of the desire-levels
+// takes one atomic per block.
 __global__ void __launch_bounds__(kBlock) k_dl(Dev d, int mode) {
+    __shared__ Stage q;
     Ctl *c = d.ctl;
     if (mode == 1 && (c->done || !c->del_big)) return;
+    stage_init(q);
     const int32_t cur = c->cur, tgt = mode == 0 ? cur : (cur ^ 1);
     int32_t *plist = tgt ? d.p1 : d.p0;
     const int32_t l = mode == 0 ? -1 : c->l;
-    const int lane = threadIdx.x % kWave;
-    int32_t ncalc = 0;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    constexpr int nwb = kBlock / kWave;
     const int32_t cnt = c->n_rc;
-    const int nw = gridDim.x * (kBlock / kWave);
-    for (int i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < cnt; i += nw) {   // wave-uniform
-        const int32_t w = d.rc[i];
-        const int32_t lw = d.level[w];
-        if (!del_viol(d, w, lw)) continue;
-        const int32_t cap = d.cap[w];
-        if (cap > kDlWaveCap) {
-            if (lane == 0) push(d.casc1, &c->n_big, d.n, w, c);
-            continue;
+    int32_t best = kInf;
+    int64_t ncalc = 0;
+    for (int base = blockIdx.x * nwb; base < cnt; base += gridDim.x * nwb) {   // block-uniform
+        const int i = base + wid;
+        bool fresh = false;
+        int32_t w = -1;
+        if (i < cnt) {   // wave-uniform
+            w = d.rc[i];
+            const int32_t lw = d.level[w];
+            if (del_viol(d, w, lw)) {
+                const int32_t cap = d.cap[w];
+                if (cap > kDlWaveCap) {
+                    if (lane == 0) push(d.casc1, &c->n_big, d.n, w, c);
+                } else {
+                    const int32_t dv = wave_dl(d, w, lw, cap);
+                    if (lane == 0) {
+                        ncalc++;
+                        fresh = dl_record(d, c, w, lw, dv, l);
+                        best = min(best, dv);
+                    }
+                }
+            }
         }
-        const int32_t dv = wave_dl(d, w, lw, cap);
-        ncalc++;
-        if (lane == 0) dl_record(d, c, w, lw, dv, l, plist, &c->p_n[tgt], &c->nm);
+        stage_push(q, fresh, w);
+        stage_flush(q, blockDim.x, plist, &c->p_n[tgt], d.n, c);
     }
-    if (lane == 0 && ncalc) atomicAdd((unsigned long long *)&c->dl_calcs, (unsigned long long)ncalc);
+    stage_flush(q, kStage, plist, &c->p_n[tgt], d.n, c);
+    block_min_to(best, &c->nm);
+    block_add64_to(ncalc, (unsigned long long *)&c->dl_calcs);
 }
 
 // A block of kBigBlock threads per listed violator with a large slab; its
 // histogram has one bin per level (min(K, kHistMax) bins of dynamic LDS), so
 // one pass over the slab usually suffices.
 constexpr int kBigBlock = 1024;
-constexpr int kBigGrid = 512;
+constexpr int kBigGrid = 512;      // deletions: many hub violators per step in some streams
+constexpr int kJmpBigGrid = 128;   // jumps: few large-slab movers per round
 __global__ void __launch_bounds__(kBigBlock) k_dl_big(Dev d, int mode, int32_t nbins) {
     extern __shared__ int32_t hist[];
     __shared__ int32_t red[kBigBlock / kWave + 2];
@@ -2292,16 +2348,18 @@ __global__ void __launch_bounds__(kBigBlock) k_dl_big(Dev d, int mode, int32_t n
     int32_t *plist = tgt ? d.p1 : d.p0;
     const int32_t l = mode == 0 ? -1 : c->l;
     const int32_t cnt = c->n_big;
-    int32_t ncalc = 0;
+    int32_t ncalc = 0, best = kInf;
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {   // block-uniform
         const int32_t w = d.casc1[i];
         const int32_t lw = d.level[w];
         const int32_t dv = block_dl(d, w, lw, hist, nbins, red);
         if (threadIdx.x == 0) {
             ncalc++;
-            dl_record(d, c, w, lw, dv, l, plist, &c->p_n[tgt], &c->nm);
+            if (dl_record(d, c, w, lw, dv, l)) push(plist, &c->p_n[tgt], d.n, w, c);
+            best = min(best, dv);
         }
     }
+    block_min_to(best, &c->nm);
     if (threadIdx.x == 0 && ncalc) atomicAdd((unsigned long long *)&c->dl_calcs, (unsigned long long)ncalc);
 }
 
@@ -2351,6 +2409,7 @@ __global__ void k_del_select(Dev d) {
     int32_t *Q = nxt ? d.p1 : d.p0;
     int gid = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x % kWave;
     int stride = gridDim.x * blockDim.x;
+    int32_t best = kInf;
     for (int i0 = gid - lane; i0 < np; i0 += stride) {
         int i = i0 + lane;
         int32_t v = -1, dv = -1;
@@ -2359,7 +2418,7 @@ __global__ void k_del_select(Dev d) {
             dv = d.dl[v];
             if (dv != l) {
                 if (dv < l) latch(c, kErrOrder);
-                atomicMin(&c->nm, dv);
+                best = min(best, dv);
             }
         }
         bool mover = i < np && dv == l;
@@ -2367,6 +2426,7 @@ __global__ void k_del_select(Dev d) {
         wpush(Q, &c->p_n[nxt], d.n, i < np && dv != l, v, c);
         add_chunks_w(d, mover ? v : -1);
     }
+    block_min_to(best, &c->nm);
 }
 
 // Part 2: every mover v (previous level pv) scans its slab.  A neighbour w
@@ -2431,10 +2491,13 @@ __global__ void k_del_fin(Dev d) {
     if (c->done || !c->del_big) return;
     int32_t l = c->l, nmv = c->n_mv;
     int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nmv; i += stride) {
-        int32_t v = d.mv[i];
-        atomicSub(&d.occ[d.level[v]], 1);
-        atomicAdd(&d.occ[l], 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&d.occ[l], nmv);   // every mover lands at level l
+    const int lane = threadIdx.x % kWave;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < nmv; i0 += stride) {
+        const int i = i0 + lane;
+        const int32_t v = i < nmv ? d.mv[i] : -1;
+        wave_add_key(d.occ, v >= 0 ? d.level[v] : -1, -1);
+        if (v < 0) continue;
         d.level[v] = l;
         d.up[v] = d.stay[v];
         d.ups[v] = d.cnt2[v];
@@ -2687,8 +2750,7 @@ __global__ void k_jmp_init(Dev d) {
         P[i] = v;
         best = min(best, d.level[v]);
     }
-    best = -wave_max(-best);
-    if (threadIdx.x % kWave == 0 && best < kInf) atomicMin(&c->nm, best);
+    block_min_to(best, &c->nm);
     if (blockIdx.x == 0 && threadIdx.x == 0) c->p_n[c->cur] = nc;
 }
 
@@ -2702,6 +2764,7 @@ __global__ void k_jmp_select(Dev d) {
     int32_t *Q = nxt ? d.p1 : d.p0;
     const int lane = threadIdx.x % kWave;
     const int stride = gridDim.x * blockDim.x;
+    int32_t best = kInf;
     for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < np; i0 += stride) {
         const int i = i0 + lane;
         int32_t v = -1, lv = -1;
@@ -2709,13 +2772,14 @@ __global__ void k_jmp_select(Dev d) {
             v = P[i];
             lv = d.level[v];
             if (lv < l) latch(c, kErrOrder);
-            else if (lv > l) atomicMin(&c->nm, lv);
+            else if (lv > l) best = min(best, lv);
         }
         const bool mover = i < np && lv == l;
         wpush(d.mv, &c->n_mv, d.n, mover, v, c);
         wpush(Q, &c->p_n[nxt], d.n, i < np && lv > l, v, c);
         add_chunks_w(d, mover ? v : -1);
     }
+    block_min_to(best, &c->nm);
 }
 
 // Part 2: each mover's desire-level into dl[]: a wavefront per slab that fits
@@ -2811,13 +2875,10 @@ __global__ void k_jmp_scan(Dev d) {
             if (cus) atomicAdd(&d.cnt2[v], cus);
         }
     }
-    best = -wave_max(-best);
-    bumps = wave_sum(bumps);
-    if (lane == 0) {
-        if (best < kInf) atomicMin(&c->nm, best);
-        if (scanned) atomicAdd((unsigned long long *)&c->scanned, (unsigned long long)scanned);
-        if (bumps) atomicAdd((unsigned long long *)&c->alg_up1, (unsigned long long)bumps);
-    }
+    // scanned is wave-uniform; count it once per wavefront
+    block_min_to(best, &c->nm);
+    block_add64_to(lane == 0 ? scanned : 0, (unsigned long long *)&c->scanned);
+    block_add64_to(bumps, (unsigned long long *)&c->alg_up1);
 }
 
 // Part 4: movers take their targets with their recounted degrees; one that
@@ -2830,15 +2891,17 @@ __global__ void k_jmp_fin(Dev d) {
     const int lane = threadIdx.x % kWave;
     const int stride = gridDim.x * blockDim.x;
     int32_t best = kInf, top = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicSub(&d.occ[c->l], nmv);   // every mover leaves level l
     for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < nmv; i0 += stride) {
         const int i = i0 + lane;
         bool pend = false;
-        int32_t v = -1;
+        int32_t v = -1, t = -1;
         if (i < nmv) {
             v = d.mv[i];
-            const int32_t t = d.dl[v];
-            atomicSub(&d.occ[d.level[v]], 1);
-            atomicAdd(&d.occ[t], 1);
+            t = d.dl[v];
+        }
+        wave_add_key(d.occ, t, 1);
+        if (i < nmv) {
             d.level[v] = t;
             d.up[v] = d.stay[v];
             d.ups[v] = d.cnt2[v];
@@ -2853,12 +2916,9 @@ __global__ void k_jmp_fin(Dev d) {
         }
         wpush(Q, &c->p_n[nxt], d.n, pend, v, c);
     }
-    best = -wave_max(-best);
+    block_min_to(best, &c->nm);
     top = wave_max(top);
-    if (lane == 0) {
-        if (best < kInf) atomicMin(&c->nm, best);
-        if (top) atomicMax((unsigned long long *)&c->top, (unsigned long long)top);
-    }
+    if (lane == 0 && top) atomicMax((unsigned long long *)&c->top, (unsigned long long)top);
 }
 
 // One thread: close a round (mode 1) or the seeding (mode 0), and take the
@@ -4472,7 +4532,7 @@ int jmp_graph(plds *h) {
         void **args;
     } ks[6] = {{(const void *)k_jmp_select, kSweepGrid / 4, kBlock, 0, a0},
                {(const void *)k_jmp_dl, kDlGrid, kBlock, 0, a0},
-               {(const void *)k_jmp_dl_big, kBigGrid, kBigBlock, blds, ab},
+               {(const void *)k_jmp_dl_big, kJmpBigGrid, kBigBlock, blds, ab},
                {(const void *)k_jmp_scan, kSweepGrid, kBlock, 0, a0},
                {(const void *)k_jmp_fin, kSweepGrid / 4, kBlock, 0, a0},
                {(const void *)k_jmp_next, 1, 1, 0, a1}};
@@ -4526,15 +4586,15 @@ int jump_sweep(plds *h, hipStream_t s) {
             for (int64_t i = 0; i < first * kJmpGraphSteps; i++) {
                 hipLaunchKernelGGL(k_jmp_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_jmp_dl, dim3(kDlGrid), dim3(kBlock), 0, s, d);
-                hipLaunchKernelGGL(k_jmp_dl_big, dim3(kBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t), s,
-                                   d, nbins);
+                hipLaunchKernelGGL(k_jmp_dl_big, dim3(kJmpBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t),
+                                   s, d, nbins);
                 tlaunch(h, 10, k_jmp_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_jmp_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_jmp_next, dim3(1), dim3(1), 0, s, d, 1);
             }
         }
         steps += first * kJmpGraphSteps;
-        first = 1;
+        first = std::min<int64_t>(first * 2, 16);   // rounds issued after a sweep's end return at once
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
