@@ -293,7 +293,7 @@ def main():
     ap.add_argument("--serve-graphs", type=int, default=64)
     ap.add_argument("--serve-scales", type=int, nargs=2, default=[16, 22])
     ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=8, help="graph slots per shard of the serving form")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -1062,6 +1062,12 @@ def run_orient(args, P, W, torch, np):
 
 
 def run_serve(args, P, W, torch, np):
+    """Configuration 5: resident R-MAT graphs behind the continuous-batching
+    server (shards of multi-graph handles; the pending requests of a shard's
+    graphs are served by one fused update call and one coreness call).
+    Request streams at saturation and at fractions of it; then the same
+    graphs and requests served one at a time with a plain handle per graph
+    (the per-graph plain launches), whose results must be identical."""
     import random
     from paper_2106_03824_amd import serve as S
 
@@ -1080,54 +1086,62 @@ def run_serve(args, P, W, torch, np):
     N = args.serve_requests
     admits = [S.Request(g, g, "admit", 0.0, graphs[g]) for g in graphs]
     retires = [S.Request(10 ** 9 + g, g, "retire", 0.0) for g in graphs]
-    srv = S.Server(1 << 60, args.workers)
+    srv = S.Server(1 << 60, slots=args.slots)
     t_build = srv.serve(fresh(admits), arrival=False)
-    log(f"admitted and built in {t_build:.1f}s")
+    log(f"admitted and built in {t_build:.1f}s ({len(srv.shards)} shards of {args.slots} slots)")
     applied = lambda tr: sum(r.result["applied_ins"] + r.result["applied_del"] for r in tr
                              if r.kind == "update" and r.result)
-    served, alone, runs = [], [], []
+    served, runs = [], []
     sat_rps = None
     for k, f in enumerate((None, 0.1, 0.5, 0.9, 1.2)):
         tr = S.make_updates(graphs, N, None if f is None else f * sat_rps, 5100 + k, rid0=(k + 1) * 10 ** 6)
-        alone.append(fresh(tr))
         served.append(tr)
+        c0, r0 = srv.fused_calls, srv.fused_requests
         wall = srv.serve(tr, arrival=f is not None)
         if f is None:
             sat_rps = N / wall
         runs.append({"rate_factor": f, "offered_per_s": None if f is None else f * sat_rps,
-                     "requests_per_s": N / wall, "updates_per_s": applied(tr) / wall, **S.latency_stats(tr)})
+                     "requests_per_s": N / wall, "updates_per_s": applied(tr) / wall,
+                     "requests_per_fused_call": (srv.fused_requests - r0) / max(srv.fused_calls - c0, 1),
+                     **S.latency_stats(tr)})
         log(f"rate {'saturation' if f is None else f}: {N / wall:.1f} requests/s, "
-            f"{applied(tr) / wall:.3e} updates/s, p50 {runs[-1]['p50_ms']:.2f} ms, p99 {runs[-1]['p99_ms']:.2f} ms")
+            f"{applied(tr) / wall:.3e} updates/s, p50 {runs[-1]['p50_ms']:.2f} ms, p99 {runs[-1]['p99_ms']:.2f} ms, "
+            f"{runs[-1]['requests_per_fused_call']:.1f} requests per fused call")
     mixed_ret = fresh(retires)
     srv.serve(mixed_ret, arrival=False)
     srv.close()
-    # the same graphs and requests, one request at a time
-    srv = S.Server(1 << 60, 1)
-    srv.serve(fresh(admits), arrival=False)
-    for tr in alone:
-        srv.serve(tr, arrival=False)
-    alone_ret = fresh(retires)
-    srv.serve(alone_ret, arrival=False)
-    srv.close()
+    # the same graphs and requests, one request at a time, a plain handle per graph
+    alone_all = fresh(admits) + [r for tr in served for r in fresh(tr)] + fresh(retires)
+    t = time.perf_counter()
+    S.serve_alone(alone_all, progress=lambda i: log(f"one at a time: {i} of {len(alone_all)} requests"))
+    log(f"one at a time: {time.perf_counter() - t:.1f}s")
+    by_rid = {r.rid: r for r in alone_all}
+    sat_alone = served[0]
+    t_alone = sum(by_rid[r.rid].done - by_rid[r.rid].start for r in sat_alone)
     same, errors = True, 0
-    for a, b in zip(served, alone):
-        for x, y in zip(a, b):
+    for tr in served:
+        for x in tr:
+            y = by_rid[x.rid]
             errors += (x.error is not None) + (y.error is not None)
             if x.kind == "query":
                 same = same and np.array_equal(x.result.view(np.int64), y.result.view(np.int64))
             elif x.kind == "update":
                 same = same and x.result == y.result
-    for x, y in zip(mixed_ret, alone_ret):
-        same = same and np.array_equal(x.result["levels"], y.result["levels"])
+    for x in mixed_ret:
+        same = same and np.array_equal(x.result["levels"], by_rid[x.rid].result["levels"])
     log(f"identical to one-at-a-time serving: {same}, errors {errors}")
     out = {
         "metric": METRIC, "value": runs[0]["updates_per_s"], "unit": "edge updates/s", "n_gpus": 1,
         "steps": N, "warmup": 0, "ms_per_step": 1e3 / sat_rps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"serving-{len(graphs)}-rmat-scale{lo}..{hi}-ef16", "graphs": len(graphs),
-                   "edges": m_total, "workers": args.workers, "requests_per_run": N,
+                   "edges": m_total, "slots_per_shard": args.slots, "requests_per_run": N,
                    "step": "one request: an update batch (1e2..1e6, 70% ins) or a 1e3-vertex coreness query"},
         "latency": runs, "identical_to_alone": same, "errors": errors, "build_s": t_build,
+        "one_at_a_time": {"updates_per_s": applied([by_rid[r.rid] for r in sat_alone]) / t_alone,
+                          "seconds": t_alone,
+                          "note": "the saturation run's requests served one at a time with a plain handle per "
+                                  "graph (sum of their service times)"},
     }
     print(json.dumps(out), flush=True)
 

@@ -151,6 +151,23 @@ int plds_create_multi(int32_t ngraphs, const int64_t *n, double delta, double la
 int plds_update_multi(plds_t *h, const int32_t *const *ins, const int64_t *n_ins, const int32_t *const *del,
                       const int64_t *n_del, void *stream);
 
+/* Applied updates per graph of the last plds_update_multi call: host
+ * arrays ins[ngraphs] and del[ngraphs] receive the unique new edges
+ * inserted into and the present edges deleted from each graph (for a plain
+ * handle, the last call's totals).  Waits for the work on `stream`. */
+int plds_graph_applied(plds_t *h, int64_t *ins, int64_t *del, void *stream);
+
+/* Empty graph g of a multi-graph handle and give it n_new vertices, 1 <=
+ * n_new <= the n it was created with (its capacity): all its edges are
+ * removed and its vertices sit at level 0; its levels per group and
+ * thresholds become those of a handle of n_new vertices (same delta,
+ * lambda, levels-per-group rule and coefficient), so from here on it goes
+ * through the states of a fresh plds_create_ex(n_new, ...) handle.  Ids of
+ * its later batches must lie in [0, n_new).  The other graphs are untouched.
+ * A serving loop reuses a graph slot for a newly admitted graph this way.
+ * Returns after the work on `stream` is complete. */
+int plds_reset_graph(plds_t *h, int32_t g, int64_t n_new, void *stream);
+
 /* Graph g of a handle: *vertex_base receives its first global vertex id,
  * *out its n, t, L, G, K (m, delta, lambda and the slab figures are those
  * of the whole handle).  Either pointer may be NULL. */

@@ -153,6 +153,7 @@ struct Dev {
     int32_t *gid;                     // [n] graph of each vertex (ng > 1)
     int32_t *gL, *gK, *gtab;          // [ng] levels per group, levels, table offset
     int32_t *Ls;                      // [nLs] the distinct levels-per-group values
+    unsigned long long *gapp;         // [2][ng] applied insertions / deletions per graph of the last call (ng > 1)
     int32_t nLs;
     int32_t *level, *deg, *up, *ups, *cap, *fill;
     int64_t *off;
@@ -2050,7 +2051,7 @@ struct Srch {
     int32_t lo, hi, clamp, up;   // up = 0: dn_min[g], 1: up_max[g] + 1
 };
 __device__ __forceinline__ int32_t srch_thr(const Dev &d, GP p, const Srch &q, int32_t j) {
-    return q.up ? d.up_max[p.tab + j / p.L] + 1 : d.dn_min[p.tab + j / p.L];
+    return q.up ? min(d.up_max[p.tab + j / p.L], INT32_MAX - 1) + 1 : d.dn_min[p.tab + j / p.L];
 }
 
 // One wavefront (every lane calls it; w is wave-uniform, cap = d.cap[w] <= kDlWaveCap).
@@ -3687,6 +3688,71 @@ __global__ void k_clear_touch(Dev d) {
     }
 }
 
+// Empty the vertex range [v0, v0+cnt) (one graph of a multi-graph handle):
+// its vertices lose their slabs (the pool space is reclaimed by the next
+// compaction) and go to level 0 (occupancy moved with one atomic per
+// distinct level of a wavefront); their degrees are summed into m_out.
+__global__ void k_reset_range(Dev d, int32_t v0, int32_t cnt) {
+    const int lane = threadIdx.x % kWave;
+    int64_t deg = 0, up0 = 0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < cnt; i0 += stride) {
+        const int i = i0 + lane;
+        const int32_t v = i < cnt ? v0 + i : -1;
+        const int32_t lv = v >= 0 ? d.level[v] : -1;
+        wave_add_key(d.occ, lv > 0 ? lv : -1, -1);
+        if (v < 0) continue;
+        up0 += lv > 0;
+        deg += d.deg[v];
+        d.level[v] = 0;
+        d.deg[v] = d.up[v] = d.ups[v] = 0;
+        d.cap[v] = d.fill[v] = 0;
+        d.off[v] = 0;
+        d.addc[v] = d.stay[v] = d.cnt2[v] = 0;
+        d.dl[v] = -1;
+        if (d.prevlvl) d.prevlvl[v] = 0;
+    }
+    block_add64_to(deg, (unsigned long long *)&d.ctl->m_out);
+    block_add64_to(up0, (unsigned long long *)&d.ctl->sum_up);
+}
+
+// Applied pairs of the list just applied (valid[0..n_valid)), per graph of
+// a multi-graph handle, into gapp[which][g]: an LDS histogram per block
+// when the graphs are few, else one atomic per distinct graph of a wavefront.
+constexpr int kGraphHist = 8192;
+__global__ void k_graph_count(Dev d, int which) {
+    __shared__ int32_t hist[kGraphHist];
+    const bool lds = d.ng <= kGraphHist;
+    if (lds) {
+        for (int i = threadIdx.x; i < d.ng; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+    }
+    const int32_t nv = d.ctl->n_valid;
+    unsigned long long *out = d.gapp + (size_t)which * d.ng;
+    const int lane = threadIdx.x % kWave;
+    for (int i0 = blockIdx.x * blockDim.x + threadIdx.x - lane; i0 < nv; i0 += gridDim.x * blockDim.x) {
+        const int i = i0 + lane;
+        const int32_t g = i < nv ? d.gid[d.valid[2 * i]] : -1;
+        if (lds) {
+            if (g >= 0) atomicAdd(&hist[g], 1);
+        } else {
+            uint64_t todo = __ballot(g >= 0);
+            while (todo) {
+                const int leader = __ffsll((unsigned long long)todo) - 1;
+                const int32_t k = __shfl(g, leader, kWave);
+                const uint64_t same = __ballot(g == k) & todo;
+                if (lane == leader) atomicAdd(&out[k], (unsigned long long)__popcll(same));
+                todo &= ~same;
+            }
+        }
+    }
+    if (lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < d.ng; i += blockDim.x)
+            if (hist[i]) atomicAdd(&out[i], (unsigned long long)hist[i]);
+    }
+}
+
 __global__ void k_set_levels(Dev d, const int32_t *lv) {
     int stride = gridDim.x * blockDim.x;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) {
@@ -3836,6 +3902,8 @@ struct plds {
     // graphs of a multi-graph handle (one entry for a plain handle)
     std::vector<Tables> gt;
     std::vector<int64_t> gbase, gn;           // first vertex and vertex count of each graph
+    std::vector<int64_t> gcap;                // vertices of each graph's range (its n at create)
+    std::vector<int32_t> gcapG;               // groups of each graph's table region (its G at create)
     std::vector<int32_t> gtab;
     int32_t *stage = nullptr;                 // gathered multi-graph batch
     int64_t stage_cap = 0;                    // pairs
@@ -3982,7 +4050,7 @@ void build_tables(plds *h, int32_t lpg) {
 void free_all(plds *h) {
     Dev &d = h->d;
     dfree(d.up_max), dfree(d.dn_min), dfree(d.pow_tab);
-    dfree(d.gid), dfree(d.gL), dfree(d.gK), dfree(d.gtab), dfree(d.Ls);
+    dfree(d.gid), dfree(d.gL), dfree(d.gK), dfree(d.gtab), dfree(d.Ls), dfree(d.gapp);
     dfree(h->stage), dfree(h->d_segs);
     if (h->h_segs) (void)hipHostFree(h->h_segs);
     h->h_segs = nullptr;
@@ -4246,6 +4314,8 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
         }
     }
     *applied = h->h_ctl->n_valid;
+    if (d.ng > 1 && *applied)
+        hipLaunchKernelGGL(k_graph_count, dim3(grid_for(*applied, kBlock, 256)), dim3(kBlock), 0, s, d, insert ? 0 : 1);
     // From here on the dedupe pass has counted this list's edges per
     // endpoint (addc) and listed the endpoints: a failure leaves the handle
     // unusable rather than half-applied.
@@ -4785,6 +4855,7 @@ int create_impl(int32_t ngraphs, const int64_t *ns, double delta, double lambda,
     for (int32_t g = 0, b = 0; g < ngraphs; b += (int32_t)ns[g], g++) {
         h->gbase.push_back(b);
         h->gn.push_back(ns[g]);
+        h->gcap.push_back(ns[g]);
     }
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
@@ -4801,6 +4872,7 @@ int create_impl(int32_t ngraphs, const int64_t *ns, double delta, double lambda,
             h->scan_grid = std::max(256, std::min(std::min(per, kScanPerCU) * ncu, kSweepGrid));
     }
     build_tables(h, levels_per_group);
+    for (auto &t : h->gt) h->gcapG.push_back(t.G);
     if ((int64_t)h->G * h->L >= (int64_t)kLevelMask) {   // levels must fit under the mover flags
         delete h;
         return PLDS_EINVAL;
@@ -4822,7 +4894,7 @@ int create_impl(int32_t ngraphs, const int64_t *ns, double delta, double lambda,
     int rc = 0;
     rc |= dalloc(&d.up_max, ntab) | dalloc(&d.dn_min, ntab) | dalloc(&d.pow_tab, ntab);
     rc |= dalloc(&d.gL, ngraphs) | dalloc(&d.gK, ngraphs) | dalloc(&d.gtab, ngraphs) | dalloc(&d.Ls, d.nLs);
-    if (ngraphs > 1) rc |= dalloc(&d.gid, n);
+    if (ngraphs > 1) rc |= dalloc(&d.gid, n) | dalloc(&d.gapp, 2 * (int64_t)ngraphs);
     rc |= dalloc(&d.level, n) | dalloc(&d.deg, n) | dalloc(&d.up, n) | dalloc(&d.ups, n);
     rc |= dalloc(&d.cap, n) | dalloc(&d.fill, n) | dalloc(&d.off, n);
     rc |= dalloc(&d.stay, n) | dalloc(&d.cnt2, n) | dalloc(&d.addc, n) | dalloc(&d.dl, n) | dalloc(&d.rcstamp, n);
@@ -5070,12 +5142,86 @@ int plds_update_multi(plds_t *h, const int32_t *const *ins, const int64_t *n_ins
         }
     rc = begin_call(h, s);
     if (rc) return rc;
+    if (h->d.gapp) HIPCHK(hipMemsetAsync(h->d.gapp, 0, 2 * (size_t)ng * sizeof(unsigned long long), s));
     HIPCHK(hipMemcpyAsync(h->d_segs, h->h_segs, nseg * sizeof(Seg), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_stage, dim3(grid_for(ti + td)), dim3(kBlock), 0, s, h->d_segs, nseg, ti + td, h->stage,
                        h->d.ctl);
     HIPCHK(hipGetLastError());
     h->range_pending = true;   // read back by the first batch application
     return run_update(h, h->stage, ti, h->stage + 2 * ti, td, s);
+}
+
+int plds_graph_applied(plds_t *h, int64_t *ins, int64_t *del, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (!ins || !del) return PLDS_EINVAL;
+    const int32_t ng = h->d.ng;
+    if (ng == 1) {
+        ins[0] = h->stats.applied_ins;
+        del[0] = h->stats.applied_del;
+        return PLDS_OK;
+    }
+    std::vector<unsigned long long> buf(2 * (size_t)ng);
+    HIPCHK(hipMemcpyAsync(buf.data(), h->d.gapp, buf.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          S(stream)));
+    HIPCHK(hipStreamSynchronize(S(stream)));
+    for (int32_t g = 0; g < ng; g++) {
+        ins[g] = (int64_t)buf[g];
+        del[g] = (int64_t)buf[ng + g];
+    }
+    return PLDS_OK;
+}
+
+int plds_reset_graph(plds_t *h, int32_t g, int64_t n_new, void *stream) {
+    int rc = guard(h);
+    if (rc) return rc;
+    if (g < 0 || g >= h->d.ng || n_new < 1 || n_new > h->gcap[g]) return PLDS_EINVAL;
+    hipStream_t s = S(stream);
+    Dev &d = h->d;
+    // the tables of a handle of n_new vertices, in the graph's table region
+    // (sized for its capacity: G and K only grow with n)
+    Tables T = make_tables(n_new, h->delta, h->lambda, h->lpg, h->up_coeff);
+    if (T.G > h->gcapG[g]) return PLDS_EINVAL;
+    const int32_t tab = h->gtab[g];
+    HIPCHK(hipMemcpyAsync(d.up_max + tab, T.up.data(), T.up.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.dn_min + tab, T.dn.data(), T.dn.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.pow_tab + tab, T.pw.data(), T.pw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.gL + g, &T.L, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.gK + g, &T.K, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    h->h_ctl->m_out = 0;
+    h->h_ctl->sum_up = 0;
+    HIPCHK(hipMemcpyAsync(&d.ctl->m_out, &h->h_ctl->m_out, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(&d.ctl->sum_up, &h->h_ctl->sum_up, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const int32_t cnt = (int32_t)h->gcap[g];
+    hipLaunchKernelGGL(k_reset_range, dim3(grid_for(cnt)), dim3(kBlock), 0, s, d, (int32_t)h->gbase[g], cnt);
+    HIPCHK(hipGetLastError());
+    rc = sync_ctl(h, s);
+    if (rc) return rc;
+    int32_t moved = (int32_t)h->h_ctl->sum_up;   // vertices that came down to level 0
+    if (moved) {
+        int32_t occ0 = 0;
+        HIPCHK(hipMemcpy(&occ0, d.occ, sizeof(int32_t), hipMemcpyDeviceToHost));
+        occ0 += moved;
+        HIPCHK(hipMemcpy(d.occ, &occ0, sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    h->m -= h->h_ctl->m_out / 2;
+    h->gn[g] = n_new;
+    h->gt[g] = std::move(T);
+    // the distinct levels-per-group values of the graphs (multi-level step bounds)
+    std::vector<int32_t> hLs;
+    for (auto &t : h->gt)
+        if (std::find(hLs.begin(), hLs.end(), t.L) == hLs.end()) hLs.push_back(t.L);
+    if ((int32_t)hLs.size() > d.nLs) {
+        dfree(d.Ls);
+        if (dalloc(&d.Ls, (int64_t)hLs.size())) {
+            h->broken = true;
+            return PLDS_ENOMEM;
+        }
+    }
+    d.nLs = (int32_t)hLs.size();
+    HIPCHK(hipMemcpy(d.Ls, hLs.data(), hLs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    memset(&h->stats, 0, sizeof(h->stats));
+    return PLDS_OK;
 }
 
 int plds_graph_info(const plds_t *h, int32_t g, int64_t *vertex_base, plds_info_t *out) {

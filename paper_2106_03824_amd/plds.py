@@ -73,6 +73,8 @@ def lib():
                                         ctypes.POINTER(_VP)]
         L.plds_update_multi.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
         L.plds_graph_info.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(_I64), ctypes.POINTER(plds_info_t)]
+        L.plds_reset_graph.argtypes = [_VP, ctypes.c_int32, _I64, _VP]
+        L.plds_graph_applied.argtypes = [_VP, _VP, _VP, _VP]
         L.plds_update.argtypes = [_VP, _VP, _I64, _VP, _I64, _VP]
         L.plds_batch_insert.argtypes = [_VP, _VP, _I64, _VP]
         L.plds_batch_delete.argtypes = [_VP, _VP, _I64, _VP]
@@ -112,7 +114,8 @@ EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi",
            "plds_stats", "plds_set_timing", "plds_set_sweep_mode", "plds_step_log", "plds_dump_state", "plds_load_state", "plds_check", "plds_sync", "plds_strerror",
            "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value",
            "plds_static_kcore", "plds_static_kcore_noalloc", "plds_delete_vertices", "plds_rebuild",
-           "plds_inject_alloc_failure", "plds_create_opts")
+           "plds_inject_alloc_failure", "plds_create_opts", "plds_reset_graph",
+           "plds_graph_applied")
 
 
 def strerror(code):
@@ -205,6 +208,19 @@ def plds_update_multi(h, ins=None, dele=None, stream=None, check=True):
     rc = lib().plds_update_multi(h, ai[0] if ai else None, ai[1] if ai else None, ad[0] if ad else None,
                                  ad[1] if ad else None, _stream(stream))
     return _chk(rc, "plds_update_multi") if check else rc
+
+
+def plds_graph_applied(h, ngraphs, stream=None):
+    """(applied insertions, applied deletions) per graph of the last update call."""
+    a = (ctypes.c_int64 * ngraphs)()
+    b = (ctypes.c_int64 * ngraphs)()
+    _chk(lib().plds_graph_applied(h, ctypes.addressof(a), ctypes.addressof(b), _stream(stream)),
+         "plds_graph_applied")
+    return list(a), list(b)
+
+
+def plds_reset_graph(h, g, n_new, stream=None):
+    return _chk(lib().plds_reset_graph(h, int(g), int(n_new), _stream(stream)), "plds_reset_graph")
 
 
 def plds_graph_info(h, g):
@@ -522,6 +538,12 @@ class MultiPLDS(PLDS):
         dev = lambda lists: None if lists is None else [self._dev(e) if e is not None and len(e) else None
                                                         for e in lists]
         return plds_update_multi(self.h, dev(ins), dev(dele), check=check)
+
+    def reset_graph(self, g, n_new, stream=None):
+        """Empty graph g and give it n_new (<= its capacity) vertices."""
+        plds_reset_graph(self.h, g, n_new, stream)
+        self.ns[g] = int(n_new)
+        self.graphs[g] = plds_graph_info(self.h, g)
 
     def graph_levels(self, g, levels=None):
         lv = self.levels() if levels is None else levels

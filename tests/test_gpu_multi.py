@@ -121,3 +121,50 @@ def test_multi_range_is_per_graph():
     assert mg.update_multi(ins=None, dele=[None, [(0, 19)]]) == 0
     assert mg.info()["m"] == 2
     assert mg.check() == 0
+
+
+def test_reset_graph_reuses_a_slot():
+    """plds_reset_graph empties a graph slot and gives it a new n (at most
+    its capacity): the new graph then goes through the states of a plain
+    handle of its own n (compared with the oracle after every batch), the
+    other graphs are untouched, and per-graph applied counts are reported."""
+    from paper_2106_03824_amd import plds as P
+    cap = 4096
+    mg = P.MultiPLDS([cap, cap, cap])
+    e0 = W.rmat(12, 8 * cap, seed=61)
+    e2 = W.rmat(11, 8 * 2048, seed=62)
+    say("reset graph: fill slots 0 and 2")
+    assert mg.update_multi([e0, None, None]) == 0
+    assert mg.update_multi([None, None, e2]) == 0
+    ai, ad = P.plds_graph_applied(mg.h, 3)
+    assert ai == [0, 0, len(np.unique(np.sort(e2, axis=1), axis=0))] and ad == [0, 0, 0]
+    lv2 = mg.graph_levels(2).cpu().numpy().copy()
+    o0 = O.Oracle(cap)
+    assert o0.insert(e0) == 0
+    assert np.array_equal(mg.graph_levels(0).cpu().numpy(), o0.levels())
+    m_before = mg.info()["m"]
+    for n_new, seed in ((1000, 63), (3000, 64)):      # slot 0 reused twice, with other sizes
+        say("reset graph: slot 0 to n", n_new)
+        mg.reset_graph(0, n_new)
+        assert mg.graphs[0]["n"] == n_new and mg.graphs[0]["L"] == O.Oracle(n_new).L
+        assert mg.info()["m"] == m_before - o0.m
+        assert (mg.graph_levels(0).cpu().numpy() == 0).all()
+        o0 = O.Oracle(n_new)
+        e = W.er(n_new, 12.0 / n_new, seed=seed)
+        for ins, dele in ((e, None), (W.new_pairs(n_new, e, 2000, seed + 1), W.sample_edges(e, 1500, seed + 2))):
+            assert mg.update_multi([ins, None, None], [dele, None, None] if dele is not None else None) == 0
+            assert o0.update(ins, dele) == 0
+            assert np.array_equal(mg.graph_levels(0).cpu().numpy(), o0.levels())
+            assert np.array_equal(mg.degrees().cpu().numpy()[:n_new], o0.degrees())
+            s = o0.stats()
+            ai, ad = P.plds_graph_applied(mg.h, 3)
+            assert (ai[0], ad[0]) == (s["applied_ins"], s["applied_del"]) and ai[1:] == [0, 0] and ad[1:] == [0, 0]
+        m_before = mg.info()["m"]
+        assert np.array_equal(mg.graph_levels(2).cpu().numpy(), lv2)
+        # ids of the old, larger graph are now out of range
+        bad = np.array([[0, n_new]], dtype=np.int32)
+        assert mg.update_multi([bad, None, None], check=False) == P.PLDS_ERANGE
+    assert mg.check() == 0
+    with pytest.raises(P.PLDSError):
+        mg.reset_graph(1, cap + 1)
+    mg.close()

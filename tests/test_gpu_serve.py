@@ -1,8 +1,10 @@
-"""Serving loop: requests of many graphs served by several workers at once,
-arriving as a Poisson stream, give exactly the results of serving each
-graph alone (one request at a time, in arrival order), and both equal the
-CPU oracle replaying each graph's requests in order (levels at retirement
-and every coreness query)."""
+"""Serving loop with continuous batching: requests of many graphs arriving as
+a Poisson stream are served in fused multi-graph calls (the updates of all
+graphs of a shard with work in one plds_update_multi, their queries in one
+plds_coreness), and must give exactly the results of serving each request
+alone with a plain handle per graph (serve_alone), and those of the CPU
+oracle replaying each graph's requests in order (levels at retirement and
+every coreness query)."""
 import copy
 import random
 import sys
@@ -97,18 +99,22 @@ def same(a, b):
 
 
 def test_serving_mix_equals_alone_equals_oracle():
-    from paper_2106_03824_amd.serve import replay
+    from paper_2106_03824_amd.serve import replay, serve_alone
     reqs = make_trace(10, 120, 5, rate=4000.0)
     alone = copy.deepcopy(reqs)
-    say("serve: mixed, 6 workers, Poisson arrivals")
-    replay(reqs, budget_bytes=64 << 30, workers=6, arrival=True)
-    say("serve: alone, 1 worker")
-    replay(alone, budget_bytes=64 << 30, workers=1, arrival=False)
+    say("serve: fused, shards of 4 slots, Poisson arrivals")
+    replay(reqs, budget_bytes=64 << 30, slots=4, arrival=True)
+    say("serve: alone, a plain handle per graph")
+    serve_alone(alone)
     say("serve: oracle replay")
     ref = oracle_replay(reqs)
     same(results(reqs), results(alone))
     same(results(reqs), ref)
-    # the mixed run really overlapped requests of different graphs
+    for a, b in zip(sorted(reqs, key=lambda r: r.rid), sorted(alone, key=lambda r: r.rid)):
+        if a.kind == "update":
+            assert a.result == b.result, (a.rid, a.result, b.result)
+    # requests of different graphs were served by one fused call
+    assert max(r.fused for r in reqs) > 1
     spans = sorted((r.start, r.done, r.graph) for r in reqs)
     assert any(b[0] < a[1] and b[2] != a[2] for a, b in zip(spans, spans[1:]))
 
@@ -116,44 +122,44 @@ def test_serving_mix_equals_alone_equals_oracle():
 def test_serving_admission_waits_for_budget():
     """With room for about two graphs at a time, admissions queue behind
     retirements and results are unchanged."""
-    from paper_2106_03824_amd.serve import footprint_bytes, replay
+    from paper_2106_03824_amd.serve import footprint_bytes, replay, serve_alone
     reqs = make_trace(5, 30, 9, rate=4000.0)
     alone = copy.deepcopy(reqs)
     biggest = max(footprint_bytes(r.payload[0], len(r.payload[1])) for r in reqs if r.kind == "admit")
     say("serve: small budget")
-    replay(reqs, budget_bytes=2 * biggest, workers=4, arrival=True)
-    replay(alone, budget_bytes=64 << 30, workers=1, arrival=False)
+    replay(reqs, budget_bytes=2 * biggest, slots=2, arrival=True)
+    serve_alone(alone)
     same(results(reqs), results(alone))
 
 
-def test_failed_admission_drains(monkeypatch):
-    """A graph whose handle cannot be created (the library's ENOMEM, forced
-    here) frees its footprint; its later requests fail with the admission's
-    error, the loop drains, and the other graphs are served as alone."""
+def test_failed_admission_drains():
+    """A graph whose shard cannot be created (the library's ENOMEM, forced by
+    failing its first allocation) fails its admission; its later requests
+    fail at once with that error, the loop drains, and the other graph is
+    served as alone."""
     from paper_2106_03824_amd import plds as P
     from paper_2106_03824_amd import serve as S
     say("serve: failed admission")
-    real = P.PLDS
-
-    class Refused(real):
-        def __init__(self, n, *a, **k):
-            if n == 777:
-                raise P.PLDSError(P.PLDS_ENOMEM, "plds_create")
-            super().__init__(n, *a, **k)
-
-    monkeypatch.setattr(S.P, "PLDS", Refused)
     n = 2 ** 10
     e = W.rmat(10, 8 * n, seed=5)
-    reqs = [S.Request(0, "a", "admit", 0.0, (n, e)), S.Request(1, "bad", "admit", 0.0, (777, e[:10])),
-            S.Request(2, "bad", "update", 0.0, (e[:5], None)), S.Request(3, "bad", "query", 0.0,
-                                                                      np.arange(5, dtype=np.int32)),
+    bad_n = 5000          # a size class of its own, so its admission needs a new shard
+    srv = S.Server(budget_bytes=1 << 40, slots=2)
+    reqs = [S.Request(0, "a", "admit", 0.0, (n, e)), S.Request(1, "bad", "admit", 0.0, (bad_n, e[:10])),
+            S.Request(2, "bad", "update", 0.0, (e[:5], None)),
+            S.Request(3, "bad", "query", 0.0, np.arange(5, dtype=np.int32)),
             S.Request(4, "a", "query", 0.0, np.arange(50, dtype=np.int32)), S.Request(5, "bad", "retire", 0.0),
             S.Request(6, "a", "retire", 0.0)]
-    srv = S.Server(budget_bytes=1 << 40, workers=2)
     try:
-        srv.serve(reqs, arrival=False)
-        assert srv.used == 0 and not srv.handles
+        srv.submit(reqs[0])
+        P.plds_inject_alloc_failure(0)       # this thread creates the shards
+        srv.submit(reqs[1])
+        P.plds_inject_alloc_failure(-1)
+        for r in reqs[2:]:
+            srv.submit(r)
+        srv.drain()
+        assert srv.used == 0 and not srv.where
     finally:
+        P.plds_inject_alloc_failure(-1)
         srv.close()
     assert isinstance(reqs[1].error, P.PLDSError)
     for r in reqs[2:4] + [reqs[5]]:
