@@ -36,18 +36,24 @@ measured batch per graph (insertion or deletion with probability 1/2, size
 uniform in [10^3, 5*10^4], deletions clamped to m).  The measured batches
 of all graphs go through one multi-graph handle in one call (the value), and
 through one plain handle per graph in a loop; the levels of both must be
-identical.
+identical.  Before measuring, the launch schedule of the multi-graph handle
+is searched (paper_2106_03824_amd/autotune.py) on a second batch per graph
+drawn with other seeds; the fused call is timed under the default schedule
+and under the one found, each from the post-build state, median of --steps
+runs.
 
-    python bench.py --batched
+    python bench.py --batched [--tune-record search.json]
 
 With --serve it runs the serving form: 64 resident R-MAT graphs (scale
-uniform in [16, 22], edge factor 16) behind the request loop of
-paper_2106_03824_amd/serve.py with 8 worker streams.  Request streams (half
-update batches of log-uniform size in [10^2, 10^6], 70% insertions; half
-coreness queries of 10^3 vertices) are served first all at once (the
+uniform in [16, 22], edge factor 16) behind the continuous-batching server
+of paper_2106_03824_amd/serve.py (shards of --slots graphs, each a
+multi-graph handle; a shard pass serves the pending requests of distinct
+graphs with one fused update call and one coreness call).  Request streams
+(half update batches of log-uniform size in [10^2, 10^6], 70% insertions;
+half coreness queries of 10^3 vertices) are served first all at once (the
 saturation rate), then as Poisson streams at 10%, 50%, 90% and 120% of it;
 p50/p99 latency per rate.  Afterwards the same graphs and requests are
-served again by one worker, one request at a time, and every query result
+served one at a time with a plain handle per graph, and every query result
 and final level must be identical.
 
     python bench.py --serve [--serve-scales 16 22] [--serve-graphs 64]
@@ -274,6 +280,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", action="store_true", help="the batched form: 256 graphs in one handle")
     ap.add_argument("--graphs", type=int, default=256)
+    ap.add_argument("--tune-reps", type=int, default=3, help="timed runs per schedule of the batched search")
+    ap.add_argument("--tune-record", default=None, help="where the batched form writes its schedule search (JSON)")
     ap.add_argument("--serve", action="store_true", help="the serving form: resident graphs behind a request loop")
     ap.add_argument("--opt", action="store_true",
                     help="the default RMAT-20 stream with the PLDSOpt level structure (ceil(log_{1+delta} n / 50) "
@@ -766,17 +774,35 @@ def batched_workload(k, W, np):
     return graphs
 
 
+def tuning_batches(graphs, W):
+    """One more batch per graph, of the measured batch's kind and size, drawn
+    with other seeds (4700 + i): the schedule search runs on these, never on
+    the measured batches."""
+    out = []
+    for i, (n, e, (kind, b)) in enumerate(graphs):
+        size = len(b)
+        out.append((kind, W.new_pairs(n, e, size, 4700 + i) if kind == "ins"
+                    else W.sample_edges(e, min(size, len(e)), 4700 + i)))
+    return out
+
+
 def run_batched(args, P, W, torch, np):
+    from paper_2106_03824_amd import autotune as AT
     k = args.graphs
     t = time.perf_counter()
     graphs = batched_workload(k, W, np)
+    tunes = tuning_batches(graphs, W)
     ns = [n for n, _, _ in graphs]
     log(f"{k} graphs, {sum(ns)} vertices, {sum(len(e) for _, e, _ in graphs)} edges, "
         f"generated in {time.perf_counter() - t:.1f}s")
     dev = torch.device("cuda", 0)
-    build = [torch.from_numpy(np.ascontiguousarray(e)).to(dev) for _, e, _ in graphs]
-    meas = [torch.from_numpy(np.ascontiguousarray(b)).to(dev) for _, _, (_, b) in graphs]
+    gpu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    build = [gpu(e) for _, e, _ in graphs]
     kinds = [kd for _, _, (kd, _) in graphs]
+    split = lambda bs: ([bs[g] if kinds[g] == "ins" else None for g in range(k)],
+                        [bs[g] if kinds[g] == "del" else None for g in range(k)])
+    ins_l, del_l = split([gpu(b) for _, _, (_, b) in graphs])
+    tin_l, tdel_l = split([gpu(b) for _, b in tunes])
     mg = P.MultiPLDS(ns)
     singles = [P.PLDS(n) for n in ns]
     mg.update_multi(ins=build)
@@ -784,39 +810,69 @@ def run_batched(args, P, W, torch, np):
         P.plds_update(singles[g].h, build[g], None)
     torch.cuda.synchronize()
     log("built")
-    ins_l = [meas[g] if kinds[g] == "ins" else None for g in range(k)]
-    del_l = [meas[g] if kinds[g] == "del" else None for g in range(k)]
-    # the plain per-graph loop
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    u_loop = 0
-    for g in range(k):
-        P.plds_update(singles[g].h, ins_l[g], del_l[g])
-        s = singles[g].stats()
-        u_loop += s["applied_ins"] + s["applied_del"]
-    torch.cuda.synchronize()
-    t_loop = time.perf_counter() - t0
-    # the batched form: one call for all graphs
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    P.plds_update_multi(mg.h, ins_l, del_l)
-    torch.cuda.synchronize()
-    t_fused = time.perf_counter() - t0
-    s = mg.stats()
-    u_fused = s["applied_ins"] + s["applied_del"]
+    # the schedule search, on the tuning batches
+    best, rec = AT.tune(mg, lambda: P.plds_update_multi(mg.h, tin_l, tdel_l), torch, reps=args.tune_reps,
+                        log=log, path=args.tune_record, workload=f"batched-{k}-graphs tuning batches")
+    log(f"tuned schedule {best}: {rec['best']['ms']:.2f} ms vs default {rec['default']['ms']:.2f} ms "
+        f"({len(rec['trials'])} schedules timed)")
+    reps = max(args.steps, 1)
+    e0, l0 = mg.dump()
+    s_state = [sg.dump() for sg in singles]
+
+    def fused(cfg):
+        P.plds_set_launch(mg.h, **cfg)
+        ts = []
+        for r in range(reps + 1):
+            mg.load(e0, l0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.plds_update_multi(mg.h, ins_l, del_l)
+            torch.cuda.synchronize()
+            if r:
+                ts.append(time.perf_counter() - t0)
+        st = mg.stats()
+        return sorted(ts)[len(ts) // 2], st["applied_ins"] + st["applied_del"], st
+
+    def loop():
+        ts = []
+        for r in range(reps + 1):
+            for g in range(k):
+                singles[g].load(*s_state[g])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, steps = 0, []
+            for g in range(k):
+                P.plds_update(singles[g].h, ins_l[g], del_l[g])
+                st = singles[g].stats()
+                u += st["applied_ins"] + st["applied_del"]
+                steps.append(st["sweeps_ins"] + st["sweeps_del"])
+            torch.cuda.synchronize()
+            if r:
+                ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2], u, steps
+
+    t_def, u_def, _ = fused({})
+    lv_def = mg.levels()
+    t_fused, u_fused, s = fused(best)
     lv = mg.levels()
-    same = all(torch.equal(mg.graph_levels(g, lv), singles[g].levels()) for g in range(k))
-    log(f"loop {u_loop} updates in {t_loop * 1e3:.1f} ms, batched {u_fused} in {t_fused * 1e3:.1f} ms, "
-        f"identical levels: {same}")
+    t_loop, u_loop, loop_steps = loop()
+    same = torch.equal(lv, lv_def) and all(torch.equal(mg.graph_levels(g, lv), singles[g].levels())
+                                           for g in range(k))
+    log(f"loop {u_loop} updates in {t_loop * 1e3:.1f} ms, batched {u_fused} in {t_fused * 1e3:.1f} ms "
+        f"(default schedule {t_def * 1e3:.1f} ms), identical levels: {same}")
     out = {
-        "metric": METRIC, "value": u_fused / t_fused, "unit": "edge updates/s", "n_gpus": 1, "steps": 1,
-        "warmup": 0, "ms_per_step": t_fused * 1e3, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": u_fused / t_fused, "unit": "edge updates/s", "n_gpus": 1, "steps": reps,
+        "warmup": 1, "ms_per_step": t_fused * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"batched-{k}-graphs-er-rmat-n2^10..2^16", "graphs": k, "vertices": sum(ns),
-                   "delta": 0.4, "lambda": 3.0, "step": "one measured batch per graph, all graphs in one call"},
+                   "delta": 0.4, "lambda": 3.0,
+                   "step": "one measured batch per graph, all graphs in one call, from the post-build state"},
         "per_graph_loop": {"value": u_loop / t_loop, "ms": t_loop * 1e3},
+        "default_schedule": {"value": u_def / t_def, "ms": t_def * 1e3},
+        "schedule": best, "schedules_timed": len(rec["trials"]),
         "speedup_vs_loop": t_loop / t_fused,
-        "identical_levels": same, "updates": u_fused, "sweeps": s["sweeps_ins"] + s["sweeps_del"],
+        "identical_levels": same, "updates": u_fused, "level_steps": s["sweeps_ins"] + s["sweeps_del"],
+        "level_steps_alone": {"max": max(loop_steps), "sum": sum(loop_steps)},
     }
     print(json.dumps(out), flush=True)
 

@@ -341,6 +341,35 @@ int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
  * way. */
 int plds_set_sweep_mode(plds_t *h, int32_t mode);
 
+/* Launch schedule of the level loops.  Every field chooses how many
+ * workgroups (blocks) a kernel of the sweeps gets, or how the steps are
+ * grouped into prebuilt HIP graphs; none changes what is computed, so levels,
+ * coreness and statistics other than timings are identical under every
+ * schedule.  0 in a field selects the default.
+ *   scan_blocks      blocks of the insertion scan, 64..2048 (default: the
+ *                    blocks the device holds at once, at most 5 per CU);
+ *   graph_steps      insertion steps per prebuilt step graph, even, 2..64
+ *                    (default 16); steps issued past a sweep's end return
+ *                    at once but still cost their launch;
+ *   dl_blocks        blocks of the desire-level kernels of deletions and
+ *                    of upward jumps, 64..4096 (default 1024);
+ *   del_scan_blocks  blocks of the deletion scan and of the jump scan,
+ *                    64..8192 (default 2048).
+ * reserved must be zero.  Out-of-range values: PLDS_EINVAL, nothing
+ * changed.  The setting belongs to the handle (plds_rebuild carries it over)
+ * and takes effect at the next update call; it is what a schedule search
+ * (an autotuner timing candidate schedules on a workload) sets. */
+typedef struct {
+    int32_t scan_blocks;
+    int32_t graph_steps;
+    int32_t dl_blocks;
+    int32_t del_scan_blocks;
+    int32_t reserved[4];
+} plds_launch_t;
+int plds_set_launch(plds_t *h, const plds_launch_t *cfg);
+/* The schedule in force, defaults resolved (no field is 0). */
+int plds_get_launch(const plds_t *h, plds_launch_t *out);
+
 /* Failure injection, for tests of error handling: after `after` more device
  * allocations by the library on the calling thread, the next one fails (the
  * call that makes it returns PLDS_ENOMEM), then allocations succeed again;

@@ -46,6 +46,7 @@ constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels (most blocks
 // than one resident round) 14% slower.
 constexpr int kScanPerCU = 5;
 constexpr int kDlGrid = 1024;        // blocks of the desire-level kernel
+constexpr int kGraphStepsDef = 16;   // insertion steps per prebuilt step graph (default)
 constexpr int kListGrid = 256;       // blocks of the per-mover list kernels
 constexpr int kApplyGrid = 1024;     // most blocks of the batch-application kernels
 constexpr int32_t kInf = INT32_MAX;
@@ -3929,8 +3930,12 @@ struct plds {
     int sweep_mode = 1;          // 0: cooperative when possible, 1: one kernel per part
     int coop_blocks = -1;        // -1 = not yet determined
     int scan_grid = kSweepGrid;  // blocks of the insertion scan: what the device holds at once
+    int scan_grid_def = kSweepGrid;   // the device default of scan_grid
+    int graph_steps = kGraphStepsDef; // insertion steps per prebuilt step graph
+    int dl_grid = kDlGrid;            // blocks of the desire-level kernels of deletions and jumps
+    int del_scan_grid = kSweepGrid;   // blocks of the deletion and jump scans
     Bar *bar = nullptr;
-    // the insertion step sequence as a prebuilt graph of kGraphSteps steps
+    // the insertion step sequence as a prebuilt graph of graph_steps steps
     hipGraph_t ins_graph = nullptr;
     hipGraphExec_t ins_exec = nullptr;
     Dev ins_graph_dev{};
@@ -4047,6 +4052,22 @@ void build_tables(plds *h, int32_t lpg) {
     }
 }
 
+// Destroys the prebuilt step graphs; the next sweep rebuilds them.
+void drop_graphs(plds *h) {
+    if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
+    if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
+    h->ins_exec = nullptr;
+    h->ins_graph = nullptr;
+    if (h->del_exec) (void)hipGraphExecDestroy(h->del_exec);
+    if (h->del_graph) (void)hipGraphDestroy(h->del_graph);
+    h->del_exec = nullptr;
+    h->del_graph = nullptr;
+    if (h->jmp_exec) (void)hipGraphExecDestroy(h->jmp_exec);
+    if (h->jmp_graph) (void)hipGraphDestroy(h->jmp_graph);
+    h->jmp_exec = nullptr;
+    h->jmp_graph = nullptr;
+}
+
 void free_all(plds *h) {
     Dev &d = h->d;
     dfree(d.up_max), dfree(d.dn_min), dfree(d.pow_tab);
@@ -4066,18 +4087,7 @@ void free_all(plds *h) {
     dfree(d.prevlvl), dfree(d.lvp), dfree(h->t_ins), dfree(h->t_del);
     dfree(h->sk_C), dfree(h->sk_B), dfree(h->sk_r), dfree(h->sk_cnt), dfree(h->sk_pw);
     dfree(h->vd_buf);
-    if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
-    if (h->ins_graph) (void)hipGraphDestroy(h->ins_graph);
-    h->ins_exec = nullptr;
-    h->ins_graph = nullptr;
-    if (h->del_exec) (void)hipGraphExecDestroy(h->del_exec);
-    if (h->del_graph) (void)hipGraphDestroy(h->del_graph);
-    h->del_exec = nullptr;
-    h->del_graph = nullptr;
-    if (h->jmp_exec) (void)hipGraphExecDestroy(h->jmp_exec);
-    if (h->jmp_graph) (void)hipGraphDestroy(h->jmp_graph);
-    h->jmp_exec = nullptr;
-    h->jmp_graph = nullptr;
+    drop_graphs(h);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     h->ev.clear();
@@ -4350,9 +4360,7 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
     return PLDS_OK;
 }
 
-constexpr int kGraphSteps = 16;
-
-// The insertion step sequence (prep, scan) x kGraphSteps as one graph of
+// The insertion step sequence (prep, scan) x graph_steps as one graph of
 // kernel nodes, rebuilt when the device buffers move.
 int ins_graph(plds *h) {
     if (h->ins_exec && !memcmp(&h->ins_graph_dev, &h->d, sizeof(Dev))) return 0;
@@ -4370,7 +4378,7 @@ int ins_graph(plds *h) {
         int grid;
     } ks[2] = {{(const void *)k_ins_prep, kListGrid}, {(const void *)k_ins_scan, h->scan_grid}};
     hipGraphNode_t prev = nullptr;
-    for (int i = 0; i < kGraphSteps; i++) {
+    for (int i = 0; i < h->graph_steps; i++) {
         for (int k = 0; k < 2; k++) {
             hipGraphNode_t node;
             hipKernelNodeParams p{};
@@ -4418,9 +4426,9 @@ int del_graph(plds *h) {
         unsigned lds;
         void **args;
     } ks[7] = {{(const void *)k_del_select, kSweepGrid / 4, kBlock, 0, a0},
-               {(const void *)k_del_scan, kSweepGrid, kBlock, 0, a0},
+               {(const void *)k_del_scan, h->del_scan_grid, kBlock, 0, a0},
                {(const void *)k_del_fin, kSweepGrid / 4, kBlock, 0, a0},
-               {(const void *)k_dl, kDlGrid, kBlock, 0, a1},
+               {(const void *)k_dl, h->dl_grid, kBlock, 0, a1},
                {(const void *)k_dl_big, kBigGrid, kBigBlock, blds, ab},
                {(const void *)k_del_next, 1, 1, 0, a1},
                {(const void *)k_del_loop, 1, kLoopBlock, 0, a0}};
@@ -4525,13 +4533,13 @@ int insertion_sweep(plds *h, hipStream_t s) {
     // took (even, so that every run starts at parity 0), then runs of 16,
     // 32, ... (a step launched after the sweep's end still costs its launches
     // on the host)
-    int run = use_graph ? kGraphSteps
+    int run = use_graph ? h->graph_steps
                         : (int)std::min<int64_t>(std::max<int64_t>((h->ins_steps_hint * 7 / 8) & ~1LL, 8), 256);
     int next_run = 16;
     // before the first wait, issue about as many steps as the last sweep
     // took (rounded down to whole step graphs); steps issued after the
     // sweep's end return at once
-    int64_t first = std::min<int64_t>(std::max<int64_t>(h->ins_steps_hint / kGraphSteps, 1), 8);
+    int64_t first = std::min<int64_t>(std::max<int64_t>(h->ins_steps_hint / h->graph_steps, 1), 8);
     while (!h->h_ctl->done && !h->h_ctl->err) {
         if (steps > 2 * (int64_t)h->K + 2) {   // a level gets at most an exit step and a moving step
             h->broken = true;
@@ -4541,7 +4549,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
             rc = ins_graph(h);
             if (rc) return rc;
             for (int64_t i = 0; i < first; i++) HIPCHK(hipGraphLaunch(h->ins_exec, s));
-            steps += first * kGraphSteps;
+            steps += first * h->graph_steps;
             first = 1;
         } else {
             steps += run;
@@ -4601,9 +4609,9 @@ int jmp_graph(plds *h) {
         unsigned lds;
         void **args;
     } ks[6] = {{(const void *)k_jmp_select, kSweepGrid / 4, kBlock, 0, a0},
-               {(const void *)k_jmp_dl, kDlGrid, kBlock, 0, a0},
+               {(const void *)k_jmp_dl, h->dl_grid, kBlock, 0, a0},
                {(const void *)k_jmp_dl_big, kJmpBigGrid, kBigBlock, blds, ab},
-               {(const void *)k_jmp_scan, kSweepGrid, kBlock, 0, a0},
+               {(const void *)k_jmp_scan, h->del_scan_grid, kBlock, 0, a0},
                {(const void *)k_jmp_fin, kSweepGrid / 4, kBlock, 0, a0},
                {(const void *)k_jmp_next, 1, 1, 0, a1}};
     hipGraphNode_t prev = nullptr;
@@ -4655,10 +4663,10 @@ int jump_sweep(plds *h, hipStream_t s) {
         } else {
             for (int64_t i = 0; i < first * kJmpGraphSteps; i++) {
                 hipLaunchKernelGGL(k_jmp_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-                hipLaunchKernelGGL(k_jmp_dl, dim3(kDlGrid), dim3(kBlock), 0, s, d);
+                hipLaunchKernelGGL(k_jmp_dl, dim3(h->dl_grid), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_jmp_dl_big, dim3(kJmpBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t),
                                    s, d, nbins);
-                tlaunch(h, 10, k_jmp_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
+                tlaunch(h, 10, k_jmp_scan, dim3(h->del_scan_grid), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_jmp_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_jmp_next, dim3(1), dim3(1), 0, s, d, 1);
             }
@@ -4686,7 +4694,7 @@ int deletion_sweep(plds *h, hipStream_t s) {
     d.loop_slots = h->sweep_mode == 2 ? 0 : kLoopSlots;
     hipLaunchKernelGGL(k_del_cand, dim3(grid_for(h->h_ctl->n_touch, kBlock, kApplyGrid)), dim3(kBlock), 0, s, d);
     const int32_t nbins = dl_bins(h);
-    tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), 0, s, d, 0);
+    tlaunch(h, 3, k_dl, dim3(h->dl_grid), dim3(kBlock), 0, s, d, 0);
     hipLaunchKernelGGL(k_dl_big, dim3(kBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t), s, d, 0, nbins);
     hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 0);
     // the level loop in one block; it stops at a step too large for it
@@ -4720,9 +4728,9 @@ int deletion_sweep(plds *h, hipStream_t s) {
             steps += run;
             for (int i = 0; i < run; i++) {
                 hipLaunchKernelGGL(k_del_select, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-                tlaunch(h, 2, k_del_scan, dim3(kSweepGrid), dim3(kBlock), 0, s, d);
+                tlaunch(h, 2, k_del_scan, dim3(h->del_scan_grid), dim3(kBlock), 0, s, d);
                 hipLaunchKernelGGL(k_del_fin, dim3(kSweepGrid / 4), dim3(kBlock), 0, s, d);
-                tlaunch(h, 3, k_dl, dim3(kDlGrid), dim3(kBlock), 0, s, d, 1);
+                tlaunch(h, 3, k_dl, dim3(h->dl_grid), dim3(kBlock), 0, s, d, 1);
                 hipLaunchKernelGGL(k_dl_big, dim3(kBigGrid), dim3(kBigBlock), (size_t)nbins * sizeof(int32_t), s, d, 1,
                                    nbins);
                 hipLaunchKernelGGL(k_del_next, dim3(1), dim3(1), 0, s, d, 1);
@@ -4870,6 +4878,7 @@ int create_impl(int32_t ngraphs, const int64_t *ns, double delta, double lambda,
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
             per > 0 && ncu > 0)
             h->scan_grid = std::max(256, std::min(std::min(per, kScanPerCU) * ncu, kSweepGrid));
+        h->scan_grid_def = h->scan_grid;
     }
     build_tables(h, levels_per_group);
     for (auto &t : h->gt) h->gcapG.push_back(t.G);
@@ -5461,6 +5470,10 @@ int plds_rebuild(plds_t *h, int64_t new_n, const int32_t *relabel, plds_t **out,
     if (!rc) rc = create_impl(1, &new_n, h->delta, h->lambda, h->lpg, 2 * m, h->up_coeff, h->up_jump, &nh);
     if (!rc) {
         nh->sweep_mode = h->sweep_mode;
+        nh->scan_grid = h->scan_grid;
+        nh->graph_steps = h->graph_steps;
+        nh->dl_grid = h->dl_grid;
+        nh->del_scan_grid = h->del_scan_grid;
         if (m) rc = plds_update(nh, e, m, nullptr, 0, stream);   // Algorithm 2 on every edge
     }
     dfree(e);
@@ -5518,6 +5531,33 @@ int plds_thresholds(const plds_t *h, int32_t *up_max, int32_t *dn_min, double *p
 int plds_set_sweep_mode(plds_t *h, int32_t mode) {
     if (!h || mode < 0 || mode > 4) return PLDS_EINVAL;
     h->sweep_mode = mode;
+    return PLDS_OK;
+}
+
+int plds_set_launch(plds_t *h, const plds_launch_t *cfg) {
+    if (!h || !cfg) return PLDS_EINVAL;
+    for (int k = 0; k < 4; k++)
+        if (cfg->reserved[k]) return PLDS_EINVAL;
+    auto in = [](int32_t v, int32_t lo, int32_t hi) { return v == 0 || (v >= lo && v <= hi); };
+    if (!in(cfg->scan_blocks, 64, kSweepGrid) || !in(cfg->graph_steps, 2, 64) || (cfg->graph_steps & 1) ||
+        !in(cfg->dl_blocks, 64, 4096) || !in(cfg->del_scan_blocks, 64, 8192))
+        return PLDS_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
+    h->scan_grid = cfg->scan_blocks ? cfg->scan_blocks : h->scan_grid_def;
+    h->graph_steps = cfg->graph_steps ? cfg->graph_steps : kGraphStepsDef;
+    h->dl_grid = cfg->dl_blocks ? cfg->dl_blocks : kDlGrid;
+    h->del_scan_grid = cfg->del_scan_blocks ? cfg->del_scan_blocks : kSweepGrid;
+    drop_graphs(h);   // the step graphs carry the grids
+    return PLDS_OK;
+}
+
+int plds_get_launch(const plds_t *h, plds_launch_t *out) {
+    if (!h || !out) return PLDS_EINVAL;
+    *out = plds_launch_t{};
+    out->scan_blocks = h->scan_grid;
+    out->graph_steps = h->graph_steps;
+    out->dl_blocks = h->dl_grid;
+    out->del_scan_blocks = h->del_scan_grid;
     return PLDS_OK;
 }
 

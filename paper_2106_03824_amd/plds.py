@@ -32,6 +32,14 @@ class plds_options_t(ctypes.Structure):
                 ("reserved", ctypes.c_int64 * 4)]
 
 
+class plds_launch_t(ctypes.Structure):
+    _fields_ = [("scan_blocks", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("dl_blocks", ctypes.c_int32),
+                ("del_scan_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+LAUNCH_FIELDS = ("scan_blocks", "graph_steps", "dl_blocks", "del_scan_blocks")
+
+
 class plds_info_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("t", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("G", ctypes.c_int32), ("K", ctypes.c_int32), ("delta", ctypes.c_double),
@@ -87,6 +95,8 @@ def lib():
         L.plds_set_timing.argtypes = [_VP, ctypes.c_int32]
         L.plds_step_log.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64)]
         L.plds_set_sweep_mode.argtypes = [_VP, ctypes.c_int32]
+        L.plds_set_launch.argtypes = [_VP, ctypes.POINTER(plds_launch_t)]
+        L.plds_get_launch.argtypes = [_VP, ctypes.POINTER(plds_launch_t)]
         L.plds_dump_state.argtypes = [_VP, _VP, _I64, ctypes.POINTER(_I64), _VP, _VP]
         L.plds_load_state.argtypes = [_VP, _VP, _I64, _VP, _VP]
         L.plds_check.argtypes = [_VP, _VP]
@@ -115,7 +125,7 @@ EXPORTS = ("plds_create", "plds_create_ex", "plds_destroy", "plds_create_multi",
            "plds_orient", "plds_track_orientation", "plds_flips", "plds_oriented_updates", "plds_densest_value",
            "plds_static_kcore", "plds_static_kcore_noalloc", "plds_delete_vertices", "plds_rebuild",
            "plds_inject_alloc_failure", "plds_create_opts", "plds_reset_graph",
-           "plds_graph_applied")
+           "plds_graph_applied", "plds_set_launch", "plds_get_launch")
 
 
 def strerror(code):
@@ -351,6 +361,21 @@ def plds_stats(h):
 
 def plds_set_sweep_mode(h, mode):
     return _chk(lib().plds_set_sweep_mode(h, int(mode)), "plds_set_sweep_mode")
+
+
+def plds_set_launch(h, **fields):
+    """Sets the launch schedule; fields not given (or 0) take their defaults."""
+    bad = set(fields) - set(LAUNCH_FIELDS)
+    if bad:
+        raise TypeError(f"unknown launch fields {sorted(bad)}")
+    c = plds_launch_t(**{k: int(v) for k, v in fields.items()})
+    return _chk(lib().plds_set_launch(h, ctypes.byref(c)), "plds_set_launch")
+
+
+def plds_get_launch(h):
+    c = plds_launch_t()
+    _chk(lib().plds_get_launch(h, ctypes.byref(c)), "plds_get_launch")
+    return {f: getattr(c, f) for f in LAUNCH_FIELDS}
 
 
 def plds_set_timing(h, kernel):
