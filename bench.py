@@ -280,7 +280,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", action="store_true", help="the batched form: 256 graphs in one handle")
     ap.add_argument("--graphs", type=int, default=256)
-    ap.add_argument("--tune-reps", type=int, default=3, help="timed runs per schedule of the batched search")
+    ap.add_argument("--tune-reps", type=int, default=3,
+                    help="timed runs per schedule of the batched search (0: no search, default schedule)")
     ap.add_argument("--tune-record", default=None, help="where the batched form writes its schedule search (JSON)")
     ap.add_argument("--serve", action="store_true", help="the serving form: resident graphs behind a request loop")
     ap.add_argument("--opt", action="store_true",
@@ -422,7 +423,7 @@ def run_rmat20(args, P, W, torch, np, steps, warmup):
                 per_kind[kind][1] += dt
                 lat.append(dt)
                 tot["updates"] += u
-                tot["alg_bytes"] += s["alg_bytes_up"]
+                tot["alg_bytes"] += kernel_bytes(kernel, s)
                 tot["timed_ms"] += s["timed_ms"]
                 tot["launches"] += s["timed_launches"]
                 tot["sweeps"] += s["sweeps_ins"] + s["sweeps_del"]
@@ -601,7 +602,7 @@ def run_rmat24(args, P, W, torch, np):
     per_kind = {"ins": [0, 0.0], "del": [0, 0.0], "mix": [0, 0.0]}
     lat = []
     tot = {"updates": 0, "alg_bytes": 0, "timed_ms": 0.0, "launches": 0, "sweeps": 0, "moves": 0, "syncs": 0,
-           "calls": 0}
+           "calls": 0, "ins_steps": 0, "ins_loop_steps": 0, "ins_loop_launches": 0}
     t0 = None
     for r in range(R):
         timed = r >= args.warmup
@@ -620,13 +621,15 @@ def run_rmat24(args, P, W, torch, np):
                 per_kind[kind][1] += dt
                 lat.append(dt)
                 tot["updates"] += u
-                tot["alg_bytes"] += s["alg_bytes_up"]
+                tot["alg_bytes"] += kernel_bytes(args.kernel, s)
                 tot["timed_ms"] += s["timed_ms"]
                 tot["launches"] += s["timed_launches"]
                 tot["sweeps"] += s["sweeps_ins"] + s["sweeps_del"]
                 tot["moves"] += s["moves_up"] + s["moves_down"]
                 tot["syncs"] += s["host_syncs"]
                 tot["calls"] += 1
+                for f in ("ins_steps", "ins_loop_steps", "ins_loop_launches"):
+                    tot[f] += s[f]
                 log(f"round {r} {kind}: {u} updates in {dt * 1e3:.2f} ms, sweeps {s['sweeps_ins'] + s['sweeps_del']}, "
                     f"host syncs {s['host_syncs']}")
     torch.cuda.synchronize()
@@ -656,6 +659,9 @@ def run_rmat24(args, P, W, torch, np):
                              "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
         "sweeps_per_step": tot["sweeps"] / args.steps, "moves_per_step": tot["moves"] / args.steps,
         "host_syncs_per_call": tot["syncs"] / max(tot["calls"], 1),
+        "insertion_steps_per_step": {"all": tot["ins_steps"] / args.steps,
+                                     "single_block_loop": tot["ins_loop_steps"] / args.steps,
+                                     "loop_launches": tot["ins_loop_launches"] / args.steps},
         "build": {"edges": build_updates, "seconds": round(t_build, 3), "updates_per_s": build_updates / t_build,
                   "batches": len(build_sweeps), "sweeps_per_batch": float(np.mean(build_sweeps)),
                   "parity_vs_oracle_trace": parity},
@@ -669,6 +675,17 @@ def run_rmat24(args, P, W, torch, np):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_rmat24(perm, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def kernel_bytes(kernel, s):
+    """Algorithmic bytes of one call moved by the timed kernel: the insertion
+    scan kernel and the single-block loop of small insertion steps split the
+    up-moves' bytes between them."""
+    if kernel == "ins_scan":
+        return s["alg_bytes_up"] - s["alg_bytes_up_loop"]
+    if kernel == "ins_loop":
+        return s["alg_bytes_up_loop"]
+    return s["alg_bytes_up"]
 
 
 def roofline(tot, kernel):
@@ -720,7 +737,7 @@ def run_stream(args, P, W, torch, np):
         per_kind[kind][1] += dt
         lat.append(dt)
         tot["updates"] += u
-        tot["alg_bytes"] += s["alg_bytes_up"]
+        tot["alg_bytes"] += kernel_bytes(args.kernel, s)
         tot["timed_ms"] += s["timed_ms"]
         tot["launches"] += s["timed_launches"]
         sweeps.append(s["sweeps_ins"] + s["sweeps_del"])
@@ -811,10 +828,13 @@ def run_batched(args, P, W, torch, np):
     torch.cuda.synchronize()
     log("built")
     # the schedule search, on the tuning batches
-    best, rec = AT.tune(mg, lambda: P.plds_update_multi(mg.h, tin_l, tdel_l), torch, reps=args.tune_reps,
-                        log=log, path=args.tune_record, workload=f"batched-{k}-graphs tuning batches")
-    log(f"tuned schedule {best}: {rec['best']['ms']:.2f} ms vs default {rec['default']['ms']:.2f} ms "
-        f"({len(rec['trials'])} schedules timed)")
+    if args.tune_reps > 0:
+        best, rec = AT.tune(mg, lambda: P.plds_update_multi(mg.h, tin_l, tdel_l), torch, reps=args.tune_reps,
+                            log=log, path=args.tune_record, workload=f"batched-{k}-graphs tuning batches")
+        log(f"tuned schedule {best}: {rec['best']['ms']:.2f} ms vs default {rec['default']['ms']:.2f} ms "
+            f"({len(rec['trials'])} schedules timed)")
+    else:
+        best, rec = {}, {"trials": []}
     reps = max(args.steps, 1)
     e0, l0 = mg.dump()
     s_state = [sg.dump() for sg in singles]
@@ -872,6 +892,8 @@ def run_batched(args, P, W, torch, np):
         "schedule": best, "schedules_timed": len(rec["trials"]),
         "speedup_vs_loop": t_loop / t_fused,
         "identical_levels": same, "updates": u_fused, "level_steps": s["sweeps_ins"] + s["sweeps_del"],
+        "insertion_steps": {"all": s["ins_steps"], "single_block_loop": s["ins_loop_steps"],
+                            "loop_launches": s["ins_loop_launches"]},
         "level_steps_alone": {"max": max(loop_steps), "sum": sum(loop_steps)},
     }
     print(json.dumps(out), flush=True)

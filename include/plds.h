@@ -77,6 +77,12 @@ typedef struct {
                               over plds_static_kcore calls: 8 per adjacency slot (id and
                               bucket; 2m per call), 8 per count update of an alive
                               neighbour of a peeled vertex                              */
+    int64_t alg_bytes_up_loop; /* the part of alg_bytes_up moved by the single-block loop of
+                              small insertion steps (the rest by the insertion scan
+                              kernel)                                                   */
+    int64_t ins_steps;     /* level steps of the insertion sweeps (a multi-level step counts once) */
+    int64_t ins_loop_steps;/* of those, the steps run by the single-block loop           */
+    int64_t ins_loop_launches; /* launches of that loop that found a sweep running       */
 } plds_stats_t;
 
 /* Create an empty structure on the current HIP device: all n vertices at
@@ -330,7 +336,10 @@ int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
  * and only the vertices it leaves behind and the residents of the next two
  * levels scan their slabs); 2 = one kernel per part, every step scanning its
  * movers' slabs; 3 = as 1, with climbing steps for groups of any size (not
- * only large ones), which exercises them on small graphs.  Deletions: the
+ * only large ones), which exercises them on small graphs.  In modes 1 and 3
+ * the insertion steps with at most 2^11 movers and 2^13 slab slots of
+ * movers run back to back in one single-block kernel, larger ones (and
+ * climbing steps) by the per-part kernels.  Deletions: the
  * steps run in one single-block kernel, a step with more than 2^11 pending
  * vertices or 2^12 slab slots of movers by the grid kernels; in mode 2 every
  * step (with any slab slots) goes to the grid kernels.  Results are
@@ -383,7 +392,9 @@ int plds_inject_alloc_failure(int64_t after);
  * preparation, 5 = the edge scan of plds_flips, 6 = the cooperative
  * insertion sweep, 7 = the relax kernel of plds_static_kcore, 8 = the
  * application of a deletion list, 9 = the single-block deletion loop,
- * 10 = the edge scan of a round of jumps of a handle made with up_jump).  Each launch of that kernel carries a HIP event pair that the
+ * 10 = the edge scan of a round of jumps of a handle made with up_jump,
+ * 11 = the single-block loop of small insertion steps).  Each launch of
+ * that kernel carries a HIP event pair that the
  * runtime stamps at the dispatch's own start and end (hipExtLaunchKernel);
  * the cooperative sweep has events recorded around it on the stream.
  * While kind 1 or 4 is timed, insertion steps are launched one by one

@@ -47,6 +47,8 @@ constexpr int kSweepGrid = 2048;     // blocks of the sweep kernels (most blocks
 constexpr int kScanPerCU = 5;
 constexpr int kDlGrid = 1024;        // blocks of the desire-level kernel
 constexpr int kGraphStepsDef = 16;   // insertion steps per prebuilt step graph (default)
+constexpr int32_t kInsLoopMovers = 2048;   // most movers of an insertion step run by the single-block loop
+constexpr int32_t kInsLoopSlots = 8192;    // most slab slots of its movers
 constexpr int kListGrid = 256;       // blocks of the per-mover list kernels
 constexpr int kApplyGrid = 1024;     // most blocks of the batch-application kernels
 constexpr int32_t kInf = INT32_MAX;
@@ -140,6 +142,13 @@ struct Ctl {
     int64_t pool_top;     // next free pool slot
     int64_t sweeps, moves, scanned, dl_calcs, top, m_out;
     int64_t alg_U, alg_up1;   // up-neighbours read, neighbours one level up (insertion scans)
+    // the single-block insertion loop (k_ins_loop)
+    int32_t ins_p;        // parity of the next insertion step (of the step left to the step kernels when ins_big)
+    int32_t ins_big;      // that step is run by the step kernels (k_ins_prep, k_ins_scan)
+    int32_t ins_trips;    // launches of the loop that found the sweep running
+    int64_t lp_scanned, lp_U, lp_up1, lp_moves;   // the loop's share of the scan statistics and moves
+    int32_t lp_steps;     // steps run by the loop
+    int32_t n_small;      // pull steps of the step kernels with at most kInsLoopMovers movers
 };
 
 // Everything a kernel needs, passed by value.
@@ -188,6 +197,7 @@ struct Dev {
     int32_t *rc;                      // [n]
     // climbing steps
     int32_t climb_ok;                 // climbing steps allowed (plain handle, per-part kernels)
+    int32_t ins_loop;                 // small insertion steps run by the single-block loop (per-part kernels)
     int32_t climb_min;                // smallest group that enters a climbing step
     int32_t loop_slots;               // most slab slots of a deletion step run by the single-block loop
     int32_t *lvb_start;               // [K+2] vertices with edges, bucketed by level at the sweep start
@@ -213,6 +223,20 @@ __device__ __forceinline__ GP gp(const Dev &d, int32_t v) {
 }
 // Invariant 1 cap and Invariant 2 floor of a vertex of graph p at level lvl
 __device__ __forceinline__ int32_t up_cap(const Dev &d, GP p, int32_t lvl) { return d.up_max[p.tab + lvl / p.L]; }
+// Whether level x is the first level of a group in some graph of the handle.
+__device__ __forceinline__ bool group_start(const Dev &d, int32_t x) {
+    if (d.ng == 1) return x % d.L == 0;
+    for (int i = 0; i < d.nLs; i++)
+        if (x % d.Ls[i] == 0) return true;
+    return false;
+}
+// The first level above x that starts a group in some graph of the handle.
+__device__ __forceinline__ int32_t next_group_start(const Dev &d, int32_t x) {
+    if (d.ng == 1) return (x / d.L + 1) * d.L;
+    int32_t b = INT32_MAX;
+    for (int i = 0; i < d.nLs; i++) b = min(b, (x / d.Ls[i] + 1) * d.Ls[i]);
+    return b;
+}
 __device__ __forceinline__ int32_t dn_floor(const Dev &d, GP p, int32_t lvl) {
     return d.dn_min[p.tab + (lvl - 1) / p.L];
 }
@@ -938,6 +962,12 @@ __global__ void k_level_scan(Dev d) {
         d.ctl->n_chunks = 0;
         d.ctl->n_cls[0] = d.ctl->n_cls[1] = d.ctl->n_cls[2] = d.ctl->n_cls[3] = 0;
         d.ctl->blocks_done = 0;
+        d.ctl->ins_p = 0;
+        d.ctl->ins_big = 0;
+        d.ctl->ins_trips = 0;
+        d.ctl->lp_scanned = d.ctl->lp_U = d.ctl->lp_up1 = d.ctl->lp_moves = 0;
+        d.ctl->lp_steps = 0;
+        d.ctl->n_small = 0;
     }
 }
 
@@ -1351,7 +1381,7 @@ __device__ InsStep climb_decide(Dev &d, const InsStep &prv, int p, int32_t *sh1,
     nx.cur = prv.cur ^ 1;
     nx.phys = nx.l = x1;
     if (stay == 0 && r1 == 0) {
-        int32_t b = min((x1 / d.L + 1) * d.L, d.K);   // first level of the next group
+        int32_t b = min(next_group_start(d, x1), d.K);   // first level of the next group (of any graph)
         if (threadIdx.x == 0) sh1[0] = b;
         __syncthreads();
         for (int32_t z = x1 + 2 + threadIdx.x; z < b; z += blockDim.x)
@@ -1388,9 +1418,14 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
     const int32_t nj = c->casc_n[st.cur];
     const int32_t a0 = d.lvl_start[x], ns = d.lvl_start[x + 1] - a0;
     // Landing on the first level of a group raises the cap: the members
-    // whose up is within the new cap stop there without any decrement.
-    const bool boundary = l == x && (x + 1) % d.L == 0;
-    const int32_t cap_new = boundary ? up_cap(d, gp(d, 0), x + 1) : 0;
+    // whose up is within the new cap stop there without any decrement (in
+    // a multi-graph handle, the members of the graphs whose group starts there).
+    const bool boundary = l == x && group_start(d, x + 1);
+    // the new cap for member v, or -1 if x+1 does not start a group of its graph
+    auto cap_new = [&](int32_t v) -> int32_t {
+        const GP g = gp(d, v);
+        return (x + 1) % g.L == 0 ? up_cap(d, g, x + 1) : -1;
+    };
     int32_t *sln = p ? d.sl1 : d.sl0;
     const int32_t ncl0 = boundary ? c->n_cl_snap : 0;   // members of earlier steps
     int64_t dsum = 0;
@@ -1409,7 +1444,7 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
         } else if (i < nsl + nj + ns) {
             v = i < nsl + nj ? casc[i - nsl] : d.sorted[a0 + i - nsl - nj];
             int32_t uv = d.up[v];
-            bool st_now = boundary && uv <= cap_new;
+            bool st_now = boundary && uv <= cap_new(v);
             d.level[v] = x | kClimb | (st_now ? kStop : 0);
             dsum += uv;
             if (st_now) stopn = v;
@@ -1418,7 +1453,7 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
             int32_t raw = d.level[u];
             // stopped members of the previous step are being fixed right
             // now: they read as kStop or as a plain level, both skipped
-            if ((raw & kClimb) && !(raw & kStop) && d.up[u] <= cap_new) {
+            if ((raw & kClimb) && !(raw & kStop) && d.up[u] <= cap_new(u)) {
                 d.level[u] = raw | kStop;
                 stopn = u;
             }
@@ -1434,7 +1469,6 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
     dsum = block_sum64(dsum, red);
     if (threadIdx.x == 0 && dsum) atomicAdd((unsigned long long *)&c->sum_up, (unsigned long long)dsum);
     // work items
-    const int32_t cap_x = up_cap(d, gp(d, 0), x);
     const int32_t *bk = d.lvb;
     int32_t s0 = 0, s1 = 0, r1a = 0, r1b = 0, r2a = 0, r2b = 0;
     if (l == x) {
@@ -1455,7 +1489,7 @@ __device__ void climb_prep_phase(Dev &d, const InsStep &prv, const InsStep &st, 
             int32_t raw = d.level[u];
             // a resident of x that stays (not climbing, within the cap); joiners
             // being flagged right now are over the cap
-            if (!(raw & kClimb) && (raw & kLevelMask) == x && d.up[u] <= cap_x) v = u;
+            if (!(raw & kClimb) && (raw & kLevelMask) == x && d.up[u] <= up_cap(d, gp(d, u), x)) v = u;
             role = kRoleStay;
         } else if (i < nst + nss) {
             v = slp[i - nst];
@@ -1527,7 +1561,7 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
     int32_t *join = (st.cur ^ 1) ? d.casc1 : d.casc0;
     int32_t *slist = p ? d.sl1 : d.sl0;
     auto wr_stop = [=](int32_t k, int32_t x) { slist[k] = x; };
-    const int32_t cap1 = up_cap(d, gp(d, 0), l + 1);   // the cap of level l+1 (one graph)
+    const int32_t cap1_all = d.ng == 1 ? up_cap(d, gp(d, 0), l + 1) : 0;   // the cap of level l+1 (one graph)
     const int lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
     const int nw = nblk * wpb;
     const int32_t total = (int32_t)min((int64_t)c->n_cw[p], d.cw_cap);
@@ -1552,7 +1586,7 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
         bool stop = false;
         if (climb && role == kRoleStay && clim) {
             int32_t old = atomicSub(&d.up[w], 1);
-            stop = old == cap1 + 1;
+            stop = old == (d.ng == 1 ? cap1_all : up_cap(d, gp(d, w), l + 1)) + 1;
             if (stop) d.level[w] = raw | kStop;   // the only write to w's level in this step
             dec++;
         }
@@ -1564,6 +1598,7 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
             scanned += hi - lo;
             if (role == kRoleUp1) {
                 if (cnt) {
+                    const int32_t cap1 = d.ng == 1 ? cap1_all : up_cap(d, gp(d, v), l + 1);
                     int32_t old = atomicAdd(&d.up[v], cnt);
                     jn = old <= cap1 && old + cnt > cap1;
                     m1 += cnt;
@@ -1733,9 +1768,9 @@ __global__ void k_ins_totals(Dev d, int nparts) {
     int64_t sums[3];
     sum_parts(d, nparts, sums);
     if (threadIdx.x == 0) {
-        d.ctl->scanned = sums[0];
-        d.ctl->alg_U = sums[1];
-        d.ctl->alg_up1 = sums[2];
+        d.ctl->scanned = sums[0] + d.ctl->lp_scanned;
+        d.ctl->alg_U = sums[1] + d.ctl->lp_U;
+        d.ctl->alg_up1 = sums[2] + d.ctl->lp_up1;
     }
 }
 
@@ -1763,6 +1798,10 @@ __global__ void k_ins_prep(Dev d, int p) {
     __shared__ int32_t sh[5 * (kBlock / kWave + 2)];
     __shared__ int32_t sh1[2];
     Ctl *c = d.ctl;
+    if (d.ins_loop) {   // only the steps the single-block loop leaves, with their own parity
+        if (!c->ins_big) return;
+        p = c->ins_p;
+    }
     // the bookkeeping is done by block 1, which starts as early as block 0
     // but has movers to gather only in large steps, so that its reads do not
     // delay the gathering of small steps
@@ -1796,7 +1835,7 @@ __global__ void k_ins_prep(Dev d, int p) {
     // (not right after an exit step: the members that stopped in its last
     // climbing step are residents of its level that no list holds)
     if (prv.mode == kPull && d.climb_ok && !cur.done && !cur.jump && cur.l == cur.phys &&
-        (cur.l + 1) % d.L != 0 && cur.l + 2 <= d.K && movers >= d.climb_min) {
+        !group_start(d, cur.l + 1) && cur.l + 2 <= d.K && movers >= d.climb_min) {
         // enter a climbing step if the level's other vertices and the two
         // levels above hold few vertices next to the movers
         int32_t work = occz - movers + d.occ[cur.l + 1] + d.occ[cur.l + 2];
@@ -1821,6 +1860,7 @@ __global__ void k_ins_prep(Dev d, int p) {
         c->n_cls2[p ^ 1][0] = c->n_cls2[p ^ 1][1] = c->n_cls2[p ^ 1][2] = c->n_cls2[p ^ 1][3] = 0;
         c->n_cw[p ^ 1] = 0;
         c->step_dec[p] = 0;
+        if (cur.mode == kPull && !cur.done && movers <= kInsLoopMovers) c->n_small++;
         if (cur.mode != kPull) {
             c->nmvb[p] = 0;
             c->nmove[p] = nmove;
@@ -1833,6 +1873,10 @@ __global__ void k_ins_prep(Dev d, int p) {
 
 __global__ void k_ins_scan(Dev d, int p) {
     Ctl *c = d.ctl;
+    if (d.ins_loop) {
+        if (!c->ins_big) return;
+        p = c->ins_p;
+    }
     // bookkeeping: atomics whose result is not waited for, so block 0 goes
     // on with its work items at once
     const bool keeper = blockIdx.x == 0 && threadIdx.x == 0;
@@ -2720,6 +2764,286 @@ __global__ void __launch_bounds__(kLoopBlock) k_del_loop(Dev d) {
             s_cur = cur ^ 1;
             s_np = s_nq;
             s_stop = c->done || (ld_dev(&c->err) & kErrOrder);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- small insertion steps in one block.  Most steps of an insertion sweep
+// move a handful of vertices with small slabs; as two grid-wide kernels
+// (k_ins_prep, k_ins_scan) such a step costs mostly launch gaps and the
+// latency of its dependent memory accesses.  k_ins_loop runs such steps back
+// to back in one workgroup.  Each step is decided, prepared and scanned as
+// those two kernels do it, with the same lists, flags, counters and
+// bookkeeping (the movers' slabs are cut into slots spread over the block's
+// threads), so that either side can take over after any step.  The loop
+// stops before a step with more than kInsLoopMovers movers or kInsLoopSlots
+// slab slots, a climbing or exit step (or the step after one), or when the
+// sweep is done.  A step it leaves is run by the step kernels launched after
+// it (they return at once otherwise): ins_big is set and ins_p holds the
+// step's parity; the next launch of the loop takes over after that step.
+// The previous step's occupancy change is applied after the next step is
+// decided, where the step kernels apply it, so a hand-over in either
+// direction sees the state the step kernels would leave.
+constexpr int kInsLoopR = kInsLoopSlots / kLoopBlock;   // slab slots per thread
+
+// Index i of the last prefix entry pre[i] <= j (pre[0] = 0, ascending; n entries).
+__device__ __forceinline__ int32_t prefix_owner(const int32_t *pre, int32_t n, int32_t j) {
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kLoopBlock) k_ins_loop(Dev d) {
+    __shared__ int32_t sh1[2];
+    __shared__ int32_t red[kLoopBlock / kWave + 2];
+    __shared__ int32_t s_pre[kInsLoopMovers + 1];   // exclusive prefix sums of the movers' slab sizes
+    __shared__ int32_t s_mv[kInsLoopMovers];
+    __shared__ int64_t s_off[kInsLoopMovers];
+    __shared__ int32_t s_stay[kInsLoopMovers];
+    __shared__ int32_t s_p, s_stop, s_nc, s_nsl, s_slbase;
+    Ctl *c = d.ctl;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int32_t p = c->ins_p;
+        if (c->ins_big) {   // the step kernels ran the step this loop left them
+            c->ins_big = 0;
+            p ^= 1;
+            c->ins_p = p;
+        }
+        s_p = p;
+        s_stop = c->done || ld_dev(&c->err) != 0;
+        if (!s_stop) c->ins_trips++;
+    }
+    __syncthreads();
+    while (!s_stop) {   // block-uniform
+        const int p = s_p;
+        const int32_t Mp = p ? kMover1 : kMover0, Mn = p ? kMover0 : kMover1;
+        const InsStep prv = c->st[p ^ 1];
+        bool hand = !prv.fresh && prv.mode != kPull;
+        InsStep cur = prv;
+        int32_t movers = 0, occz = 0, a0 = 0, nA = 0, nB = 0;
+        if (!hand) {
+            if (prv.fresh) {
+                cur.fresh = 0;
+                if (!cur.done) {
+                    a0 = d.lvl_start[cur.phys];
+                    movers = d.lvl_start[cur.phys + 1] - a0;
+                    occz = d.occ[cur.phys];
+                }
+                nA = movers;
+                nB = c->casc_n[cur.cur];
+            } else {
+                const int32_t cn = c->casc_n[prv.cur ^ 1];
+                cur = ins_decide(d, prv, c->nmove[p ^ 1], cn, sh1, &movers, &occz, &a0);
+                nA = movers - cn;
+                nB = cn;
+            }
+            if (d.climb_ok && !cur.done && !cur.jump && cur.l == cur.phys && !group_start(d, cur.l + 1) &&
+                cur.l + 2 <= d.K && movers >= d.climb_min) {
+                const int32_t work = occz - movers + d.occ[cur.l + 1] + d.occ[cur.l + 2];
+                if ((int64_t)work * 2 <= movers) hand = true;   // a climbing step: the step kernels run it
+            }
+        }
+        const int32_t nm = nA + nB;
+        int32_t slots = 0;
+        if (!hand && !cur.done) {
+            if (cur.phys < 0 || cur.phys > cur.l || cur.l + 1 >= d.K || nm > d.n) {
+                if (tid == 0) {
+                    latch(c, kErrLevel);
+                    s_stop = 1;
+                }
+                __syncthreads();
+                break;
+            }
+            if (nm > kInsLoopMovers) {
+                hand = true;
+            } else {
+                // the movers, their slabs and slab sizes (two per thread)
+                const int32_t *casc = cur.cur ? d.casc1 : d.casc0;
+                int32_t cap2 = 0;
+                for (int i = 2 * tid; i < 2 * tid + 2; i++) {
+                    if (i >= nm) break;
+                    const int32_t v = i < nA ? d.sorted[a0 + i] : casc[i - nA];
+                    const int32_t cp = d.cap[v];
+                    s_mv[i] = v;
+                    s_off[i] = d.off[v];
+                    s_stay[i] = 0;
+                    s_pre[i] = cp;
+                    cap2 += cp;
+                }
+                int32_t first = 0;
+                const int32_t base = block_excl(cap2, &slots, red);
+                if (2 * tid < nm) {
+                    first = s_pre[2 * tid];
+                    s_pre[2 * tid] = base;
+                    if (2 * tid + 1 < nm) s_pre[2 * tid + 1] = base + first;
+                }
+                if (tid == 0) s_pre[nm] = slots;
+                __syncthreads();
+                if (slots > kInsLoopSlots) hand = true;
+            }
+        }
+        if (hand) {
+            if (tid == 0) {
+                c->ins_big = 1;
+                c->ins_p = p;
+                s_stop = 1;
+            }
+            __syncthreads();
+            break;
+        }
+        // commit: the previous step's bookkeeping and occupancy change, the
+        // step state, the work-list counters (as k_ins_prep's writer and
+        // k_ins_scan's keeper)
+        if (tid == 0) {
+            if (!prv.fresh) {
+                const int32_t nm0 = c->nmove[p ^ 1];
+                ins_account(d, prv, nm0, ins_items(c, p ^ 1));
+                if (nm0) {
+                    d.occ[prv.phys] -= nm0;
+                    d.occ[prv.l + 1] += nm0;
+                }
+            }
+            c->st[p] = cur;
+            ins_store(c, cur);
+            c->n_chunks2[p ^ 1] = 0;
+            c->n_cls2[p ^ 1][0] = c->n_cls2[p ^ 1][1] = c->n_cls2[p ^ 1][2] = c->n_cls2[p ^ 1][3] = 0;
+            c->n_cw[p ^ 1] = 0;
+            c->step_dec[p] = 0;
+            c->n_sl[p ^ 1] = 0;
+            c->n_cl_snap = c->n_cl;
+            s_nc = 0;
+            s_nsl = 0;
+            s_slbase = c->n_sl[p];
+        }
+        {   // the previous step's movers lose its flag (a mover that moves again keeps this step's)
+            const int32_t np = c->nmvb[p ^ 1];
+            const int32_t *prev = p ? d.mv : d.mv1;
+            for (int i = tid; i < np; i += kLoopBlock) {
+                const int32_t u = prev[i];
+                const int32_t raw = d.level[u];
+                d.level[u] = (raw & (kLevelMask | kClimb)) | ((raw & Mp) ? Mp : 0);
+            }
+        }
+        __syncthreads();
+        if (cur.done) {
+            if (tid == 0) s_stop = 1;
+            __syncthreads();
+            break;
+        }
+        // prepare: flag the movers, list them for the next step's clearing,
+        // and count them by slab-size class (the step log's work items)
+        int32_t *mvp = p ? d.mv1 : d.mv;
+        int32_t k0 = 0, k1 = 0, k2 = 0, k3 = 0, kch = 0;
+        for (int i = tid; i < nm; i += kLoopBlock) {
+            const int32_t v = s_mv[i];
+            const int32_t cp = s_pre[i + 1] - s_pre[i];
+            mvp[i] = v;
+            d.level[v] = cur.phys | Mp;
+            k0 += cp <= 8;
+            k1 += cp > 8 && cp <= 16;
+            k2 += cp > 16 && cp <= 32;
+            k3 += cp > 32 && cp <= 64;
+            kch += cp > 64 ? (cp + kChunk - 1) / kChunk : 0;
+        }
+        k0 = block_sum32(k0, red);
+        k1 = block_sum32(k1, red);
+        k2 = block_sum32(k2, red);
+        k3 = block_sum32(k3, red);
+        kch = block_sum32(kch, red);   // (its barriers also order the flagging before the scan)
+        if (tid == 0) {
+            c->n_cls2[p][0] = k0;
+            c->n_cls2[p][1] = k1;
+            c->n_cls2[p][2] = k2;
+            c->n_cls2[p][3] = k3;
+            c->n_chunks2[p] = kch;
+            c->nmvb[p] = c->nmove[p] = nm;
+        }
+        // scan: the slots of all movers' slabs, kInsLoopR per thread, their
+        // loads issued together
+        const int32_t l = cur.l, nxt = cur.cur ^ 1;
+        int32_t *casc = nxt ? d.casc1 : d.casc0;
+        const int32_t ub1_all = d.ng == 1 ? d.up_max[(l + 1) / d.L] : 0;
+        int32_t wv[kInsLoopR], mo[kInsLoopR];
+#pragma unroll
+        for (int k = 0; k < kInsLoopR; k++) {
+            const int32_t j = tid + k * kLoopBlock;
+            wv[k] = -1;
+            mo[k] = 0;
+            if (j < slots) {
+                const int32_t mi = prefix_owner(s_pre, nm, j);
+                mo[k] = mi;
+                wv[k] = d.pool[s_off[mi] + (j - s_pre[mi])];
+            }
+        }
+        int32_t rw[kInsLoopR];
+#pragma unroll
+        for (int k = 0; k < kInsLoopR; k++) rw[k] = wv[k] >= 0 ? d.level[wv[k]] : 0;
+        int32_t nU = 0, n1 = 0;
+#pragma unroll
+        for (int k = 0; k < kInsLoopR; k++) {
+            const int32_t w = wv[k], raw = rw[k];
+            const bool comover = w >= 0 && (raw & Mp);
+            const int32_t lw = (w < 0 || comover) ? -1 : (raw & kLevelMask);
+            nU += comover || lw >= l;
+            if (lw == l) {
+                atomicAdd(&s_stay[mo[k]], 1);
+            } else if (lw == l + 1) {
+                n1++;
+                const int32_t ub1 = d.ng == 1 ? ub1_all : up_cap(d, gp(d, w), l + 1);
+                const int32_t old = atomicAdd(&d.up[w], 1);
+                if (cur.jump) atomicAdd(&d.ups[w], 1);
+                if (old == ub1) {
+                    const int32_t pos = atomicAdd(&s_nc, 1);
+                    if (pos < d.n) casc[pos] = w;
+                    else latch(c, kErrPool);
+                }
+            } else if (lw == l + 2) {
+                atomicAdd(&d.ups[w], 1);
+            }
+        }
+        nU = block_sum32(nU, red);
+        n1 = block_sum32(n1, red);
+        // finish the movers: level l+1, up*(v) = old up(v), up(v) = old up(v) - stay;
+        // a mover still above the cap of l+1 keeps moving (next step's flag, cascade list)
+        int32_t *slist = p ? d.sl1 : d.sl0;
+        for (int i = tid; i < nm; i += kLoopBlock) {
+            const int32_t v = s_mv[i];
+            int32_t u = ld_dev(&d.up[v]);   // atomics of earlier steps of this launch may have changed it
+            d.ups[v] = u;
+            u -= s_stay[i];
+            d.up[v] = u;
+            const int32_t ub1 = d.ng == 1 ? ub1_all : up_cap(d, gp(d, v), l + 1);
+            const bool viol = u > ub1;
+            d.level[v] = (l + 1) | Mp | (viol ? Mn : 0);
+            if (viol) {
+                const int32_t pos = atomicAdd(&s_nc, 1);
+                if (pos < d.n) casc[pos] = v;
+                else latch(c, kErrPool);
+            } else if (d.climb_ok) {
+                const int32_t pos = s_slbase + atomicAdd(&s_nsl, 1);
+                if (pos < d.n) slist[pos] = v;
+                else latch(c, kErrPool);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            c->casc_n[nxt] = s_nc;
+            c->n_sl[p] = s_slbase + s_nsl;
+            c->lp_scanned += slots;
+            c->lp_U += nU;
+            c->lp_up1 += n1;
+            c->lp_moves += (int64_t)nm * (l + 1 - cur.phys);
+            c->lp_steps++;
+            s_p = p ^ 1;
+            c->ins_p = p ^ 1;
+            if (c->n_steps > 2 * d.K + 2) latch(c, kErrLevel);   // a level gets at most an exit and a moving step
+            s_stop = ld_dev(&c->err) != 0;
         }
         __syncthreads();
     }
@@ -3926,6 +4250,8 @@ struct plds {
     // steps of the last insertion sweep: that many are issued before the
     // first wait for the sweep's end
     int64_t ins_steps_hint = 0;
+    int64_t ins_trips_hint = 0;   // launches of the single-block loop the last sweep needed
+    bool ins_loop_on = true;      // the next insertion sweep runs its small steps in the single-block loop
     // insertion sweep as one cooperative launch (0 blocks = not available)
     int sweep_mode = 1;          // 0: cooperative when possible, 1: one kernel per part
     int coop_blocks = -1;        // -1 = not yet determined
@@ -4361,7 +4687,9 @@ int apply_list(plds *h, const int32_t *e, int64_t cnt, int insert, hipStream_t s
 }
 
 // The insertion step sequence (prep, scan) x graph_steps as one graph of
-// kernel nodes, rebuilt when the device buffers move.
+// kernel nodes, each pair preceded by the single-block loop when it runs the
+// small steps (then a pair runs only a step the loop leaves); rebuilt when
+// the device buffers move.
 int ins_graph(plds *h) {
     if (h->ins_exec && !memcmp(&h->ins_graph_dev, &h->d, sizeof(Dev))) return 0;
     if (h->ins_exec) (void)hipGraphExecDestroy(h->ins_exec);
@@ -4375,18 +4703,20 @@ int ins_graph(plds *h) {
     void *a1[] = {(void *)dv, (void *)&h->par[1]};
     struct K {
         const void *f;
-        int grid;
-    } ks[2] = {{(const void *)k_ins_prep, kListGrid}, {(const void *)k_ins_scan, h->scan_grid}};
+        int grid, block;
+    } ks[3] = {{(const void *)k_ins_loop, 1, kLoopBlock},
+               {(const void *)k_ins_prep, kListGrid, kBlock},
+               {(const void *)k_ins_scan, h->scan_grid, kBlock}};
     hipGraphNode_t prev = nullptr;
     for (int i = 0; i < h->graph_steps; i++) {
-        for (int k = 0; k < 2; k++) {
+        for (int k = h->d.ins_loop ? 0 : 1; k < 3; k++) {
             hipGraphNode_t node;
             hipKernelNodeParams p{};
             p.func = const_cast<void *>(ks[k].f);
             p.gridDim = dim3(ks[k].grid);
-            p.blockDim = dim3(kBlock);
+            p.blockDim = dim3(ks[k].block);
             p.sharedMemBytes = 0;
-            p.kernelParams = (i & 1) ? a1 : a0;
+            p.kernelParams = (i & 1) ? a1 : a0;   // (the loop takes the Dev alone)
             p.extra = nullptr;
             if (hipGraphAddKernelNode(&node, h->ins_graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
                 return PLDS_EHIP;
@@ -4477,8 +4807,11 @@ int insertion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
     int nt = h->h_ctl->n_touch;
     // climbing steps: plain handles, per-part kernels, level histograms in LDS
-    d.climb_ok = (h->sweep_mode == 1 || h->sweep_mode == 3) && d.ng == 1 && h->K <= kHistMax ? 1 : 0;
+    d.climb_ok = (h->sweep_mode == 1 || h->sweep_mode == 3) && h->K <= kHistMax ? 1 : 0;
     d.climb_min = h->sweep_mode == 3 ? 1 : kClimbMin;
+    // small steps in the single-block loop: per-part kernels (mode 2 sends
+    // every step to them), when most steps of the last sweep were small
+    d.ins_loop = (h->sweep_mode == 1 || h->sweep_mode == 3) && h->ins_loop_on ? 1 : 0;
     HIPCHK(hipMemsetAsync(d.lvl_cnt, 0, (size_t)(h->K + 1) * sizeof(int32_t), s));
     size_t hist = (size_t)(h->K <= kHistMax ? h->K : 0) * sizeof(int32_t);
     hipLaunchKernelGGL(k_ins_seed, dim3(grid_for(nt, kBlock, kApplyGrid)), dim3(kBlock), hist, s, d);
@@ -4490,7 +4823,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
     // seeding without a wait (the steps of a sweep without candidates return
     // at once).  Otherwise, and for the cooperative or timed forms, wait.
     const bool eager = h->sweep_mode != 0 && h->sweep_mode != 4 && h->timed_kind != 1 && h->timed_kind != 4 &&
-                       h->ins_steps_hint >= 32;
+                       h->timed_kind != 11 && h->ins_steps_hint >= 32;
     int rc = PLDS_OK;
     if (!eager) {
         rc = sync_ctl(h, s);
@@ -4528,18 +4861,21 @@ int insertion_sweep(plds *h, hipStream_t s) {
     }
     int64_t steps = 0;
     // a timed step kernel is launched directly, so that its events bracket the dispatch alone
-    bool use_graph = h->timed_kind != 1 && h->timed_kind != 4;
+    bool use_graph = h->timed_kind != 1 && h->timed_kind != 4 && h->timed_kind != 11;
     // launched one by one: a first run of 7/8 of the steps the last sweep
     // took (even, so that every run starts at parity 0), then runs of 16,
     // 32, ... (a step launched after the sweep's end still costs its launches
     // on the host)
-    int run = use_graph ? h->graph_steps
-                        : (int)std::min<int64_t>(std::max<int64_t>((h->ins_steps_hint * 7 / 8) & ~1LL, 8), 256);
+    // with the single-block loop, a step slot of the sequence is (loop,
+    // prep, scan), and the sweep needs about as many slots as the loop's
+    // launches that found it running
+    const int64_t hint = d.ins_loop ? h->ins_trips_hint : h->ins_steps_hint;
+    int run = use_graph ? h->graph_steps : (int)std::min<int64_t>(std::max<int64_t>((hint * 7 / 8) & ~1LL, 8), 256);
     int next_run = 16;
     // before the first wait, issue about as many steps as the last sweep
     // took (rounded down to whole step graphs); steps issued after the
     // sweep's end return at once
-    int64_t first = std::min<int64_t>(std::max<int64_t>(h->ins_steps_hint / h->graph_steps, 1), 8);
+    int64_t first = std::min<int64_t>(std::max<int64_t>(hint / h->graph_steps, 1), 8);
     while (!h->h_ctl->done && !h->h_ctl->err) {
         if (steps > 2 * (int64_t)h->K + 2) {   // a level gets at most an exit step and a moving step
             h->broken = true;
@@ -4555,6 +4891,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
             steps += run;
             for (int i = 0; i < run; i++) {      // run is even: every run starts at parity 0
                 int par = i & 1;
+                if (d.ins_loop) tlaunch(h, 11, k_ins_loop, dim3(1), dim3(kLoopBlock), 0, s, d);
                 tlaunch(h, 4, k_ins_prep, dim3(kListGrid), dim3(kBlock), 0, s, d, par);
                 tlaunch(h, 1, k_ins_scan, dim3(h->scan_grid), dim3(kBlock), 0, s, d, par);
             }
@@ -4576,9 +4913,17 @@ int insertion_sweep(plds *h, hipStream_t s) {
     Ctl *c = h->h_ctl;
     h->stats.viol_ins0 = c->n_cand;
     h->ins_steps_hint = c->n_steps + 1;   // the steps and the one that found the sweep done
+    h->ins_trips_hint = c->ins_trips + 1;
+    // the loop pays off when most steps are small (it decides a large step
+    // before leaving it to the step kernels, and costs a launch per step slot)
+    if (c->n_steps > 0) h->ins_loop_on = 2 * (d.ins_loop ? c->lp_steps : c->n_small) >= c->n_steps;
     h->stats.sweeps_ins += c->sweeps;
     h->stats.moves_up += c->moves;
     h->stats.alg_bytes_up += 8 * (c->alg_U + c->alg_up1) + 4 * c->moves;
+    h->stats.alg_bytes_up_loop += 8 * (c->lp_U + c->lp_up1) + 4 * c->lp_moves;
+    h->stats.ins_steps += c->n_steps;
+    h->stats.ins_loop_steps += c->lp_steps;
+    h->stats.ins_loop_launches += c->ins_trips;
     h->stats.slots_scanned += c->scanned;
     h->stats.top_level = std::max(h->stats.top_level, c->top);
     return check_err(h);
@@ -5567,7 +5912,7 @@ int plds_inject_alloc_failure(int64_t after) {
 }
 
 int plds_set_timing(plds_t *h, int32_t kernel) {
-    if (!h || kernel < 0 || kernel > 10) return PLDS_EINVAL;
+    if (!h || kernel < 0 || kernel > 11) return PLDS_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return PLDS_EHIP;
     if (kernel && h->ev.empty()) {
         h->ev.assign(2 * kEvPairs, nullptr);

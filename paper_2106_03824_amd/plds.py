@@ -49,15 +49,20 @@ class plds_info_t(ctypes.Structure):
 
 STAT_FIELDS = ("applied_ins", "applied_del", "sweeps_ins", "sweeps_del", "moves_up", "moves_down", "dl_calcs",
                "slots_scanned", "top_level", "viol_ins0", "viol_del0", "host_syncs", "alg_bytes_up",
-               "timed_launches", "timed_ms", "alg_bytes_peel")
+               "timed_launches", "timed_ms", "alg_bytes_peel", "alg_bytes_up_loop", "ins_steps", "ins_loop_steps",
+               "ins_loop_launches")
 
 
 class plds_stats_t(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS[:-2]] + [("timed_ms", ctypes.c_double),
-                                                                   ("alg_bytes_peel", ctypes.c_int64)]
+    _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS[:-6]] + [("timed_ms", ctypes.c_double),
+                                                                   ("alg_bytes_peel", ctypes.c_int64),
+                                                                   ("alg_bytes_up_loop", ctypes.c_int64),
+                                                                   ("ins_steps", ctypes.c_int64),
+                                                                   ("ins_loop_steps", ctypes.c_int64),
+                                                                   ("ins_loop_launches", ctypes.c_int64)]
 
 TIMED_KERNELS = {"ins_scan": 1, "del_scan": 2, "dl": 3, "ins_prep": 4, "flip_scan": 5, "ins_sweep": 6, "sk_relax": 7,
-                 "apply_del": 8, "del_loop": 9, "jmp_scan": 10}
+                 "apply_del": 8, "del_loop": 9, "jmp_scan": 10, "ins_loop": 11}
 
 
 _lib = None

@@ -36,14 +36,16 @@ def make_graphs(k, seed, nmin_log=6, nmax_log=12):
     return gs
 
 
-def run_case(k, seed, rounds, with_oracle):
+def run_case(k, seed, rounds, with_oracle, mode=None):
     from paper_2106_03824_amd import plds as P
     rng = random.Random(seed + 7)
     gs = make_graphs(k, seed)
     ns = [n for n, _ in gs]
-    say("multi", k, "graphs, n from", min(ns), "to", max(ns))
+    say("multi", k, "graphs, n from", min(ns), "to", max(ns), "sweep mode", mode)
     mg = P.MultiPLDS(ns)
     singles = [P.PLDS(n) for n in ns]
+    if mode is not None:
+        P.plds_set_sweep_mode(mg.h, mode)
     oras = [O.Oracle(n) for n in ns] if with_oracle else None
     assert len(set(gi["L"] for gi in mg.graphs)) > 1     # graphs really differ in levels per group
     cur = [e for _, e in gs]
@@ -106,6 +108,16 @@ def test_multi_small_against_singles_and_oracle():
 
 def test_multi_many_graphs_against_singles():
     run_case(24, 2, 2, False)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_multi_climbing_and_plain_steps(mode):
+    """Mode 3 lets groups of any size climb (so the climbing steps run with
+    members of graphs that differ in levels per group and caps, landing on
+    group boundaries of some graphs and not others); mode 2 runs every step
+    as a plain step.  Both against the graphs' own plain handles and the
+    oracle."""
+    run_case(8, 5, 3, True, mode=mode)
 
 
 def test_multi_range_is_per_graph():
