@@ -3986,11 +3986,31 @@ __global__ void k_dump_edges(Dev d, int32_t *out, int64_t cap_out) {
 }
 
 // number of vertices per level
+// Vertices per level into occ: a histogram per block in LDS (dynamic, K bins)
+// when K <= kHistMax, flushed with one atomic per non-empty bin; else
+// atomics aggregated per wavefront over equal levels.
 __global__ void k_count_levels(Dev d, int32_t *occ) {
-    int stride = gridDim.x * blockDim.x;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < d.n; v += stride) {
-        int32_t x = d.level[v];
-        if (x >= 0 && x < d.K) atomicAdd(&occ[x], 1);
+    extern __shared__ int32_t hist[];
+    const int stride = gridDim.x * blockDim.x;
+    const bool lds = d.K <= kHistMax;
+    if (lds) {
+        for (int i = threadIdx.x; i < d.K; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+    }
+    for (int v0 = blockIdx.x * blockDim.x; v0 < d.n; v0 += stride) {   // wave-uniform
+        const int v = v0 + threadIdx.x;
+        const int32_t x = v < d.n ? d.level[v] : -1;
+        const bool ok = x >= 0 && x < d.K;
+        if (lds) {
+            if (ok) atomicAdd(&hist[x], 1);
+        } else {
+            wave_add_key(occ, ok ? x : -1, 1);
+        }
+    }
+    if (lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < d.K; i += blockDim.x)
+            if (hist[i]) atomicAdd(&occ[i], hist[i]);
     }
 }
 
@@ -4353,6 +4373,13 @@ void dfree(T *&p) {
 int grid_for(int64_t work, int block = kBlock, int cap = 4096) {
     int64_t g = (work + block - 1) / block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// Vertices per level of the handle into occ (k_count_levels).
+void count_levels(const plds *h, int32_t *occ, hipStream_t s) {
+    const bool lds = h->K <= kHistMax;
+    hipLaunchKernelGGL(k_count_levels, dim3(lds ? std::min(grid_for(h->n), 512) : grid_for(h->n)), dim3(kBlock),
+                       lds ? (size_t)h->K * sizeof(int32_t) : 0, s, h->d, occ);
 }
 
 // Tables of every graph of the handle, concatenated; the handle's t, L, G,
@@ -4915,8 +4942,12 @@ int insertion_sweep(plds *h, hipStream_t s) {
     h->ins_steps_hint = c->n_steps + 1;   // the steps and the one that found the sweep done
     h->ins_trips_hint = c->ins_trips + 1;
     // the loop pays off when most steps are small (it decides a large step
-    // before leaving it to the step kernels, and costs a launch per step slot)
-    if (c->n_steps > 0) h->ins_loop_on = 2 * (d.ins_loop ? c->lp_steps : c->n_small) >= c->n_steps;
+    // before leaving it to the step kernels, and costs a launch per step
+    // slot): on when at least 4/5 of the step kernels' steps had few movers
+    // (the loop would also need their slabs to be small), off again when it
+    // ran less than half of the steps
+    if (c->n_steps > 0)
+        h->ins_loop_on = d.ins_loop ? 2 * c->lp_steps >= c->n_steps : 5 * (int64_t)c->n_small >= 4 * (int64_t)c->n_steps;
     h->stats.sweeps_ins += c->sweeps;
     h->stats.moves_up += c->moves;
     h->stats.alg_bytes_up += 8 * (c->alg_U + c->alg_up1) + 4 * c->moves;
@@ -5946,7 +5977,7 @@ int plds_check(plds_t *h, void *stream) {
     HIPCHK(hipMemsetAsync(h->bad, 0, 8 * sizeof(int32_t), s));
     hipLaunchKernelGGL(k_check, dim3(grid_for(h->n * kWave)), dim3(kBlock), 0, s, h->d, h->bad);
     HIPCHK(hipMemsetAsync(h->d.lvl_cnt, 0, (h->K + 1) * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_count_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, h->d, h->d.lvl_cnt);
+    count_levels(h, h->d.lvl_cnt, s);
     hipLaunchKernelGGL(k_compare, dim3(grid_for(h->K)), dim3(kBlock), 0, s, h->d.lvl_cnt, h->d.occ, h->K,
                        h->bad + 6);
     HIPCHK(hipGetLastError());
@@ -6009,7 +6040,7 @@ int plds_load_state(plds_t *h, const int32_t *edges, int64_t m, const int32_t *l
     HIPCHK(hipMemsetAsync(d.dl, 0xff, n4, s));
     hipLaunchKernelGGL(k_set_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d, levels);
     HIPCHK(hipMemsetAsync(d.occ, 0, (h->K + 1) * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_count_levels, dim3(grid_for(h->n)), dim3(kBlock), 0, s, d, d.occ);
+    count_levels(h, d.occ, s);
     HIPCHK(hipGetLastError());
     int64_t applied = 0;
     if (m) {
