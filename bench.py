@@ -771,24 +771,7 @@ def run_stream(args, P, W, torch, np):
 
 def batched_workload(k, W, np):
     """The graphs and measured batches of the batched form (seed 4000 + i)."""
-    import random
-    rng = random.Random(4000)
-    graphs = []
-    for i in range(k):
-        if i % 2 == 0:
-            n = int(round(2 ** rng.uniform(10, 16)))
-            e = W.er(n, rng.uniform(4, 32) / (n - 1), seed=4000 + i)
-        else:
-            sc = rng.randint(10, 16)
-            n = 2 ** sc
-            e = W.rmat(sc, 8 * n, seed=4000 + i)
-        size = rng.randint(10 ** 3, 5 * 10 ** 4)
-        if rng.random() < 0.5:
-            b = ("ins", W.new_pairs(n, e, size, 4500 + i))
-        else:
-            b = ("del", W.sample_edges(e, min(size, len(e)), 4500 + i))
-        graphs.append((n, e, b))
-    return graphs
+    return W.batched_graphs(k)
 
 
 def tuning_batches(graphs, W):

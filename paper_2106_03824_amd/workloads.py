@@ -191,3 +191,31 @@ class RmatStream:
         cur = np.setdiff1d(self.cur, _keys(dele), assume_unique=True)
         self.cur = np.sort(np.concatenate([cur, _keys(ins)]))
         return ins, dele
+
+
+def batched_graphs(k, seed=4000):
+    """The batched form's workload: k graphs of uneven size, alternately
+    Erdos-Renyi G(n, p) (n log-uniform in [2^10, 2^16], mean degree uniform
+    in [4, 32]) and R-MAT (scale uniform in [10, 16], edge factor 8), each
+    with one measured batch: insertions of new pairs or deletions of present
+    edges (probability 1/2 each), size uniform in [10^3, 5*10^4], deletions
+    clamped to m.  Returns [(n, edges, (kind, batch))]; graph i draws with
+    seed + i, its batch with seed + 500 + i."""
+    import random
+    rng = random.Random(seed)
+    graphs = []
+    for i in range(k):
+        if i % 2 == 0:
+            n = int(round(2 ** rng.uniform(10, 16)))
+            e = er(n, rng.uniform(4, 32) / (n - 1), seed=seed + i)
+        else:
+            sc = rng.randint(10, 16)
+            n = 2 ** sc
+            e = rmat(sc, 8 * n, seed=seed + i)
+        size = rng.randint(10 ** 3, 5 * 10 ** 4)
+        if rng.random() < 0.5:
+            b = ("ins", new_pairs(n, e, size, seed + 500 + i))
+        else:
+            b = ("del", sample_edges(e, min(size, len(e)), seed + 500 + i))
+        graphs.append((n, e, b))
+    return graphs

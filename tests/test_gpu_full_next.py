@@ -176,3 +176,40 @@ def test_vertex_deletions_full_size(stream):
     sg, so = g.stats(), o.stats()
     for k in ("applied_del", "sweeps_del", "moves_down", "viol_del0"):
         assert sg[k] == so[k], (k, sg[k], so[k])
+
+
+def test_dirty_mixed_batch_full_size(stream):
+    """Batch application (a1) at full size on a dirty mixed batch: the
+    insertion list repeats its pairs (also reversed), holds self-loops and
+    edges already present; the deletion list repeats its pairs, holds pairs
+    that are absent and self-loops; some pairs are in both lists.  The
+    oracle loaded with its stored post-build state applies the same lists;
+    levels, degrees and the applied counts must be identical."""
+    g = built(stream)
+    rng = np.random.default_rng(4200)
+    n = stream.n
+    e = np.concatenate(stream.build)
+    fresh = W.new_pairs(n, e, 400000, 4201)
+    present = W.sample_edges(e, 300000, 4202)
+    loops = np.repeat(rng.integers(0, n, 5000).astype(np.int32)[:, None], 2, axis=1)
+    absent = W.new_pairs(n, e, 100000, 4203)
+    both = fresh[:50000]                                   # inserted and deleted in the same batch
+    ins = np.concatenate([fresh, fresh[rng.integers(0, len(fresh), 200000)], fresh[:100000, ::-1],
+                          present[:100000], loops])
+    dele = np.concatenate([present, present[rng.integers(0, len(present), 100000), ::-1], absent, loops[:1000],
+                           both])
+    ins = np.ascontiguousarray(ins[rng.permutation(len(ins))]).astype(np.int32)
+    dele = np.ascontiguousarray(dele[rng.permutation(len(dele))]).astype(np.int32)
+    say("full size: dirty mixed batch", len(ins), "insertions,", len(dele), "deletions")
+    assert g.update(ins, dele) == 0
+    assert g.check() == 0
+    say("full size: dirty mixed batch on the oracle")
+    o = O.Oracle(n, 0.4, 3.0)
+    lv_oracle = np.load(os.path.join(GOLDEN, "rmat20_oracle_levels.npz"))["levels"].astype(np.int32)
+    assert o.load_state(e, lv_oracle) == 0
+    assert o.update(ins, dele) == 0
+    assert np.array_equal(g.levels().cpu().numpy(), o.levels())
+    assert np.array_equal(g.degrees().cpu().numpy(), o.degrees())
+    sg, so = g.stats(), o.stats()
+    for k in ("applied_ins", "applied_del", "viol_ins0", "viol_del0"):
+        assert sg[k] == so[k], (k, sg[k], so[k])
