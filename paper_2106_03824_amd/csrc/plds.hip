@@ -4833,8 +4833,12 @@ int coop_blocks(plds *h) {
 int insertion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
     int nt = h->h_ctl->n_touch;
-    // climbing steps: plain handles, per-part kernels, level histograms in LDS
-    d.climb_ok = (h->sweep_mode == 1 || h->sweep_mode == 3) && h->K <= kHistMax ? 1 : 0;
+    // climbing steps: per-part kernels, level histograms in LDS, and a batch
+    // with enough touched endpoints that a step could have kClimbMin movers
+    // (mode 3: any); otherwise the sweep skips the O(n) resident buckets
+    // they need (climbing is exact, so results do not depend on it)
+    d.climb_ok = (h->sweep_mode == 1 || h->sweep_mode == 3) && h->K <= kHistMax &&
+                 (h->sweep_mode == 3 || nt >= kClimbMin) ? 1 : 0;
     d.climb_min = h->sweep_mode == 3 ? 1 : kClimbMin;
     // small steps in the single-block loop: per-part kernels (mode 2 sends
     // every step to them), when most steps of the last sweep were small

@@ -24,15 +24,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make_trace(ngraphs, nreq, seed, rate):
+def make_trace(ngraphs, nreq, seed, rate, scales=(8, 12), ef=8, size_exp=(1, 3.3), query=100):
     from paper_2106_03824_amd.serve import Request
     rng = random.Random(seed)
     reqs, t, rid = [], 0.0, 0
     graphs = {}
     for g in range(ngraphs):
-        sc = rng.randint(8, 12)
+        sc = rng.randint(*scales)
         n = 2 ** sc
-        e = W.rmat(sc, 8 * n, seed=seed * 100 + g)
+        e = W.rmat(sc, ef * n, seed=seed * 100 + g)
         graphs[g] = (n, e)
         reqs.append(Request(rid, g, "admit", t, (n, e)))
         rid += 1
@@ -42,7 +42,7 @@ def make_trace(ngraphs, nreq, seed, rate):
         g = rng.randrange(ngraphs)
         n, e = graphs[g]
         if rng.random() < 0.5:
-            size = int(round(10 ** rng.uniform(1, 3.3)))
+            size = int(round(10 ** rng.uniform(*size_exp)))
             if rng.random() < 0.7:
                 r = np.random.default_rng(seed * 7919 + i)
                 ins = r.integers(0, n, size=(size, 2), dtype=np.int32)
@@ -51,7 +51,7 @@ def make_trace(ngraphs, nreq, seed, rate):
                 reqs.append(Request(rid, g, "update", t, (None, W.sample_edges(e, min(size, len(e)), seed + i))))
         else:
             r = np.random.default_rng(seed * 104729 + i)
-            reqs.append(Request(rid, g, "query", t, r.integers(0, n, size=100, dtype=np.int32)))
+            reqs.append(Request(rid, g, "query", t, r.integers(0, n, size=query, dtype=np.int32)))
         rid += 1
         last[g] = t
     for g in graphs:
@@ -117,6 +117,21 @@ def test_serving_mix_equals_alone_equals_oracle():
     assert max(r.fused for r in reqs) > 1
     spans = sorted((r.start, r.done, r.graph) for r in reqs)
     assert any(b[0] < a[1] and b[2] != a[2] for a, b in zip(spans, spans[1:]))
+
+
+def test_serving_benchmark_mix_against_oracle():
+    """The serving benchmark's graph shape and request mix (R-MAT with edge
+    factor 16, update batches of log-uniform size from 10^2, 70% insertions,
+    coreness queries of 10^3 vertices) at scales 12..13 and batches up to
+    10^4 (the oracle builds a scale-14 graph in one batch in about 11 s, a
+    scale-16 one in minutes): fused serving equals the oracle's replay."""
+    from paper_2106_03824_amd.serve import replay
+    reqs = make_trace(4, 40, 11, rate=2000.0, scales=(12, 13), ef=16, size_exp=(2, 4), query=1000)
+    say("serve: benchmark mix, fused")
+    replay(reqs, budget_bytes=64 << 30, slots=4, arrival=False)
+    say("serve: benchmark mix, oracle replay")
+    same(results(reqs), oracle_replay(reqs))
+    assert max(r.fused for r in reqs) > 1
 
 
 def test_serving_admission_waits_for_budget():
