@@ -149,6 +149,7 @@ struct Ctl {
     int64_t lp_scanned, lp_U, lp_up1, lp_moves;   // the loop's share of the scan statistics and moves
     int32_t lp_steps;     // steps run by the loop
     int32_t n_small;      // pull steps of the step kernels with at most kInsLoopMovers movers
+    int32_t n_climbable;  // steps decided with at least kClimbMin movers (a climbing group could form)
 };
 
 // Everything a kernel needs, passed by value.
@@ -968,6 +969,7 @@ __global__ void k_level_scan(Dev d) {
         d.ctl->lp_scanned = d.ctl->lp_U = d.ctl->lp_up1 = d.ctl->lp_moves = 0;
         d.ctl->lp_steps = 0;
         d.ctl->n_small = 0;
+        d.ctl->n_climbable = 0;
     }
 }
 
@@ -1861,6 +1863,7 @@ __global__ void k_ins_prep(Dev d, int p) {
         c->n_cw[p ^ 1] = 0;
         c->step_dec[p] = 0;
         if (cur.mode == kPull && !cur.done && movers <= kInsLoopMovers) c->n_small++;
+        if (!cur.done && movers >= kClimbMin) c->n_climbable++;
         if (cur.mode != kPull) {
             c->nmvb[p] = 0;
             c->nmove[p] = nmove;
@@ -4272,6 +4275,7 @@ struct plds {
     int64_t ins_steps_hint = 0;
     int64_t ins_trips_hint = 0;   // launches of the single-block loop the last sweep needed
     bool ins_loop_on = true;      // the next insertion sweep runs its small steps in the single-block loop
+    bool climb_hint = true;       // the last insertion sweep decided a step that could climb
     // insertion sweep as one cooperative launch (0 blocks = not available)
     int sweep_mode = 1;          // 0: cooperative when possible, 1: one kernel per part
     int coop_blocks = -1;        // -1 = not yet determined
@@ -4834,11 +4838,12 @@ int insertion_sweep(plds *h, hipStream_t s) {
     Dev &d = h->d;
     int nt = h->h_ctl->n_touch;
     // climbing steps: per-part kernels, level histograms in LDS, and a batch
-    // with enough touched endpoints that a step could have kClimbMin movers
-    // (mode 3: any); otherwise the sweep skips the O(n) resident buckets
-    // they need (climbing is exact, so results do not depend on it)
+    // with enough touched endpoints that a step could have kClimbMin movers,
+    // after a sweep that had such a step (mode 3: always); otherwise the
+    // sweep skips the O(n) resident buckets they need (climbing is exact,
+    // so results do not depend on it)
     d.climb_ok = (h->sweep_mode == 1 || h->sweep_mode == 3) && h->K <= kHistMax &&
-                 (h->sweep_mode == 3 || nt >= kClimbMin) ? 1 : 0;
+                 (h->sweep_mode == 3 || (nt >= kClimbMin && h->climb_hint)) ? 1 : 0;
     d.climb_min = h->sweep_mode == 3 ? 1 : kClimbMin;
     // small steps in the single-block loop: per-part kernels (mode 2 sends
     // every step to them), when most steps of the last sweep were small
@@ -4945,6 +4950,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
     h->stats.viol_ins0 = c->n_cand;
     h->ins_steps_hint = c->n_steps + 1;   // the steps and the one that found the sweep done
     h->ins_trips_hint = c->ins_trips + 1;
+    h->climb_hint = c->n_climbable > 0 || c->n_steps == 0;
     // the loop pays off when most steps are small (it decides a large step
     // before leaving it to the step kernels, and costs a launch per step
     // slot): on when at least 4/5 of the step kernels' steps had few movers
