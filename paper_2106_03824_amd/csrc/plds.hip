@@ -4754,6 +4754,19 @@ int ins_graph(plds *h) {
             prev = node;
         }
     }
+    {   // the sweep's totals of the scan statistics, recomputed at the end of every graph, so
+        // that they are ready when the host sees the sweep done
+        hipGraphNode_t node;
+        hipKernelNodeParams p{};
+        void *at[] = {(void *)dv, (void *)&h->scan_grid};
+        p.func = (void *)k_ins_totals;
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(kBlock);
+        p.sharedMemBytes = 0;
+        p.kernelParams = at;
+        p.extra = nullptr;
+        if (hipGraphAddKernelNode(&node, h->ins_graph, &prev, 1, &p) != hipSuccess) return PLDS_EHIP;
+    }
     if (hipGraphInstantiate(&h->ins_exec, h->ins_graph, nullptr, nullptr, 0) != hipSuccess) return PLDS_EHIP;
     return 0;
 }
@@ -4896,6 +4909,7 @@ int insertion_sweep(plds *h, hipStream_t s) {
         }
     }
     int64_t steps = 0;
+    bool totals = false;
     // a timed step kernel is launched directly, so that its events bracket the dispatch alone
     bool use_graph = h->timed_kind != 1 && h->timed_kind != 4 && h->timed_kind != 11;
     // launched one by one: a first run of 7/8 of the steps the last sweep
@@ -4933,19 +4947,25 @@ int insertion_sweep(plds *h, hipStream_t s) {
             }
             run = next_run;
             next_run = std::min(next_run * 2, 256);
+            hipLaunchKernelGGL(k_ins_totals, dim3(1), dim3(kBlock), 0, s, d, h->scan_grid);
         }
         HIPCHK(hipGetLastError());
         rc = sync_ctl(h, s);
         if (rc) return rc;
         take_timing(h, h->ev_used);
+        totals = true;   // each run of steps ends with the totals (the graph's last node)
     }
-    hipLaunchKernelGGL(k_ins_totals, dim3(1), dim3(kBlock), 0, s, d, h->scan_grid);
+    if (!totals) {   // no step run by this loop (none needed, or the cooperative sweep ran them)
+        hipLaunchKernelGGL(k_ins_totals, dim3(1), dim3(kBlock), 0, s, d, h->scan_grid);
+        HIPCHK(hipGetLastError());
+        rc = sync_ctl(h, s);
+        if (rc) return rc;
+    }
+    // up* of the climbers that stopped; nothing the host reads depends on it
     if (h->h_ctl->n_rc > 0)
         hipLaunchKernelGGL(k_ups_recount, dim3(grid_for((int64_t)h->h_ctl->n_rc * kWave, kBlock, 2048)),
                            dim3(kBlock), 0, s, d);
     HIPCHK(hipGetLastError());
-    rc = sync_ctl(h, s);
-    if (rc) return rc;
     Ctl *c = h->h_ctl;
     h->stats.viol_ins0 = c->n_cand;
     h->ins_steps_hint = c->n_steps + 1;   // the steps and the one that found the sweep done
