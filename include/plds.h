@@ -19,7 +19,15 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is ordered on it.  Batch calls (insert/delete/update/load_state)
  *     return only after their work on `stream` is complete; plds_coreness,
- *     plds_levels and plds_degrees only enqueue work.
+ *     plds_levels and plds_degrees only enqueue work.  Batch calls block
+ *     because the host drives the level loops: it issues prebuilt graphs of
+ *     level steps and reads the small control block back between them to
+ *     learn whether a sweep has ended (a few host round trips per call; the
+ *     count is in plds_stats_t.host_syncs).  The HIP graphs of this
+ *     toolchain have no conditional nodes, and a persistent kernel with grid
+ *     barriers (sweep mode 0) measures slower, so a call cannot end its own
+ *     loop on the device.  Device errors are latched in the control block and
+ *     returned by the call that meets them.
  *   - a handle is not thread-safe; distinct handles are independent.
  *   - vertex ids are int32 in [0, n); n <= 2^31 - 1.
  */
@@ -357,9 +365,11 @@ int plds_set_sweep_mode(plds_t *h, int32_t mode);
  * schedule.  0 in a field selects the default.
  *   scan_blocks      blocks of the insertion scan, 64..2048 (default: the
  *                    blocks the device holds at once, at most 5 per CU);
- *   graph_steps      insertion steps per prebuilt step graph, even, 2..64
- *                    (default 16); steps issued past a sweep's end return
- *                    at once but still cost their launch;
+ *   graph_steps      insertion step slots per prebuilt step graph, even,
+ *                    2..64 (default 16; a slot is the step kernels' pair,
+ *                    preceded by the single-block loop when it runs the
+ *                    small steps); slots issued past a sweep's end return at
+ *                    once but still cost their launch;
  *   dl_blocks        blocks of the desire-level kernels of deletions and
  *                    of upward jumps, 64..4096 (default 1024);
  *   del_scan_blocks  blocks of the deletion scan and of the jump scan,
