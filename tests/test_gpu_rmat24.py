@@ -1,8 +1,10 @@
 """RMAT scale 24 (2^24 vertices, 16*2^24 unique edges), the large streamed
 workload of the benchmark, run through the C ABI exactly as bench.py
---scale 24 times it: the whole graph inserted as 10^6-edge batches in a
-seeded random permutation, then two deletion batches of 10^6 sampled edges
-and one mixed batch.
+--workload stream times it: the whole graph inserted as 10^6-edge batches
+in a seeded random permutation, then two deletion batches of 10^6 sampled
+edges and one mixed batch, then one deletion batch of every edge of the
+2,000 largest hubs (random deletions leave every vertex within its floor at
+this size, so this batch is the one that runs the deletion pass).
 
 Bit-exact parity: the stream's first batches (as many as the stored oracle
 trace tests/golden/rmat24_oracle_trace.json holds, written by
@@ -116,6 +118,18 @@ def test_rmat24_stream_properties():
     kept = ~np.isin(keys(e), keys(dels), assume_unique=True)
     cur = np.concatenate([e[kept], mix_ins])
     del e, kept
+    # random deletions barely move anyone at this size; every edge of the
+    # 2,000 largest hubs, deleted in one batch, makes the deletion pass work
+    deg0 = np.bincount(cur[:, 0], minlength=n) + np.bincount(cur[:, 1], minlength=n)
+    hub = np.zeros(n, dtype=bool)
+    hub[np.argsort(deg0, kind="stable")[-2000:]] = True
+    inc = hub[cur[:, 0]] | hub[cur[:, 1]]
+    say(f"rmat24 hub deletions: {int(inc.sum())} edges")
+    assert P.plds_update(g.h, None, torch.from_numpy(np.ascontiguousarray(cur[inc])).to(dev)) == 0
+    s = g.stats()
+    assert s["applied_del"] == int(inc.sum()) and s["sweeps_del"] > 0 and s["moves_down"] > 0, s
+    say(f"rmat24 hub deletions: {s['sweeps_del']} sweeps, {s['moves_down']} moves down")
+    cur = cur[~inc]
     assert g.info()["m"] == cur.shape[0]
     lv = g.levels().cpu().numpy()
     say("rmat24 final invariants")
