@@ -2484,6 +2484,17 @@ __global__ void k_del_select(Dev d) {
 // that starts violating Invariant 2, or that is already pending, gets its
 // desire-level recomputed after the step.  v's own degrees at level l are
 // counted on the way.
+// Whether a pending vertex's desire-level dw (-1: not pending) can change
+// when a neighbour moves down from level pv to l in a deletion step.  The
+// desire-level is the largest l' whose count of neighbours at level >= l'-1
+// reaches the floor; the move lowers the counts at the levels in (l, pv]
+// alone, and counts only fall during the pass, so dw can change only when
+// dw-1 is among those levels.  Otherwise the stored value stays exact and
+// no recomputation is needed.
+__device__ __forceinline__ bool pending_changes(int32_t dw, int32_t l, int32_t pv) {
+    return dw >= 0 && dw - 1 > l && dw - 1 <= pv;
+}
+
 __global__ void k_del_scan(Dev d) {
     Ctl *c = d.ctl;
     if (c->done || !c->del_big) return;
@@ -2511,7 +2522,7 @@ __global__ void k_del_scan(Dev d) {
                     int32_t lw = d.level[w];
                     cu += lw >= l;
                     cus += lw >= l - 1;
-                    bool again = dw >= 0;
+                    bool again = pending_changes(dw, l, pv);
                     if (lw > l && lw <= pv) atomicSub(&d.up[w], 1);
                     if (lw > l + 1 && lw <= pv + 1) {
                         int32_t old = atomicSub(&d.ups[w], 1);
@@ -2658,7 +2669,7 @@ __global__ void __launch_bounds__(kLoopBlock) k_del_loop(Dev d) {
                         const int32_t lw = d.level[w];
                         cu += lw >= l;
                         cus += lw >= l - 1;
-                        bool again = dw >= 0;
+                        bool again = pending_changes(dw, l, pv);
                         if (lw > l && lw <= pv) atomicSub(&d.up[w], 1);
                         if (lw > l + 1 && lw <= pv + 1) {
                             const int32_t old = atomicSub(&d.ups[w], 1);
