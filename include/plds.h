@@ -333,8 +333,9 @@ int plds_stats(const plds_t *h, plds_stats_t *out);
  * the call.  Insertion step: (l, level the movers left, movers, work items
  * of its scan + 2^48 * kind), the movers landing at l+1; kind 0 = movers
  * scan their slabs, 1 = climbing step, 2 = exit step (no move; l+1 = the
- * level left).  Deletion step: (-1-l, -1, movers, cumulative slots
- * scanned), the movers landing at l. */
+ * level left).  Deletion step: (-1-l, pending vertices, movers,
+ * cumulative slots scanned + 2^48 if the step ran in the grid kernels
+ * rather than the single-block loop), the movers landing at l. */
 int plds_step_log(plds_t *h, int64_t *out, int64_t cap, int64_t *rows);
 
 /* How the level loops run.  Insertions: 0 = the whole loop in one

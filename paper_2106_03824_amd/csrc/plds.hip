@@ -2424,9 +2424,9 @@ __global__ void k_del_next(Dev d, int mode) {
         if (c->n_log < 4 * d.K) {
             int64_t *row = d.steplog + 4 * c->n_log++;
             row[0] = -1 - c->l;
-            row[1] = -1;
+            row[1] = c->p_n[cur];
             row[2] = c->n_mv;
-            row[3] = c->scanned;
+            row[3] = c->scanned | (1LL << 48);   // run by the grid kernels
         }
         c->sweeps += 1;
         c->moves += c->n_mv;
@@ -2756,7 +2756,7 @@ __global__ void __launch_bounds__(kLoopBlock) k_del_loop(Dev d) {
             if (c->n_log < 4 * d.K) {
                 int64_t *row = d.steplog + 4 * c->n_log++;
                 row[0] = -1 - l;
-                row[1] = -1;
+                row[1] = np;
                 row[2] = nmv;
                 row[3] = c->scanned + (int64_t)s_scanned;
             }
