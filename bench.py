@@ -19,8 +19,10 @@ batch checked against the stored oracle trace of the stream; --no-rmat20
 leaves it out), the insertion-scan kernel against the HBM roofline (its
 launches timed with HIP events inside the library, on the call's stream;
 HBM traffic per launch from the committed counter summary under profiles/
-when it matches the current kernel source), and the CPU oracle (one core)
-timed on a bounded sample of the same RMAT-24 stream.
+when it matches the current kernel source), the CPU oracle (one core)
+timed on a bounded sample of the same RMAT-24 stream, and, as extra keys,
+the batched form ("batched", as --batched below; --no-batched leaves it
+out) and the serving form ("serving", as --serve below; --no-serve).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
     python bench.py --workload rmat20      # configuration 2 alone
@@ -273,6 +275,8 @@ def main():
                          "stream: the whole RMAT graph of --scale streamed in insertion batches, then deletions")
     ap.add_argument("--scale", type=int, default=24, help="scale of the rmat24 and stream workloads")
     ap.add_argument("--no-rmat20", action="store_true", help="leave the RMAT-20 stream out of the default run")
+    ap.add_argument("--no-batched", action="store_true", help="leave the batched form out of the default run")
+    ap.add_argument("--no-serve", action="store_true", help="leave the serving form out of the default run")
     ap.add_argument("--batch", type=int, default=10 ** 6)
     ap.add_argument("--kernel", default="ins_scan", help="kernel timed for the roofline")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -326,9 +330,11 @@ def main():
         return
     dev = torch.device("cuda", 0)
     if args.batched:
-        return run_batched(args, P, W, torch, np)
+        print(json.dumps(run_batched(args, P, W, torch, np)), flush=True)
+        return
     if args.serve:
-        return run_serve(args, P, W, torch, np)
+        print(json.dumps(run_serve(args, P, W, torch, np)), flush=True)
+        return
     if args.orient:
         return run_orient(args, P, W, torch, np)
     if args.static:
@@ -674,6 +680,16 @@ def run_rmat24(args, P, W, torch, np):
                                              "sweeps_per_step", "roofline", "parity_vs_oracle_trace", "config")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_rmat24(perm, n, args.cpu_seconds)
+    del perm
+    if not args.no_batched:   # configuration 4, as extra keys
+        b = run_batched(args, P, W, torch, np)
+        out["batched"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "per_graph_loop", "default_schedule",
+                                            "schedule", "schedules_timed", "speedup_vs_loop", "identical_levels",
+                                            "level_steps", "level_steps_alone", "config")}
+    if not args.no_serve:     # configuration 5, as extra keys
+        v = run_serve(args, P, W, torch, np)
+        out["serving"] = {k: v[k] for k in ("value", "unit", "latency", "identical_to_alone", "errors",
+                                            "one_at_a_time", "config")}
     print(json.dumps(out), flush=True)
 
 
@@ -879,7 +895,7 @@ def run_batched(args, P, W, torch, np):
                             "loop_launches": s["ins_loop_launches"]},
         "level_steps_alone": {"max": max(loop_steps), "sum": sum(loop_steps)},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_vertex(args, P, W, torch, np):
@@ -1204,7 +1220,7 @@ def run_serve(args, P, W, torch, np):
                           "note": "the saturation run's requests served one at a time with a plain handle per "
                                   "graph (sum of their service times)"},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def st_edges_after_build(st):
