@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Edge updates/s of the batch-dynamic PLDS on one MI355X.
 
-Default workload (configuration 3): an R-MAT graph of scale 24 (2^24
+Default workload: an R-MAT graph of scale 24 (2^24
 vertices, 16*2^24 unique edges, a=0.57 b=0.19 c=0.19, seed 1), delta=0.4,
 lambda=3, in the order of a seeded random permutation (seed 3001).  All but
 a held-out tail of the permutation is streamed in as insertion batches of
@@ -13,7 +13,7 @@ graph (deletions), and a mixed batch of half each.  Batches are in HBM
 before the timed region; the value is the number of applied updates over the
 wall time of the K timed steps.
 
-Beside it: configuration 2 (the RMAT-20 stream: 16 build batches, then
+Beside it: the RMAT-20 stream (16 build batches, then
 rounds of 10^6 new uniform pairs, sampled deletions and mixed batches, every
 batch checked against the stored oracle trace of the stream; --no-rmat20
 leaves it out), the insertion-scan kernel against the HBM roofline (its
@@ -25,7 +25,7 @@ the batched form ("batched", as --batched below; --no-batched leaves it
 out) and the serving form ("serving", as --serve below; --no-serve).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
-    python bench.py --workload rmat20      # configuration 2 alone
+    python bench.py --workload rmat20      # the RMAT-20 stream alone
     python bench.py --workload stream [--scale 24] [--batch 1000000]
                        # the whole graph streamed in insertion batches, then
                        # two deletion batches and one mixed batch, all timed
@@ -270,8 +270,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24", choices=["rmat24", "rmat20", "stream"],
-                    help="rmat24 (default): the RMAT-24 stream and timed rounds of ins/del/mix (configuration 3), "
-                         "with the RMAT-20 stream (configuration 2) reported beside it; rmat20: that stream alone; "
+                    help="rmat24 (default): the RMAT-24 stream and timed rounds of ins/del/mix, "
+                         "with the RMAT-20 stream reported beside it; rmat20: that stream alone; "
                          "stream: the whole RMAT graph of --scale streamed in insertion batches, then deletions")
     ap.add_argument("--scale", type=int, default=24, help="scale of the rmat24 and stream workloads")
     ap.add_argument("--no-rmat20", action="store_true", help="leave the RMAT-20 stream out of the default run")
@@ -351,7 +351,7 @@ def main():
 
 
 def run_rmat20(args, P, W, torch, np, steps, warmup):
-    """Configuration 2: the RMAT-20 stream (16 build batches, then rounds of
+    """The RMAT-20 stream (16 build batches, then rounds of
     1e6 insertions, deletions and mixed updates), checked against the stored
     oracle trace; returns the JSON object."""
     dev = torch.device("cuda", 0)
@@ -550,7 +550,7 @@ def cpu_baseline_rmat24(perm, n, seconds):
 
 
 def run_rmat24(args, P, W, torch, np):
-    """Configuration 3: R-MAT of scale 24 (16*2^24 unique edges, seed 1) in the
+    """R-MAT of scale 24 (16*2^24 unique edges, seed 1) in the
     order of a seeded random permutation.  All but a held-out tail of the
     permutation is streamed in as insertion batches of 1e6 (the build; its
     first batches are checked against the stored oracle trace of the stream),
@@ -681,12 +681,12 @@ def run_rmat24(args, P, W, torch, np):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_rmat24(perm, n, args.cpu_seconds)
     del perm
-    if not args.no_batched:   # configuration 4, as extra keys
+    if not args.no_batched:   # the batched form, as extra keys
         b = run_batched(args, P, W, torch, np)
         out["batched"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "per_graph_loop", "default_schedule",
                                             "schedule", "schedules_timed", "speedup_vs_loop", "identical_levels",
                                             "level_steps", "level_steps_alone", "config")}
-    if not args.no_serve:     # configuration 5, as extra keys
+    if not args.no_serve:     # the serving form, as extra keys
         v = run_serve(args, P, W, torch, np)
         out["serving"] = {k: v[k] for k in ("value", "unit", "latency", "identical_to_alone", "errors",
                                             "one_at_a_time", "config")}
@@ -1139,7 +1139,7 @@ def run_orient(args, P, W, torch, np):
 
 
 def run_serve(args, P, W, torch, np):
-    """Configuration 5: resident R-MAT graphs behind the continuous-batching
+    """Resident R-MAT graphs behind the continuous-batching
     server (shards of multi-graph handles; the pending requests of a shard's
     graphs are served by one fused update call and one coreness call).
     Request streams at saturation and at fractions of it; then the same

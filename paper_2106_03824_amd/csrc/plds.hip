@@ -197,7 +197,7 @@ struct Dev {
     int32_t *p0, *p1;                 // [n]
     int32_t *rc;                      // [n]
     // climbing steps
-    int32_t climb_ok;                 // climbing steps allowed (plain handle, per-part kernels)
+    int32_t climb_ok;                 // climbing steps allowed in this sweep (per-part kernels)
     int32_t ins_loop;                 // small insertion steps run by the single-block loop (per-part kernels)
     int32_t climb_min;                // smallest group that enters a climbing step
     int32_t loop_slots;               // most slab slots of a deletion step run by the single-block loop
@@ -1563,7 +1563,7 @@ __device__ void climb_scan_phase(Dev &d, const InsStep &st, int p, int bid, int 
     int32_t *join = (st.cur ^ 1) ? d.casc1 : d.casc0;
     int32_t *slist = p ? d.sl1 : d.sl0;
     auto wr_stop = [=](int32_t k, int32_t x) { slist[k] = x; };
-    const int32_t cap1_all = d.ng == 1 ? up_cap(d, gp(d, 0), l + 1) : 0;   // the cap of level l+1 (one graph)
+    const int32_t cap1_all = d.ng == 1 ? up_cap(d, gp(d, 0), l + 1) : 0;   // the cap of level l+1 (plain handle)
     const int lane = threadIdx.x % kWave, wpb = blockDim.x / kWave;
     const int nw = nblk * wpb;
     const int32_t total = (int32_t)min((int64_t)c->n_cw[p], d.cw_cap);
