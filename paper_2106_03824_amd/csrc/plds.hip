@@ -227,9 +227,9 @@ __device__ __forceinline__ int32_t up_cap(const Dev &d, GP p, int32_t lvl) { ret
 // Whether level x is the first level of a group in some graph of the handle.
 __device__ __forceinline__ bool group_start(const Dev &d, int32_t x) {
     if (d.ng == 1) return x % d.L == 0;
-    for (int i = 0; i < d.nLs; i++)
-        if (x % d.Ls[i] == 0) return true;
-    return false;
+    bool hit = false;   // no early exit: the loads of the list are independent
+    for (int i = 0; i < d.nLs; i++) hit |= x % d.Ls[i] == 0;
+    return hit;
 }
 // The first level above x that starts a group in some graph of the handle.
 __device__ __forceinline__ int32_t next_group_start(const Dev &d, int32_t x) {
@@ -1836,8 +1836,9 @@ __global__ void k_ins_prep(Dev d, int p) {
     }
     // (not right after an exit step: the members that stopped in its last
     // climbing step are residents of its level that no list holds)
-    if (prv.mode == kPull && d.climb_ok && !cur.done && !cur.jump && cur.l == cur.phys &&
-        !group_start(d, cur.l + 1) && cur.l + 2 <= d.K && movers >= d.climb_min) {
+    // (the group-boundary test last: in a multi-graph handle it reads the list of levels per group)
+    if (prv.mode == kPull && d.climb_ok && !cur.done && !cur.jump && cur.l == cur.phys && cur.l + 2 <= d.K &&
+        movers >= d.climb_min && !group_start(d, cur.l + 1)) {
         // enter a climbing step if the level's other vertices and the two
         // levels above hold few vertices next to the movers
         int32_t work = occz - movers + d.occ[cur.l + 1] + d.occ[cur.l + 2];
@@ -2857,8 +2858,8 @@ __global__ void __launch_bounds__(kLoopBlock) k_ins_loop(Dev d) {
                 nA = movers - cn;
                 nB = cn;
             }
-            if (d.climb_ok && !cur.done && !cur.jump && cur.l == cur.phys && !group_start(d, cur.l + 1) &&
-                cur.l + 2 <= d.K && movers >= d.climb_min) {
+            if (d.climb_ok && !cur.done && !cur.jump && cur.l == cur.phys && cur.l + 2 <= d.K &&
+                movers >= d.climb_min && !group_start(d, cur.l + 1)) {
                 const int32_t work = occz - movers + d.occ[cur.l + 1] + d.occ[cur.l + 2];
                 if ((int64_t)work * 2 <= movers) hand = true;   // a climbing step: the step kernels run it
             }
