@@ -29,3 +29,29 @@ def test_rmat_edges_are_unique_canonical_pairs():
     assert (e[:, 0] != e[:, 1]).all() and e.min() >= 0 and e.max() < 2 ** 13
     k = np.minimum(e[:, 0], e[:, 1]).astype(np.int64) << 32 | np.maximum(e[:, 0], e[:, 1])
     assert np.unique(k).size == k.size
+
+
+def test_batched_graphs_recipe():
+    """The batched form's workload: seeded (two calls agree), graph sizes and
+    batch sizes in the stated ranges, insertions are new pairs, deletions are
+    present edges without repeats, clamped to m."""
+    def keys(e):
+        e = np.asarray(e, dtype=np.int64)
+        return (np.minimum(e[:, 0], e[:, 1]) << 32) | np.maximum(e[:, 0], e[:, 1])
+
+    a = W.batched_graphs(12)
+    b = W.batched_graphs(12)
+    for (n, e, (kind, x)), (n2, e2, (kind2, x2)) in zip(a, b):
+        assert n == n2 and kind == kind2 and np.array_equal(e, e2) and np.array_equal(x, x2)
+    for i, (n, e, (kind, x)) in enumerate(a):
+        assert 2 ** 10 - 1 <= n <= 2 ** 16 + 1
+        if i % 2 == 1:
+            assert n & (n - 1) == 0 and len(e) == 8 * n          # R-MAT, edge factor 8
+        ke = keys(e)
+        assert len(np.unique(ke)) == len(ke) and (e[:, 0] != e[:, 1]).all()
+        kx = keys(x)
+        assert len(np.unique(kx)) == len(kx)
+        if kind == "ins":
+            assert 10 ** 3 <= len(x) <= 5 * 10 ** 4 and not np.isin(kx, ke).any()
+        else:
+            assert len(x) <= min(5 * 10 ** 4, len(e)) and np.isin(kx, ke).all()
